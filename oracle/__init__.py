@@ -1,0 +1,240 @@
+"""Oracle for the trapped-ion Coulomb + linear-Paul-trap + velocity-Verlet path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code with
+the GPU library (``paper_1907_10514_amd``) and never imports it.
+
+The heavy lifting is ``lion_oracle.c`` (plain FP64 C, compensated sums, no
+fast-math), loaded here through ctypes.  The few closed forms that the paper
+states directly are written out in numpy below:
+
+* eq. (Mathieuaq): Mathieu coefficients of the linear Paul trap,
+* eq. (pseudopot): pseudopotential secular frequency,
+* the axial frequency implied by the dc term of eq. (field).
+
+Every function cites the passage it follows; see ``lion_oracle.c`` for the
+statement of the field, the acceleration and the step.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lion_oracle.c")
+_LIB = os.path.join(_HERE, "liblion_oracle.so")
+
+# CODATA 2018 / SI 2019, written out independently of the GPU library.
+E_CHARGE = 1.602176634e-19  # C
+EPS0 = 8.8541878128e-12  # F/m
+AMU = 1.66053906660e-27  # kg
+K_B = 1.380649e-23  # J/K
+COULOMB_K = 1.0 / (4.0 * math.pi * EPS0)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``lion_oracle.c`` into ``liblion_oracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c99",
+               "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Trap(ctypes.Structure):
+    _fields_ = [("V0", ctypes.c_double), ("Omega", ctypes.c_double), ("U0", ctypes.c_double),
+                ("R0", ctypes.c_double), ("Z0", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class Trap:
+    """Linear Paul trap of eq. (field): rf amplitude V0 (V) at angular frequency
+    Omega (rad/s), end-cap voltage U0 (V), lengths R0, Z0 (m), geometry factor kappa."""
+    V0: float = 0.0
+    Omega: float = 1.0
+    U0: float = 0.0
+    R0: float = 1.0
+    Z0: float = 1.0
+    kappa: float = 0.0
+
+    def _c(self) -> _Trap:
+        return _Trap(self.V0, self.Omega, self.U0, self.R0, self.Z0, self.kappa)
+
+
+_lib = None
+
+
+def bind(path: str):
+    """Load a compiled oracle library from ``path`` and declare its prototypes."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    lp = ctypes.POINTER(ctypes.c_int64)
+    tp = ctypes.POINTER(_Trap)
+    lib.oracle_coulomb_constant.restype = ctypes.c_double
+    lib.oracle_coulomb_field.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp]
+    lib.oracle_coulomb_field.restype = i64
+    lib.oracle_accel.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, dp, dp, dp]
+    lib.oracle_accel.restype = i64
+    lib.oracle_accel_scale.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, dp]
+    lib.oracle_accel_scale.restype = None
+    lib.oracle_step.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
+    lib.oracle_step.restype = i64
+    lib.oracle_energy.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, tp, dp, dp, dp]
+    lib.oracle_energy.restype = None
+    lib.oracle_step_batch.argtypes = [ctypes.c_int32, lp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                      dp, dp, tp, dp, dp, dp, i64, dp]
+    lib.oracle_step_batch.restype = i64
+    lib.oracle_accel_batch.argtypes = [ctypes.c_int32, lp, dp, dp, dp, dp, dp, tp, dp, dp,
+                                       dp, dp]
+    lib.oracle_accel_batch.restype = i64
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = bind(_LIB)
+    return _lib
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def coulomb_constant() -> float:
+    """k_e = 1/(4 pi eps0) as the C oracle evaluates it."""
+    return _load().oracle_coulomb_constant()
+
+
+def coulomb_field(x, y, z, charge):
+    """E_c,i = k_e sum_{j!=i} Q_j (r_i-r_j)/|r_i-r_j|^3 (V/m); the field whose
+    potential is the pair term of eq. (fullPotential).  Returns (ex, ey, ez, coincident)."""
+    x, y, z, q = map(_f64, (x, y, z, charge))
+    n = x.size
+    ex, ey, ez = np.empty(n), np.empty(n), np.empty(n)
+    c = _load().oracle_coulomb_field(n, _d(x), _d(y), _d(z), _d(q), _d(ex), _d(ey), _d(ez))
+    return ex, ey, ez, int(c)
+
+
+def accel(x, y, z, charge, mass, trap: Trap, t: float):
+    """a_i = (Q_i/M_i)(E_c,i + E_ext(r_i, t)), eq. (field) with the confining dc
+    reading.  Returns (ax, ay, az) in m/s^2."""
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    n = x.size
+    ax, ay, az = np.empty(n), np.empty(n), np.empty(n)
+    tr = trap._c()
+    _load().oracle_accel(n, _d(x), _d(y), _d(z), _d(q), _d(m), ctypes.byref(tr), float(t),
+                         _d(ax), _d(ay), _d(az))
+    return ax, ay, az
+
+
+def accel_scale(x, y, z, charge, mass, trap: Trap, t: float) -> np.ndarray:
+    """Sum of the magnitudes of all contributions to a_i (m/s^2): the scale
+    against which a relative force error is measured."""
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    s = np.empty(x.size)
+    tr = trap._c()
+    _load().oracle_accel_scale(x.size, _d(x), _d(y), _d(z), _d(q), _d(m), ctypes.byref(tr),
+                               float(t), _d(s))
+    return s
+
+
+def step(state: dict, charge, mass, trap: Trap, gamma: float, t_start: float, dt: float,
+         nsteps: int) -> dict:
+    """Advance ``state`` (dict of x, y, z, vx, vy, vz arrays) by ``nsteps``
+    damped velocity-Verlet steps from t_start.  Returns a new dict that also
+    holds the final accelerations and time ``t``."""
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    q, m = _f64(charge), _f64(mass)
+    ax, ay, az = accel(s["x"], s["y"], s["z"], q, m, trap, t_start)
+    t_end = ctypes.c_double(0.0)
+    tr = trap._c()
+    _load().oracle_step(s["x"].size, _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]), _d(s["vy"]),
+                        _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q), _d(m), ctypes.byref(tr),
+                        float(gamma), float(t_start), float(dt), int(nsteps), ctypes.byref(t_end))
+    s.update(ax=ax, ay=ay, az=az, t=t_end.value)
+    return s
+
+
+def energy(state: dict, charge, mass, trap: Trap):
+    """(kinetic, Coulomb, dc-trap) energies in J; Coulomb is the pair term of
+    eq. (fullPotential) counted once per pair."""
+    x, y, z, vx, vy, vz = (_f64(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz"))
+    q, m = _f64(charge), _f64(mass)
+    k, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    tr = trap._c()
+    _load().oracle_energy(x.size, _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _d(q), _d(m),
+                          ctypes.byref(tr), ctypes.byref(k), ctypes.byref(c), ctypes.byref(d))
+    return k.value, c.value, d.value
+
+
+def accel_batch(offsets, x, y, z, charge, mass, traps, t):
+    """Per-trap accel for independent traps concatenated in trap order."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    tarr = (_Trap * len(traps))(*[tr._c() for tr in traps])
+    tt = _f64(t)
+    n = x.size
+    ax, ay, az = np.empty(n), np.empty(n), np.empty(n)
+    _load().oracle_accel_batch(len(traps), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               _d(x), _d(y), _d(z), _d(q), _d(m), tarr, _d(tt), _d(ax), _d(ay),
+                               _d(az))
+    return ax, ay, az
+
+
+def step_batch(offsets, state: dict, charge, mass, traps, gamma, t_start, dt, nsteps: int):
+    """``step`` applied to each trap of a batch with its own parameters."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    q, m = _f64(charge), _f64(mass)
+    ts, g, h = _f64(t_start), _f64(gamma), _f64(dt)
+    ax, ay, az = accel_batch(off, s["x"], s["y"], s["z"], q, m, traps, ts)
+    tarr = (_Trap * len(traps))(*[tr._c() for tr in traps])
+    t_end = np.empty(len(traps))
+    _load().oracle_step_batch(len(traps), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]), _d(s["vy"]),
+                              _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q), _d(m), tarr, _d(g),
+                              _d(ts), _d(h), int(nsteps), _d(t_end))
+    s.update(ax=ax, ay=ay, az=az, t=t_end)
+    return s
+
+
+# ---------------------------------------------------------------- closed forms
+
+def mathieu_coefficients(V0, U0, M, Q, Omega, R0, Z0, kappa):
+    """eq. (Mathieuaq): (q_x, a_x) with q_y = -q_x, a_y = a_x, a_z = -2 a_x, q_z = 0."""
+    a_x = -4.0 * Q * kappa * U0 / (M * Z0 ** 2 * Omega ** 2)
+    q_x = 2.0 * Q * V0 / (M * R0 ** 2 * Omega ** 2)
+    return q_x, a_x
+
+
+def voltages_for(q_x, a_x, M, Q, Omega, R0, Z0, kappa):
+    """Inverse of eq. (Mathieuaq): the (V0, U0) that give (q_x, a_x) to an ion of
+    mass M and charge Q."""
+    V0 = q_x * M * R0 ** 2 * Omega ** 2 / (2.0 * Q)
+    U0 = -a_x * M * Z0 ** 2 * Omega ** 2 / (4.0 * Q * kappa)
+    return V0, U0
+
+
+def pseudopotential_frequency(q, a, Omega):
+    """eq. (pseudopot): omega ~ (Omega/2) sqrt(a + q^2/2), rad/s."""
+    return 0.5 * Omega * math.sqrt(a + 0.5 * q * q)
+
+
+def axial_frequency(U0, M, Q, Z0, kappa):
+    """omega_z of the dc term of eq. (field): z'' = -(2 Q kappa U0/(M Z0^2)) z."""
+    return math.sqrt(2.0 * Q * kappa * U0 / (M * Z0 ** 2))

@@ -1,0 +1,235 @@
+/*
+ * Oracle for the trapped-ion Coulomb + linear-Paul-trap + velocity-Verlet path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, FP64 CPU statement of
+ * what the GPU path computes.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no code, header or constant
+ * with the GPU library and the GPU library never calls it.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math), so every
+ * product and sum below is rounded as written.
+ *
+ * Physics followed (paper: "Dynamics of trapped ions", eq. (field), eq. (Mathieuaq),
+ * eq. (fullPotential); "Implementation details": units si, coul/cut, nve):
+ *   E_ext(r, t) = (V0/R0^2) cos(Omega t) (x, -y, 0) + (kappa U0/Z0^2) (x, y, -2z)
+ *     The dc term is read as axially confining, i.e. minus the gradient of
+ *     (kappa U0/Z0^2)(z^2 - (x^2+y^2)/2); this is the only sign consistent with
+ *     eq. (Mathieuaq) (a_x = -a_z/2 = -4 Q kappa U0/(M Z0^2 Omega^2)).
+ *   E_c,i = k_e sum_{j != i} Q_j (r_i - r_j) / |r_i - r_j|^3   (unscreened, no cutoff;
+ *     the paper's 10 m cutoff never acts on a trapped cloud)
+ *   a_i = (Q_i / M_i) (E_c,i + E_ext(r_i, t))
+ *   Step (velocity Verlet as LAMMPS nve, with laser-cooling damping applied as exact
+ *   exp(-gamma dt/2) velocity scalings before and after):
+ *     v <- f v;  v <- v + (dt/2) a;  x <- x + dt v;  t_{k+1} = t_start + (k+1) dt;
+ *     a <- accel(x, t_{k+1});  v <- v + (dt/2) a;  v <- f v,   f = exp(-gamma dt / 2).
+ *
+ * Pair sums use Neumaier's compensated summation (Neumaier 1974) in ascending j, so
+ * the oracle's own rounding error is far below the GPU tolerances it checks.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+/* CODATA 2018 / SI 2019 values, written out here independently of the GPU library. */
+#define OR_ECHARGE 1.602176634e-19
+#define OR_EPS0 8.8541878128e-12
+#define OR_PI 3.14159265358979323846
+
+typedef struct {
+    double V0;     /* rf amplitude (V) */
+    double Omega;  /* rf angular frequency (rad/s) */
+    double U0;     /* end-cap dc voltage (V) */
+    double R0;     /* radial length scale (m) */
+    double Z0;     /* axial length scale (m) */
+    double kappa;  /* geometric factor */
+} oracle_trap;
+
+double oracle_coulomb_constant(void) { return 1.0 / (4.0 * OR_PI * OR_EPS0); }
+
+/* Neumaier running sum: value s, compensation c. */
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum *a, double t) {
+    double u = a->s + t;
+    if (fabs(a->s) >= fabs(t))
+        a->c += (a->s - u) + t;
+    else
+        a->c += (t - u) + a->s;
+    a->s = u;
+}
+
+static double nsum_get(const nsum *a) { return a->s + a->c; }
+
+/* External field of eq. (field) at one point, dc sign read as confining. */
+static void trap_field(const oracle_trap *tp, double t, double x, double y, double z,
+                       double *ex, double *ey, double *ez) {
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    double c = cos(tp->Omega * t);
+    *ex = a_rf * c * x + a_dc * x;
+    *ey = -a_rf * c * y + a_dc * y;
+    *ez = -2.0 * a_dc * z;
+}
+
+/* Coulomb field E_c,i (V/m) on every ion of one cloud.  Returns the number of
+ * exactly coincident pairs met (they contribute zero). */
+int64_t oracle_coulomb_field(int64_t n, const double *x, const double *y, const double *z,
+                             const double *charge, double *ex, double *ey, double *ez) {
+    const double ke = oracle_coulomb_constant();
+    int64_t coincident = 0;
+#pragma omp parallel for schedule(static) reduction(+ : coincident) if (n >= 256)
+    for (int64_t i = 0; i < n; ++i) {
+        nsum sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) {
+                ++coincident;
+                continue;
+            }
+            double s = charge[j] * (1.0 / (r2 * sqrt(r2)));
+            nsum_add(&sx, s * dx);
+            nsum_add(&sy, s * dy);
+            nsum_add(&sz, s * dz);
+        }
+        ex[i] = ke * nsum_get(&sx);
+        ey[i] = ke * nsum_get(&sy);
+        ez[i] = ke * nsum_get(&sz);
+    }
+    return coincident;
+}
+
+/* Acceleration a_i = (Q_i/M_i)(E_c,i + E_ext(r_i, t)) for one cloud in one trap. */
+int64_t oracle_accel(int64_t n, const double *x, const double *y, const double *z,
+                     const double *charge, const double *mass, const oracle_trap *tp,
+                     double t, double *ax, double *ay, double *az) {
+    int64_t coincident = oracle_coulomb_field(n, x, y, z, charge, ax, ay, az);
+    for (int64_t i = 0; i < n; ++i) {
+        double ex, ey, ez;
+        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
+        double qm = charge[i] / mass[i];
+        ax[i] = qm * (ax[i] + ex);
+        ay[i] = qm * (ay[i] + ey);
+        az[i] = qm * (az[i] + ez);
+    }
+    return coincident;
+}
+
+/* Rounding scale of a_i: (|Q_i|/M_i)(k_e sum_j |Q_j|/r_ij^2 + |E_rf,i| + |E_dc,i|),
+ * the sum of the magnitudes of every contribution to a_i. */
+void oracle_accel_scale(int64_t n, const double *x, const double *y, const double *z,
+                        const double *charge, const double *mass, const oracle_trap *tp,
+                        double t, double *scale) {
+    const double ke = oracle_coulomb_constant();
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    double c = cos(tp->Omega * t);
+#pragma omp parallel for schedule(static) if (n >= 256)
+    for (int64_t i = 0; i < n; ++i) {
+        nsum s = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            nsum_add(&s, fabs(charge[j]) / r2);
+        }
+        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
+        scale[i] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&s) + erf + edc);
+    }
+}
+
+/* nsteps velocity-Verlet steps with damping, starting at t_start.  On entry
+ * (ax, ay, az) must hold accel(x, t_start); on exit they hold accel at the end
+ * time t_start + nsteps dt, which is returned through *t_end. */
+int64_t oracle_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                    double *vz, double *ax, double *ay, double *az, const double *charge,
+                    const double *mass, const oracle_trap *tp, double gamma, double t_start,
+                    double dt, int64_t nsteps, double *t_end) {
+    const double f = exp(-(gamma * dt) * 0.5);
+    const double h = 0.5 * dt;
+    int64_t coincident = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] = f * vx[i];
+            vy[i] = f * vy[i];
+            vz[i] = f * vz[i];
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            x[i] = x[i] + dt * vx[i];
+            y[i] = y[i] + dt * vy[i];
+            z[i] = z[i] + dt * vz[i];
+        }
+        double t = t_start + (double)(k + 1) * dt;
+        coincident += oracle_accel(n, x, y, z, charge, mass, tp, t, ax, ay, az);
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            vx[i] = f * vx[i];
+            vy[i] = f * vy[i];
+            vz[i] = f * vz[i];
+        }
+    }
+    *t_end = t_start + (double)nsteps * dt;
+    return coincident;
+}
+
+/* Kinetic energy sum 1/2 M v^2, Coulomb energy sum_{i<j} k_e Q_i Q_j / r_ij
+ * (eq. (fullPotential), each pair once), and the dc-trap energy
+ * sum Q_i (kappa U0/Z0^2)(z^2 - (x^2+y^2)/2).  Joules. */
+void oracle_energy(int64_t n, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz, const double *charge,
+                   const double *mass, const oracle_trap *tp, double *kinetic, double *coulomb,
+                   double *dc_trap) {
+    const double ke = oracle_coulomb_constant();
+    double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    nsum k = {0, 0}, c = {0, 0}, d = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        nsum_add(&k, 0.5 * mass[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]));
+        nsum_add(&d, charge[i] * a_dc * (z[i] * z[i] - 0.5 * (x[i] * x[i] + y[i] * y[i])));
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r == 0.0) continue;
+            nsum_add(&c, ke * charge[i] * charge[j] / r);
+        }
+    }
+    *kinetic = nsum_get(&k);
+    *coulomb = nsum_get(&c);
+    *dc_trap = nsum_get(&d);
+}
+
+/* Independent traps concatenated in trap order: trap k owns ions
+ * [offset[k], offset[k+1]).  Each trap is one oracle_step call with its own
+ * parameters, damping rate and step size; no force crosses traps. */
+int64_t oracle_step_batch(int32_t n_traps, const int64_t *offset, double *x, double *y,
+                          double *z, double *vx, double *vy, double *vz, double *ax, double *ay,
+                          double *az, const double *charge, const double *mass,
+                          const oracle_trap *traps, const double *gamma, const double *t_start,
+                          const double *dt, int64_t nsteps, double *t_end) {
+    int64_t coincident = 0;
+    for (int32_t k = 0; k < n_traps; ++k) {
+        int64_t o = offset[k], m = offset[k + 1] - offset[k];
+        coincident += oracle_step(m, x + o, y + o, z + o, vx + o, vy + o, vz + o, ax + o, ay + o,
+                                  az + o, charge + o, mass + o, &traps[k], gamma[k], t_start[k],
+                                  dt[k], nsteps, &t_end[k]);
+    }
+    return coincident;
+}
+
+int64_t oracle_accel_batch(int32_t n_traps, const int64_t *offset, const double *x,
+                           const double *y, const double *z, const double *charge,
+                           const double *mass, const oracle_trap *traps, const double *t,
+                           double *ax, double *ay, double *az) {
+    int64_t coincident = 0;
+    for (int32_t k = 0; k < n_traps; ++k) {
+        int64_t o = offset[k], m = offset[k + 1] - offset[k];
+        coincident += oracle_accel(m, x + o, y + o, z + o, charge + o, mass + o, &traps[k], t[k],
+                                   ax + o, ay + o, az + o);
+    }
+    return coincident;
+}

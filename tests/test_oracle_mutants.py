@@ -1,0 +1,65 @@
+"""The pins catch plausible slips: each planted mistake below is compiled into
+a copy of the oracle (on the CPU, in a temporary directory) and at least one
+pin must fail against it.  The real oracle is untouched."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "lion_oracle.c")
+
+MUTANTS = {
+    "dc_sign_flipped": ("*ez = -2.0 * a_dc * z;", "*ez = 2.0 * a_dc * z;"),
+    "rf_y_sign_flipped": ("*ey = -a_rf * c * y + a_dc * y;", "*ey = a_rf * c * y + a_dc * y;"),
+    "rf_term_dropped": ("*ex = a_rf * c * x + a_dc * x;", "*ex = a_dc * x;"),
+    "pair_index_swapped": ("double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {",
+                           "double dx = x[j] - x[i], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {"),
+    "source_charge_is_target": ("double s = charge[j] *", "double s = charge[i] *"),
+    "inverse_square_power": ("(1.0 / (r2 * sqrt(r2)))", "(1.0 / r2)"),
+    "first_damping_dropped": ("            vx[i] = f * vx[i];\n            vy[i] = f * vy[i];\n            vz[i] = f * vz[i];\n            vx[i] = vx[i] + h * ax[i];",
+                              "            vx[i] = vx[i] + h * ax[i];"),
+    "force_time_not_advanced": ("double t = t_start + (double)(k + 1) * dt;", "double t = t_start + (double)k * dt;"),
+    "full_kick": ("const double h = 0.5 * dt;", "const double h = dt;"),
+    "coulomb_constant_2x": ("return 1.0 / (4.0 * OR_PI * OR_EPS0);", "return 1.0 / (2.0 * OR_PI * OR_EPS0);"),
+    "self_term_kept_as_neighbour": ("if (j == i) continue;\n            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {",
+                                    "if (j == i + 1) continue;\n            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {"),
+}
+
+PINS = [
+    lambda o: pins.test_accel_matches_40_digit_bruteforce(o, 3, 1),
+    lambda o: pins.test_ten_steps_match_40_digit_bruteforce(o),
+    lambda o: pins.test_single_ion_matches_transfer_matrices(o, "x"),
+    lambda o: pins.test_single_ion_matches_transfer_matrices(o, "y"),
+    lambda o: pins.test_two_ion_spacing_closed_form(o),
+    lambda o: pins.test_laser_cooling_free_particle(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(tmp_path, name, oracle_mod):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {name}"
+    mutated = src.replace(old, new, 1)
+    c = tmp_path / "mut.c"
+    so = tmp_path / "libmut.so"
+    c.write_text(mutated)
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c99", "-shared", "-fPIC",
+                    str(c), "-o", str(so), "-lm"], check=True)
+    saved = oracle._lib
+    oracle._lib = oracle.bind(str(so))
+    failures = 0
+    try:
+        for pin in PINS:
+            try:
+                pin(oracle)
+            except (AssertionError, ValueError, FloatingPointError):
+                failures += 1
+    finally:
+        oracle._lib = saved
+    assert failures >= 1, f"no pin caught mutant {name}"
