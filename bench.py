@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark of the trapped-ion hot path on one MI355X.
+
+One step = drift + all-pairs Coulomb field + trap field + kick/damping for the
+whole cloud (every kernel of the path).  Default workload: the 16384-ion
+mixed-species cloud (80 % Ca-40, 20 % mass-17, sigma 200 um, 10 mK, q = 0.25),
+run with FP32 pair arithmetic + FP64 accumulation (the headline value), with
+plain FP64 and with compensated FP32 beside it; plus the 512-trap batch.
+
+Prints ONE JSON line.  `value` = ordered pair interactions per second (N(N-1)
+per step) of the whole job, inputs resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Coulomb pair-interactions/s + steps/s at N=16384, FP64 vs FP32-mixed, % vector peak"
+FLOP_PER_PAIR = 20  # credited: 3 sub, 3 mul/fma for r^2, rsqrt ~ 4, r^-3 x q 3, 3 fma, flop-counted
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "mixed_kahan": 157.3}
+DTYPE = {"fp64": "f64", "mixed": "f32", "mixed_kahan": "f32"}
+KERNEL_SRC = os.path.join(ROOT, "paper_1907_10514_amd", "csrc", "lion_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_for(kernel_key: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel_key)
+    if not ent or ent.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def sync(torch):
+    torch.cuda.synchronize()
+
+
+def time_single(torch, w, precision, steps, warmup, reps):
+    from paper_1907_10514_amd import runner
+
+    sim = runner.simulation_for(w, precision=precision)
+    dt = w.traps[0].dt
+    sim.step(warmup, dt)
+    sync(torch)
+    t0 = time.perf_counter()
+    sim.step(steps, dt)
+    sync(torch)
+    el = time.perf_counter() - t0
+    finite = sim.check_finite() == 0
+    kernel_ms = sim.time_pair_kernel(reps)
+    cfg = sim.config()
+    sim.close()
+    n = w.n
+    pairs = n * (n - 1)
+    return dict(pairs_per_s=pairs * steps / el, steps_per_s=steps / el,
+                ms_per_step=1e3 * el / steps, pair_kernel_ms=kernel_ms,
+                pair_kernel_tflops=FLOP_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12,
+                pct_vector_peak=100.0 * FLOP_PER_PAIR * pairs * steps / el / 1e12
+                / PEAK_TFLOPS[precision],
+                finite=finite, launch=cfg)
+
+
+def time_batch(torch, precision, steps, warmup, seq_steps):
+    import numpy as np
+
+    import lion_inputs as li
+    from paper_1907_10514_amd import runner
+
+    w = li.batch512(nsteps=steps)
+    pairs = w.ordered_pairs()
+    sim = runner.simulation_for(w, precision=precision)
+    dts = runner.step_dts(w)
+    sim.step(warmup, dts)
+    sync(torch)
+    t0 = time.perf_counter()
+    sim.step(steps, dts)
+    sync(torch)
+    el = time.perf_counter() - t0
+    finite = sim.check_finite() == 0
+    kernel_ms = sim.time_batch_kernel(3, 100, float(dts[0]))
+    cfg = sim.config()
+    sim.close()
+    # the same traps one by one through the single-trap path
+    seq_el = 0.0
+    for k in range(w.n_traps):
+        o, e = int(w.offsets[k]), int(w.offsets[k + 1])
+        sub = li.Workload(f"trap{k}", w.mass[o:e], w.charge[o:e], w.x[o:e], w.y[o:e], w.z[o:e],
+                          w.vx[o:e], w.vy[o:e], w.vz[o:e], [w.traps[k]],
+                          np.array([0, e - o], dtype=np.int64), seq_steps, w.precision)
+        s1 = runner.simulation_for(sub, precision=precision, batched=False)
+        s1.step(seq_steps, w.traps[k].dt)  # captures the launch graph outside the timing
+        sync(torch)
+        t0 = time.perf_counter()
+        s1.step(seq_steps, w.traps[k].dt)
+        sync(torch)
+        seq_el += time.perf_counter() - t0
+        s1.close()
+    seq_pairs_per_s = pairs * seq_steps / seq_el
+    return dict(pairs_per_s=pairs * steps / el, steps_per_s=steps / el,
+                ms_per_step=1e3 * el / steps, kernel_ms_per_100_steps=kernel_ms,
+                kernel_tflops=FLOP_PER_PAIR * pairs * 100 / (kernel_ms * 1e-3) / 1e12,
+                pct_vector_peak=100.0 * FLOP_PER_PAIR * pairs * steps / el / 1e12
+                / PEAK_TFLOPS[precision],
+                sequential_single_trap_pairs_per_s=seq_pairs_per_s,
+                speedup_vs_sequential=(pairs * steps / el) / seq_pairs_per_s,
+                finite=finite, launch=cfg, n_traps=w.n_traps, n_ions=w.n,
+                ordered_pairs_per_step=pairs)
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle on the host cores, on a bounded number of steps of the
+    same workload."""
+    import oracle
+
+    oracle.build(force=False)
+    spec = w.traps[0]
+    V0, U0 = oracle.voltages_for(spec.q_x, spec.a_x, spec.ref_mass, spec.ref_charge, spec.omega,
+                                 spec.r0, spec.z0, spec.kappa)
+    tr = oracle.Trap(V0=V0, Omega=spec.omega, U0=U0, R0=spec.r0, Z0=spec.z0, kappa=spec.kappa)
+    st = w.state()
+    # oracle.step evaluates the starting acceleration, then one evaluation per
+    # step: calibrate on one step, then time one call of k steps (k + 1 passes)
+    t0 = time.perf_counter()
+    oracle.step(st, w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, 1)
+    per_eval = (time.perf_counter() - t0) / 2
+    k = max(3, int(seconds / per_eval) - 1)
+    t0 = time.perf_counter()
+    oracle.step(st, w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, k)
+    el = time.perf_counter() - t0
+    steps, evals = k, k + 1
+    n = w.n
+    return dict(value=n * (n - 1) * evals / el, unit="pair-interactions/s",
+                cores=oracle.num_threads(), kind="oracle",
+                steps_per_s=steps / el,
+                sample=f"{steps} steps of the {n}-ion workload in {el:.1f} s (FP64 oracle, "
+                       f"OpenMP over targets; {evals} all-pairs force evaluations, each "
+                       f"N(N-1) pair interactions)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--seq-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--precisions", default="fp64,mixed,mixed_kahan")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "this engine measures the path on one GPU only.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lion_inputs as li
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    props = torch.cuda.get_device_properties(0)
+    w = li.mixed16384()
+    n = w.n
+    precs = [p for p in args.precisions.split(",") if p]
+    res = {}
+    for p in precs:
+        log(f"[bench] {p}: N={n}, {args.warmup} warmup + {args.steps} timed steps")
+        res[p] = time_single(torch, w, p, args.steps, args.warmup, args.kernel_reps)
+        log(f"[bench] {p}: {res[p]['pairs_per_s']:.4e} pairs/s, {res[p]['ms_per_step']:.4f} ms/step, "
+            f"pair kernel {res[p]['pair_kernel_ms']:.4f} ms")
+    head = "mixed" if "mixed" in res else precs[0]
+    r = res[head]
+    pairs = n * (n - 1)
+    kern_key = f"pair_{head}_n{n}"
+    out = {
+        "metric": METRIC,
+        "value": r["pairs_per_s"],
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[head],
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_ions": n, "precision": head,
+                   "species": "80% Ca-40 + 20% mass-17 (+e)", "sigma_m": 200e-6,
+                   "temperature_K": 10e-3, "q_x": 0.25, "dt_s": w.traps[0].dt,
+                   "launch": r["launch"]},
+        "steps_per_s": r["steps_per_s"],
+        "pct_vector_peak": r["pct_vector_peak"],
+        "flop_per_pair_credited": FLOP_PER_PAIR,
+        "precisions": res,
+    }
+    if "fp64" in res and head != "fp64":
+        out["speedup_mixed_over_fp64"] = r["pairs_per_s"] / res["fp64"]["pairs_per_s"]
+    if "mixed_kahan" in res and "fp64" in res:
+        out["speedup_kahan_over_fp64"] = res["mixed_kahan"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
+    out["roofline"] = {
+        "kernel": kern_key,
+        "bound": "alu",
+        "achieved": r["pair_kernel_tflops"],
+        "peak": PEAK_TFLOPS[head],
+        "unit": "TFLOP/s",
+        "frac": r["pair_kernel_tflops"] / PEAK_TFLOPS[head],
+        "traffic": traffic_for(kern_key),
+        "algorithmic_flop_per_launch": FLOP_PER_PAIR * pairs,
+        "avg_launch_ms": r["pair_kernel_ms"],
+    }
+    if not args.no_batch:
+        out["batch512"] = {}
+        for p in ("mixed", "fp64"):
+            if p not in precs:
+                continue
+            log(f"[bench] batch512 {p}: {args.batch_steps} steps")
+            out["batch512"][p] = time_batch(torch, p, args.batch_steps, 100, args.seq_steps)
+            log(f"[bench] batch512 {p}: {out['batch512'][p]['pairs_per_s']:.4e} pairs/s, "
+                f"x{out['batch512'][p]['speedup_vs_sequential']:.1f} vs one-by-one")
+        if "mixed" in out["batch512"] and "fp64" in res:
+            out["batch512"]["speedup_batched_mixed_over_single_fp64_n16384"] = (
+                out["batch512"]["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"])
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    out["device"] = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+                     "cu": props.multi_processor_count}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * lion.h -- C ABI of the MI355X trapped-ion engine.
+ *
+ * One call per step of the problem as the paper states it ("Overview": create
+ * the ions with their masses and charges, add a linear Paul trap with the full
+ * fields of eq. (field), add laser cooling, then evolve N steps with a fixed
+ * time step; "Implementation details": SI units, unscreened Coulomb pair
+ * interaction summed over all pairs, Newtonian (velocity-Verlet) integration).
+ *
+ * Physics computed by every step (all ions i of one trap, t in seconds):
+ *   E_c,i  = k_e sum_{j != i} Q_j (r_i - r_j) / |r_i - r_j|^3       (no cutoff)
+ *   E_ext  = (V0/R0^2) cos(Omega t) (x, -y, 0) + (kappa U0/Z0^2) (x, y, -2z)
+ *            (the dc term is taken as axially confining, the sign for which
+ *            eq. (Mathieuaq) holds)
+ *   a_i    = (Q_i/M_i) (E_c,i + E_ext(r_i, t))
+ *   step   v <- f v; v <- v + (dt/2) a; x <- x + dt v; a <- a(x, t_{k+1});
+ *          v <- v + (dt/2) a; v <- f v;   f = exp(-gamma dt/2),
+ *          t_k = t_call_start + k dt within one lion_step call.
+ * Exactly coincident ions exert no force on each other.
+ *
+ * Conventions
+ *   - SI units throughout: m, m/s, kg, C, V, rad/s, s.
+ *   - Host arrays (double, length n_total, trap order for batches) are read or
+ *     written during the call only and stay owned by the caller.
+ *   - Device memory: the caller allocates one workspace of
+ *     lion_workspace_bytes(...) bytes (256-byte aligned) and keeps it alive
+ *     until lion_destroy; the library carves all device arrays from it and
+ *     never allocates or frees device memory itself.
+ *   - Every call runs on the HIP stream given at creation (a hipStream_t
+ *     passed as void*, NULL = the default stream) and returns once its work is
+ *     queued, except lion_get_state / lion_compute_accel / lion_get_energy,
+ *     which synchronise the stream before returning host data.
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ *   - Every call returns LION_OK or a negative status; lion_last_error gives a
+ *     message for the last failure on that handle.
+ */
+#ifndef LION_H
+#define LION_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lion_sim lion_sim;
+
+/* Arithmetic of the pair sum.  Positions, velocities, the trap field, the rf
+ * phase and the Verlet update are FP64 in every mode.
+ *   LION_FP64          pair differences, r^-3 and accumulation in FP64
+ *   LION_MIXED_F64ACC  pair arithmetic in FP32 on float-float positions,
+ *                      accumulated in FP32 over short runs of sources and
+ *                      flushed into FP64 sums
+ *   LION_MIXED_KAHAN   pair arithmetic in FP32, compensated (Kahan) FP32 sums */
+enum lion_precision { LION_FP64 = 0, LION_MIXED_F64ACC = 1, LION_MIXED_KAHAN = 2 };
+
+enum lion_status {
+    LION_OK = 0,
+    LION_ERR_ARG = -1,         /* invalid argument (message says which)          */
+    LION_ERR_STATE = -2,       /* call out of order, e.g. step before set_state  */
+    LION_ERR_HIP = -3,         /* a HIP runtime call failed                       */
+    LION_ERR_WORKSPACE = -4,   /* workspace missing, too small or misaligned     */
+    LION_ERR_NONFINITE = -5,   /* non-finite state detected                      */
+    LION_ERR_UNSUPPORTED = -6  /* option not available for this handle           */
+};
+
+/* Bytes of device workspace needed for n_total ions in n_traps traps (1 for a
+ * single trap) at the given precision.  Returns 0 for invalid arguments. */
+size_t lion_workspace_bytes(int64_t n_total, int32_t n_traps, int precision);
+
+/* One trap of n ions (n >= 1) with masses (kg, > 0, finite) and charges (C,
+ * finite).  Ions are created with zero position and velocity; call
+ * lion_set_state before stepping.  No trap field and no damping until set. */
+int lion_create(lion_sim **out, int64_t n, const double *masses_kg, const double *charges_C,
+                int precision, void *dev_workspace, size_t ws_bytes, void *hip_stream);
+
+/* n_traps independent traps (1 <= n_traps, 1 <= n_per_trap[k] <= 1024); trap k
+ * owns the n_per_trap[k] ions that follow those of trap k-1 in every array.
+ * No force acts between traps; each trap has its own field, damping, time step
+ * and clock.  All traps of a batch run in one persistent launch per chunk. */
+int lion_create_batch(lion_sim **out, int32_t n_traps, const int64_t *n_per_trap,
+                      const double *masses_kg, const double *charges_C, int precision,
+                      void *dev_workspace, size_t ws_bytes, void *hip_stream);
+
+/* Positions (m) and velocities (m/s) of all ions and the current time t (s; for
+ * a batch every trap's clock is set to t).  Computes the accelerations at
+ * (x, t).  Non-finite input -> LION_ERR_ARG. */
+int lion_set_state(lion_sim *sim, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz, double t);
+
+/* Linear Paul trap of eq. (field) for trap `trap` (-1 = every trap): rf
+ * amplitude V_rf (V) at angular frequency Omega (rad/s), end-cap voltage U_dc
+ * (V), lengths r0, z0 (m, > 0), geometry factor kappa.  Recomputes the cached
+ * accelerations at the current positions and time.  Omega <= 0 with V_rf != 0,
+ * r0 or z0 <= 0, or any non-finite value -> LION_ERR_ARG. */
+int lion_set_trap(lion_sim *sim, int32_t trap, double V_rf, double Omega_rad_s, double U_dc,
+                  double r0, double z0, double kappa);
+
+/* Laser cooling (section "Cooling the motion of ions") as an isotropic viscous
+ * force -M gamma v on every ion of trap `trap` (-1 = every trap); gamma in 1/s,
+ * >= 0 and finite.  Applied as exact exp(-gamma dt/2) velocity scalings. */
+int lion_set_damping(lion_sim *sim, int32_t trap, double gamma_per_s);
+
+/* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite).
+ * nsteps = 0 is a no-op.  Time afterwards: t + nsteps dt.  Requires
+ * lion_set_state first (else LION_ERR_STATE). */
+int lion_step(lion_sim *sim, int64_t nsteps, double dt);
+
+/* As lion_step with a per-trap time step dt[k] (batches only). */
+int lion_step_batch(lion_sim *sim, int64_t nsteps, const double *dt_per_trap);
+
+/* Copy the state to host arrays of length n_total (any pointer may be NULL to
+ * skip it); *t receives the time (trap 0's clock for a batch). Synchronises. */
+int lion_get_state(const lion_sim *sim, double *x, double *y, double *z, double *vx,
+                   double *vy, double *vz, double *t);
+
+/* Accelerations (m/s^2) at the current positions and time, recomputed now
+ * (length n_total host arrays).  Synchronises. */
+int lion_compute_accel(lion_sim *sim, double *ax, double *ay, double *az);
+
+/* Kinetic energy sum M v^2/2, Coulomb energy sum_{i<j} k_e Q_i Q_j / r_ij
+ * (the pair term of eq. (fullPotential)) and dc-trap energy
+ * sum Q_i (kappa U0/Z0^2)(z^2 - (x^2 + y^2)/2), in J, summed over all traps.
+ * Synchronises. */
+int lion_get_energy(lion_sim *sim, double *kinetic, double *coulomb, double *dc_trap);
+
+/* LION_ERR_NONFINITE if any position or velocity is NaN or infinite, else
+ * LION_OK.  Synchronises. */
+int lion_check_finite(lion_sim *sim);
+
+/* Message of the last failure on this handle ("" if none; a static string for
+ * sim == NULL). */
+const char *lion_last_error(const lion_sim *sim);
+
+/* Release host-side objects and cached launch graphs.  The workspace stays
+ * owned by the caller. */
+void lion_destroy(lion_sim *sim);
+
+/* Launch shape of the hot kernels; any field <= 0 keeps the built-in choice.
+ * Values outside the listed sets -> LION_ERR_ARG. */
+typedef struct {
+    int32_t i_per_lane;   /* target ions per lane in the pair kernel: 1, 2 or 4          */
+    int32_t j_split;      /* source slices per step (1..64), partial sums reduced in order */
+    int32_t chunk_steps;  /* steps per captured launch graph (1..1000)                     */
+    int32_t flush_len;    /* LION_MIXED_F64ACC: sources per FP32 run: 4, 8 or 16           */
+    int32_t batch_block;  /* threads per trap in batched mode: 64, 128, 256, 512 or 1024   */
+    int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
+} lion_kernel_config;
+
+int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);
+int lion_get_kernel_config(const lion_sim *sim, lion_kernel_config *cfg);
+
+/* Measurement helper: launches the pair-field kernel of this handle `reps`
+ * times (1..10000) on the handle's stream at the current positions, each launch
+ * bracketed by HIP events on that stream, and returns the mean launch
+ * duration in *ms_avg.  Changes no state (only the partial-sum scratch).
+ * Single-trap handles only (LION_ERR_UNSUPPORTED for batches).  Synchronises. */
+int lion_time_pair_kernel(lion_sim *sim, int32_t reps, double *ms_avg);
+
+/* As lion_time_pair_kernel for the batched kernel: `reps` launches of
+ * `nsteps` in-kernel steps each.  The state advances by reps * nsteps steps.
+ * Batched handles only.  Synchronises. */
+int lion_time_batch_kernel(lion_sim *sim, int32_t reps, int32_t nsteps, double dt,
+                           double *ms_avg);
+
+/* Host-only helper, eq. (Mathieuaq): the (V0, U0) giving Mathieu coefficients
+ * (q_x, a_x) to an ion of mass M (kg) and charge Q (C) in a trap of angular
+ * frequency Omega and geometry (r0, z0, kappa).  LION_ERR_ARG on invalid input. */
+int lion_mathieu_to_voltages(double q_x, double a_x, double M, double Q, double Omega,
+                             double r0, double z0, double kappa, double *V0, double *U0);
+
+/* Physical constants used by the library (CODATA 2018): elementary charge (C),
+ * vacuum permittivity (F/m), atomic mass unit (kg). */
+void lion_constants(double *e_charge, double *eps0, double *amu);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LION_H */

@@ -78,12 +78,16 @@ def bind(path: str):
     lp = ctypes.POINTER(ctypes.c_int64)
     tp = ctypes.POINTER(_Trap)
     lib.oracle_coulomb_constant.restype = ctypes.c_double
+    lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_coulomb_field.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp]
     lib.oracle_coulomb_field.restype = i64
     lib.oracle_accel.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, dp, dp, dp]
     lib.oracle_accel.restype = i64
     lib.oracle_accel_scale.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, dp]
     lib.oracle_accel_scale.restype = None
+    lib.oracle_accel_at.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, i64, lp, dp,
+                                    dp, dp, dp]
+    lib.oracle_accel_at.restype = None
     lib.oracle_step.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
     lib.oracle_step.restype = i64
@@ -113,6 +117,11 @@ def _d(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(_load().oracle_num_threads())
 
 
 def coulomb_constant() -> float:
@@ -151,6 +160,20 @@ def accel_scale(x, y, z, charge, mass, trap: Trap, t: float) -> np.ndarray:
     _load().oracle_accel_scale(x.size, _d(x), _d(y), _d(z), _d(q), _d(m), ctypes.byref(tr),
                                float(t), _d(s))
     return s
+
+
+def accel_at(x, y, z, charge, mass, trap: Trap, t: float, idx):
+    """``accel`` and ``accel_scale`` for the targets ``idx`` only (every source
+    still counts).  Returns (ax, ay, az, scale) of length len(idx)."""
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    ii = np.ascontiguousarray(idx, dtype=np.int64)
+    k = ii.size
+    ax, ay, az, sc = np.empty(k), np.empty(k), np.empty(k), np.empty(k)
+    tr = trap._c()
+    _load().oracle_accel_at(x.size, _d(x), _d(y), _d(z), _d(q), _d(m), ctypes.byref(tr), float(t),
+                            k, ii.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(ax), _d(ay),
+                            _d(az), _d(sc))
+    return ax, ay, az, sc
 
 
 def step(state: dict, charge, mass, trap: Trap, gamma: float, t_start: float, dt: float,

@@ -29,6 +29,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CODATA 2018 / SI 2019 values, written out here independently of the GPU library. */
 #define OR_ECHARGE 1.602176634e-19
@@ -45,6 +48,15 @@ typedef struct {
 } oracle_trap;
 
 double oracle_coulomb_constant(void) { return 1.0 / (4.0 * OR_PI * OR_EPS0); }
+
+/* Threads the OpenMP loops of this library use. */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Neumaier running sum: value s, compensation c. */
 typedef struct { double s, c; } nsum;
@@ -114,6 +126,43 @@ int64_t oracle_accel(int64_t n, const double *x, const double *y, const double *
         az[i] = qm * (az[i] + ez);
     }
     return coincident;
+}
+
+/* Acceleration of the selected targets idx[0..m) only (same definition as
+ * oracle_accel); used to check very large clouds on a sample of ions. */
+void oracle_accel_at(int64_t n, const double *x, const double *y, const double *z,
+                     const double *charge, const double *mass, const oracle_trap *tp, double t,
+                     int64_t m, const int64_t *idx, double *ax, double *ay, double *az,
+                     double *scale) {
+    const double ke = oracle_coulomb_constant();
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    double c = cos(tp->Omega * t);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = idx[k];
+        nsum sx = {0, 0}, sy = {0, 0}, sz = {0, 0}, sm = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double s = charge[j] * (1.0 / (r2 * sqrt(r2)));
+            nsum_add(&sx, s * dx);
+            nsum_add(&sy, s * dy);
+            nsum_add(&sz, s * dz);
+            nsum_add(&sm, fabs(charge[j]) / r2);
+        }
+        double ex, ey, ez;
+        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
+        double qm = charge[i] / mass[i];
+        ax[k] = qm * (ke * nsum_get(&sx) + ex);
+        ay[k] = qm * (ke * nsum_get(&sy) + ey);
+        az[k] = qm * (ke * nsum_get(&sz) + ez);
+        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
+        scale[k] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&sm) + erf + edc);
+    }
 }
 
 /* Rounding scale of a_i: (|Q_i|/M_i)(k_e sum_j |Q_j|/r_ij^2 + |E_rf,i| + |E_dc,i|),

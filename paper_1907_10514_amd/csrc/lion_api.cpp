@@ -1,0 +1,710 @@
+// C ABI of the trapped-ion engine: argument checking, workspace carving,
+// launch-shape choice and launch-graph caching around the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lion.h"
+#include "lion_internal.h"
+
+using lion::DevState;
+using lion::LaunchShape;
+using lion::TrapDev;
+
+struct lion_sim {
+    int precision = 0;
+    int64_t n = 0;
+    int32_t n_traps = 1;
+    bool batched = false;
+    int max_trap = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    DevState d{};
+    LaunchShape ls{};
+    lion_kernel_config cfg{};
+    int j_max = 1;
+    std::vector<TrapDev> traps;     // host mirror
+    std::vector<double> t_now;      // per-trap clock
+    std::vector<int64_t> offsets;   // [n_traps + 1]
+    std::vector<double> mass, charge;
+    bool state_set = false;
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (chunk length, kind)
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxTrap = 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int64_t padded(int64_t n) { return round_up(std::max<int64_t>(n, 1), 1024); }
+
+// Upper bound on source slices for n ions: at most 64, at most one slice per 16
+// sources, and partial sums kept under ~400 MB for very large n.
+int j_max_for(int64_t n) {
+    int64_t j = std::min<int64_t>(64, std::max<int64_t>(1, (int64_t(1) << 24) / std::max<int64_t>(n, 1)));
+    j = std::min<int64_t>(j, std::max<int64_t>(1, round_up(n, 16) / 16));
+    return (int)j;
+}
+
+struct Layout {
+    size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
+        flags, total;
+};
+
+Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
+    const int64_t np = padded(n);
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.src = take(np * sizeof(double4));
+    L.srcm = (precision != LION_FP64 && !batched) ? take(np * sizeof(lion::MixedSrc)) : SIZE_MAX;
+    L.v = take(3 * np * sizeof(double));
+    L.a = take(3 * np * sizeof(double));
+    L.qm = take(np * sizeof(double));
+    L.qe = take(np * sizeof(double));
+    L.mass = take(np * sizeof(double));
+    L.trap_of = take(np * sizeof(int32_t));
+    L.part = batched ? SIZE_MAX : take((size_t)j_max_for(n) * 3 * np * sizeof(double));
+    L.scratch = take(np * sizeof(double));
+    L.traps = take((size_t)n_traps * sizeof(TrapDev));
+    L.offsets = take((size_t)(n_traps + 1) * sizeof(int64_t));
+    L.order = take((size_t)n_traps * sizeof(int32_t));
+    L.counter = take(sizeof(int64_t));
+    L.flags = take(4 * sizeof(int32_t));
+    L.total = o;
+    return L;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int fail(lion_sim* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+int hip_fail(lion_sim* s, hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(s, LION_ERR_HIP, m);
+}
+
+#define LION_HIP(s, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail((s), e_, #call); \
+    } while (0)
+
+void default_shape(lion_sim* s) {
+    LaunchShape& ls = s->ls;
+    const int64_t n = s->n;
+    ls.i_per_lane = s->cfg.i_per_lane > 0 ? s->cfg.i_per_lane : (n >= 8192 ? 2 : 1);
+    ls.flush_len = s->cfg.flush_len > 0 ? s->cfg.flush_len : 8;
+    ls.batch_block = s->cfg.batch_block > 0 ? s->cfg.batch_block : 256;
+    const int64_t n16 = round_up(n, 16);
+    int j;
+    if (s->cfg.j_split > 0) {
+        j = s->cfg.j_split;
+    } else {
+        // aim for ~4096 waves (4 per SIMD on 256 CUs), slices of >= 64 sources
+        const int64_t waves_i = std::max<int64_t>(1, (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane));
+        j = (int)std::max<int64_t>(1, (4096 + waves_i - 1) / waves_i);
+        j = (int)std::min<int64_t>(j, std::max<int64_t>(1, n16 / 64));
+    }
+    j = std::max(1, std::min(j, s->j_max));
+    ls.jps = (int)round_up((n16 + j - 1) / j, 16);
+    ls.j_split = (int)((n16 + ls.jps - 1) / ls.jps);  // slices that hold sources
+}
+
+void clear_graphs(lion_sim* s) {
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+}
+
+int upload_traps(lion_sim* s) {
+    LION_HIP(s, hipMemcpyAsync(s->d.traps, s->traps.data(), s->traps.size() * sizeof(TrapDev),
+                               hipMemcpyHostToDevice, s->stream));
+    return LION_OK;
+}
+
+// Accelerations at the current positions and clocks.
+int refresh_accel(lion_sim* s) {
+    for (int k = 0; k < s->n_traps; ++k) s->traps[k].t_start = s->t_now[k];
+    int rc = upload_traps(s);
+    if (rc) return rc;
+    if (s->batched) {
+        LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), s->stream));
+        LION_HIP(s, lion::launch_batch_accel(s->d, s->precision, s->n_traps, s->max_trap, s->ls,
+                                             s->stream));
+        return LION_OK;
+    }
+    LION_HIP(s, lion::launch_pair(s->d, s->precision, s->ls, false, s->stream));
+    LION_HIP(s, lion::launch_update(s->d, s->precision, s->ls, lion::kModeAccel, false, s->stream));
+    return LION_OK;
+}
+
+// Kernels of one chunk of L steps on stream st.
+hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
+    hipError_t e;
+    if (s->batched) {
+        e = lion::launch_batch(s->d, s->precision, s->n_traps, s->max_trap, s->ls, (int)L, 0, st);
+        if (e != hipSuccess) return e;
+        return lion::launch_counter_add(s->d, L, st);
+    }
+    e = lion::launch_drift(s->d, st);
+    if (e != hipSuccess) return e;
+    for (int64_t k = 0; k < L; ++k) {
+        e = lion::launch_pair(s->d, s->precision, s->ls, true, st);
+        if (e != hipSuccess) return e;
+        const int mode = (k + 1 < L) ? lion::kModeEndDrift : lion::kModeEnd;
+        e = lion::launch_update(s->d, s->precision, s->ls, mode, true, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int run_chunk(lion_sim* s, int64_t L) {
+    if (s->cfg.use_graph == 2) {
+        LION_HIP(s, enqueue_chunk(s, L, s->stream));
+        return LION_OK;
+    }
+    auto key = std::make_pair(L, 0);
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+        hipGraph_t g = nullptr;
+        LION_HIP(s, hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_chunk(s, L, s->capture);
+        hipError_t e2 = hipStreamEndCapture(s->capture, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(s, e, "capture chunk");
+        }
+        if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+        it = s->graphs.emplace(key, ex).first;
+    }
+    LION_HIP(s, hipGraphLaunch(it->second, s->stream));
+    return LION_OK;
+}
+
+int check_ws(lion_sim* s, void* ws, size_t bytes, size_t need) {
+    if (!ws) return fail(s, LION_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(s, LION_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (bytes < need)
+        return fail(s, LION_ERR_WORKSPACE,
+                    "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                        std::to_string(bytes));
+    return LION_OK;
+}
+
+// Message of the last failed create on this thread (no handle exists then).
+thread_local std::string g_create_err;
+
+int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, int64_t n,
+                  const double* masses, const double* charges, int precision, void* ws,
+                  size_t ws_bytes, void* stream, bool batched) {
+    if (!out) return LION_ERR_ARG;
+    *out = nullptr;
+    auto* s = new lion_sim();
+    auto bail = [&](int code) {
+        g_create_err = s->err;
+        delete s;
+        return code;
+    };
+    if (precision < LION_FP64 || precision > LION_MIXED_KAHAN)
+        return bail(fail(s, LION_ERR_ARG, "unknown precision"));
+    if (n < 1) return bail(fail(s, LION_ERR_ARG, "need at least one ion"));
+    if (n > (int64_t(1) << 30)) return bail(fail(s, LION_ERR_ARG, "too many ions"));
+    if (!masses || !charges) return bail(fail(s, LION_ERR_ARG, "masses or charges is NULL"));
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_fin(masses[i]) || masses[i] <= 0.0)
+            return bail(fail(s, LION_ERR_ARG, "mass " + std::to_string(i) + " not finite and > 0"));
+        if (!is_fin(charges[i]))
+            return bail(fail(s, LION_ERR_ARG, "charge " + std::to_string(i) + " not finite"));
+    }
+    s->precision = precision;
+    s->n = n;
+    s->n_traps = n_traps;
+    s->batched = batched;
+    s->stream = (hipStream_t)stream;
+    s->offsets.assign(n_traps + 1, 0);
+    for (int k = 0; k < n_traps; ++k) s->offsets[k + 1] = s->offsets[k] + n_per_trap[k];
+    s->max_trap = 0;
+    for (int k = 0; k < n_traps; ++k) s->max_trap = std::max<int>(s->max_trap, (int)n_per_trap[k]);
+    Layout L = layout_for(n, n_traps, precision, batched);
+    int rc = check_ws(s, ws, ws_bytes, L.total);
+    if (rc) return bail(rc);
+    if (hipGetDevice(&s->device) != hipSuccess) return bail(fail(s, LION_ERR_HIP, "hipGetDevice failed"));
+    if (hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(s, LION_ERR_HIP, "hipStreamCreateWithFlags failed"));
+    char* base = (char*)ws;
+    DevState& d = s->d;
+    d.n = n;
+    d.n_pad = padded(n);
+    d.src = (double4*)(base + L.src);
+    d.srcm = L.srcm == SIZE_MAX ? nullptr : (lion::MixedSrc*)(base + L.srcm);
+    d.vx = (double*)(base + L.v);
+    d.vy = d.vx + d.n_pad;
+    d.vz = d.vy + d.n_pad;
+    d.ax = (double*)(base + L.a);
+    d.ay = d.ax + d.n_pad;
+    d.az = d.ay + d.n_pad;
+    d.qm = (double*)(base + L.qm);
+    d.qe = (double*)(base + L.qe);
+    d.mass = (double*)(base + L.mass);
+    d.trap_of = (int32_t*)(base + L.trap_of);
+    d.part = L.part == SIZE_MAX ? nullptr : (double*)(base + L.part);
+    d.scratch = (double*)(base + L.scratch);
+    d.traps = (TrapDev*)(base + L.traps);
+    d.offsets = (int64_t*)(base + L.offsets);
+    d.order = (int32_t*)(base + L.order);
+    d.counter = (int64_t*)(base + L.counter);
+    d.flags = (int32_t*)(base + L.flags);
+    s->j_max = batched ? 1 : j_max_for(n);
+    s->cfg.chunk_steps = 100;
+    s->cfg.use_graph = 1;
+    default_shape(s);
+
+    // per-ion constants
+    const int64_t np = d.n_pad;
+    std::vector<double> qm(np, 0.0), qe(np, 0.0), mass(np, 0.0);
+    std::vector<int32_t> trap_of(np, 0);
+    for (int k = 0; k < n_traps; ++k)
+        for (int64_t i = s->offsets[k]; i < s->offsets[k + 1]; ++i) trap_of[i] = k;
+    for (int64_t i = 0; i < n; ++i) {
+        qm[i] = charges[i] / masses[i];
+        qe[i] = charges[i] / lion::kElementaryCharge;
+        mass[i] = masses[i];
+    }
+    s->mass.assign(masses, masses + n);
+    s->charge.assign(charges, charges + n);
+    s->traps.assign(n_traps, TrapDev{0, 1.0, 0, 1.0, 0, 0, 0, 0});
+    s->t_now.assign(n_traps, 0.0);
+    std::vector<int32_t> order(n_traps);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return n_per_trap[a] > n_per_trap[b]; });
+    std::vector<double4> zero_src(np, make_double4(0, 0, 0, 0));
+    for (int64_t i = 0; i < n; ++i) zero_src[i].w = 1.5 * qe[i];
+    hipStream_t st = s->stream;
+    bool ok = hipMemcpyAsync(d.qm, qm.data(), np * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.qe, qe.data(), np * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.mass, mass.data(), np * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.trap_of, trap_of.data(), np * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.offsets, s->offsets.data(), (n_traps + 1) * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.order, order.data(), n_traps * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.src, zero_src.data(), np * sizeof(double4), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemsetAsync(d.vx, 0, 3 * np * 8, st) == hipSuccess &&
+              hipMemsetAsync(d.ax, 0, 3 * np * 8, st) == hipSuccess &&
+              hipMemsetAsync(d.counter, 0, 8, st) == hipSuccess &&
+              hipMemsetAsync(d.flags, 0, 16, st) == hipSuccess &&
+              hipMemcpyAsync(d.traps, s->traps.data(), n_traps * sizeof(TrapDev), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (ok && d.srcm) ok = lion::launch_pack_mixed(d, st) == hipSuccess;
+    if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        (void)hipStreamDestroy(s->capture);
+        return bail(fail(s, LION_ERR_HIP, "device initialisation failed"));
+    }
+    g_create_err.clear();
+    *out = s;
+    return LION_OK;
+}
+
+int check_handle(const lion_sim* s) { return s ? LION_OK : LION_ERR_ARG; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lion_workspace_bytes(int64_t n_total, int32_t n_traps, int precision) {
+    if (n_total < 1 || n_traps < 1 || precision < 0 || precision > 2) return 0;
+    return layout_for(n_total, n_traps, precision, n_traps > 1).total;
+}
+
+int lion_create(lion_sim** out, int64_t n, const double* masses_kg, const double* charges_C,
+                int precision, void* dev_workspace, size_t ws_bytes, void* hip_stream) {
+    const int64_t per[1] = {n};
+    return create_common(out, 1, per, n, masses_kg, charges_C, precision, dev_workspace,
+                         ws_bytes, hip_stream, false);
+}
+
+int lion_create_batch(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap,
+                      const double* masses_kg, const double* charges_C, int precision,
+                      void* dev_workspace, size_t ws_bytes, void* hip_stream) {
+    if (!out) return LION_ERR_ARG;
+    *out = nullptr;
+    if (n_traps < 1 || !n_per_trap) {
+        g_create_err = "need n_traps >= 1 and n_per_trap";
+        return LION_ERR_ARG;
+    }
+    int64_t n = 0;
+    for (int k = 0; k < n_traps; ++k) {
+        if (n_per_trap[k] < 1 || n_per_trap[k] > kMaxTrap) {
+            g_create_err = "trap " + std::to_string(k) + " must hold 1..1024 ions";
+            return LION_ERR_ARG;
+        }
+        n += n_per_trap[k];
+    }
+    // a batch of one trap still uses the batched (workgroup-per-trap) path
+    return create_common(out, n_traps, n_per_trap, n, masses_kg, charges_C, precision,
+                         dev_workspace, ws_bytes, hip_stream, true);
+}
+
+int lion_set_state(lion_sim* s, const double* x, const double* y, const double* z,
+                   const double* vx, const double* vy, const double* vz, double t) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (!x || !y || !z || !vx || !vy || !vz) return fail(s, LION_ERR_ARG, "state array is NULL");
+    if (!is_fin(t)) return fail(s, LION_ERR_ARG, "t not finite");
+    const int64_t n = s->n, np = s->d.n_pad;
+    std::vector<double4> src(np, make_double4(0, 0, 0, 0));
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_fin(x[i]) || !is_fin(y[i]) || !is_fin(z[i]) || !is_fin(vx[i]) || !is_fin(vy[i]) ||
+            !is_fin(vz[i]))
+            return fail(s, LION_ERR_ARG, "state of ion " + std::to_string(i) + " not finite");
+        src[i] = make_double4(x[i], y[i], z[i], 1.5 * (s->charge[i] / lion::kElementaryCharge));
+    }
+    LION_HIP(s, hipSetDevice(s->device));
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipMemcpyAsync(s->d.src, src.data(), np * sizeof(double4), hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(s->d.vx, vx, n * 8, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(s->d.vy, vy, n * 8, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(s->d.vz, vz, n * 8, hipMemcpyHostToDevice, st));
+    if (s->d.srcm) LION_HIP(s, lion::launch_pack_mixed(s->d, st));
+    std::fill(s->t_now.begin(), s->t_now.end(), t);
+    int rc = refresh_accel(s);
+    if (rc) return rc;
+    LION_HIP(s, hipStreamSynchronize(st));
+    s->state_set = true;
+    return LION_OK;
+}
+
+int lion_set_trap(lion_sim* s, int32_t trap, double V_rf, double Omega, double U_dc, double r0,
+                  double z0, double kappa) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (trap < -1 || trap >= s->n_traps) return fail(s, LION_ERR_ARG, "trap index out of range");
+    if (!is_fin(V_rf) || !is_fin(Omega) || !is_fin(U_dc) || !is_fin(r0) || !is_fin(z0) ||
+        !is_fin(kappa))
+        return fail(s, LION_ERR_ARG, "trap parameter not finite");
+    if (r0 <= 0 || z0 <= 0) return fail(s, LION_ERR_ARG, "r0 and z0 must be > 0");
+    if (V_rf != 0.0 && Omega <= 0.0) return fail(s, LION_ERR_ARG, "Omega must be > 0 when V_rf != 0");
+    const int lo = trap < 0 ? 0 : trap, hi = trap < 0 ? s->n_traps : trap + 1;
+    for (int k = lo; k < hi; ++k) {
+        s->traps[k].a_rf = V_rf / (r0 * r0);
+        s->traps[k].omega = Omega;
+        s->traps[k].a_dc = kappa * U_dc / (z0 * z0);
+    }
+    LION_HIP(s, hipSetDevice(s->device));
+    int rc = upload_traps(s);
+    if (rc) return rc;
+    if (s->state_set) return refresh_accel(s);
+    return LION_OK;
+}
+
+int lion_set_damping(lion_sim* s, int32_t trap, double gamma) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (trap < -1 || trap >= s->n_traps) return fail(s, LION_ERR_ARG, "trap index out of range");
+    if (!is_fin(gamma) || gamma < 0.0) return fail(s, LION_ERR_ARG, "gamma must be finite and >= 0");
+    const int lo = trap < 0 ? 0 : trap, hi = trap < 0 ? s->n_traps : trap + 1;
+    for (int k = lo; k < hi; ++k) s->traps[k].gamma = gamma;
+    return LION_OK;
+}
+
+static int step_common(lion_sim* s, int64_t nsteps, const double* dts) {
+    if (nsteps < 0) return fail(s, LION_ERR_ARG, "nsteps must be >= 0");
+    for (int k = 0; k < s->n_traps; ++k)
+        if (!is_fin(dts[k]) || dts[k] <= 0.0) return fail(s, LION_ERR_ARG, "dt must be finite and > 0");
+    if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
+    if (nsteps == 0) return LION_OK;
+    LION_HIP(s, hipSetDevice(s->device));
+    for (int k = 0; k < s->n_traps; ++k) {
+        TrapDev& T = s->traps[k];
+        T.dt = dts[k];
+        T.h = 0.5 * dts[k];
+        T.f = std::exp(-(T.gamma * dts[k]) * 0.5);
+        T.t_start = s->t_now[k];
+    }
+    int rc = upload_traps(s);
+    if (rc) return rc;
+    LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), s->stream));
+    const int64_t S = std::max(1, s->cfg.chunk_steps);
+    for (int64_t done = 0; done < nsteps;) {
+        const int64_t L = std::min(S, nsteps - done);
+        rc = run_chunk(s, L);
+        if (rc) return rc;
+        done += L;
+    }
+    for (int k = 0; k < s->n_traps; ++k) s->t_now[k] = s->traps[k].t_start + (double)nsteps * dts[k];
+    return LION_OK;
+}
+
+int lion_step(lion_sim* s, int64_t nsteps, double dt) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    std::vector<double> dts(s->n_traps, dt);
+    return step_common(s, nsteps, dts.data());
+}
+
+int lion_step_batch(lion_sim* s, int64_t nsteps, const double* dt_per_trap) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (!dt_per_trap) return fail(s, LION_ERR_ARG, "dt_per_trap is NULL");
+    return step_common(s, nsteps, dt_per_trap);
+}
+
+int lion_get_state(const lion_sim* cs, double* x, double* y, double* z, double* vx, double* vy,
+                   double* vz, double* t) {
+    lion_sim* s = const_cast<lion_sim*>(cs);
+    if (check_handle(s)) return LION_ERR_ARG;
+    const int64_t n = s->n;
+    LION_HIP(s, hipSetDevice(s->device));
+    std::vector<double4> src(n);
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipMemcpyAsync(src.data(), s->d.src, n * sizeof(double4), hipMemcpyDeviceToHost, st));
+    if (vx) LION_HIP(s, hipMemcpyAsync(vx, s->d.vx, n * 8, hipMemcpyDeviceToHost, st));
+    if (vy) LION_HIP(s, hipMemcpyAsync(vy, s->d.vy, n * 8, hipMemcpyDeviceToHost, st));
+    if (vz) LION_HIP(s, hipMemcpyAsync(vz, s->d.vz, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+        if (x) x[i] = src[i].x;
+        if (y) y[i] = src[i].y;
+        if (z) z[i] = src[i].z;
+    }
+    if (t) *t = s->t_now[0];
+    return LION_OK;
+}
+
+int lion_compute_accel(lion_sim* s, double* ax, double* ay, double* az) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (!ax || !ay || !az) return fail(s, LION_ERR_ARG, "output array is NULL");
+    if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
+    LION_HIP(s, hipSetDevice(s->device));
+    int rc = refresh_accel(s);
+    if (rc) return rc;
+    const int64_t n = s->n;
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipMemcpyAsync(ax, s->d.ax, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(ay, s->d.ay, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(az, s->d.az, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    return LION_OK;
+}
+
+int lion_get_energy(lion_sim* s, double* kinetic, double* coulomb, double* dc_trap) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
+    LION_HIP(s, hipSetDevice(s->device));
+    const int64_t n = s->n;
+    hipStream_t st = s->stream;
+    LION_HIP(s, lion::launch_coulomb_potential(s->d, s->n_traps, st));
+    std::vector<double> pe(n), vx(n), vy(n), vz(n);
+    std::vector<double4> src(n);
+    LION_HIP(s, hipMemcpyAsync(pe.data(), s->d.scratch, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(src.data(), s->d.src, n * sizeof(double4), hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(vx.data(), s->d.vx, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(vy.data(), s->d.vy, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(vz.data(), s->d.vz, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    // compensated host sums
+    auto add = [](double& sum, double& c, double v) {
+        double t = sum + v;
+        c += std::fabs(sum) >= std::fabs(v) ? (sum - t) + v : (v - t) + sum;
+        sum = t;
+    };
+    const double ke_e2 = lion::kElementaryCharge * lion::kElementaryCharge / (4.0 * lion::kPi * lion::kEps0);
+    double K = 0, Kc = 0, C = 0, Cc = 0, D = 0, Dc = 0;
+    for (int k = 0; k < s->n_traps; ++k) {
+        const double a_dc = s->traps[k].a_dc;
+        for (int64_t i = s->offsets[k]; i < s->offsets[k + 1]; ++i) {
+            const double m = s->mass[i], q = s->charge[i];
+            add(K, Kc, 0.5 * m * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]));
+            add(C, Cc, 0.5 * ke_e2 * (q / lion::kElementaryCharge) * pe[i]);
+            const double4 p = src[i];
+            add(D, Dc, q * a_dc * (p.z * p.z - 0.5 * (p.x * p.x + p.y * p.y)));
+        }
+    }
+    if (kinetic) *kinetic = K + Kc;
+    if (coulomb) *coulomb = C + Cc;
+    if (dc_trap) *dc_trap = D + Dc;
+    return LION_OK;
+}
+
+int lion_check_finite(lion_sim* s) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    LION_HIP(s, hipSetDevice(s->device));
+    hipStream_t st = s->stream;
+    int32_t flags[4] = {0, 0, 0, 0};
+    LION_HIP(s, hipMemsetAsync(s->d.flags, 0, 16, st));
+    LION_HIP(s, lion::launch_check_finite(s->d, st));
+    LION_HIP(s, hipMemcpyAsync(flags, s->d.flags, 16, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    if (flags[0] != 0)
+        return fail(s, LION_ERR_NONFINITE, std::to_string(flags[0]) + " ions have a non-finite state");
+    return LION_OK;
+}
+
+const char* lion_last_error(const lion_sim* s) {
+    if (!s) return g_create_err.empty() ? "invalid handle" : g_create_err.c_str();
+    return s->err.c_str();
+}
+
+void lion_destroy(lion_sim* s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    clear_graphs(s);
+    if (s->capture) (void)hipStreamDestroy(s->capture);
+    delete s;
+}
+
+int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
+    if (check_handle(s) || !c) return LION_ERR_ARG;
+    auto in = [](int v, std::initializer_list<int> set) {
+        return v <= 0 || std::find(set.begin(), set.end(), v) != set.end();
+    };
+    if (!in(c->i_per_lane, {1, 2, 4})) return fail(s, LION_ERR_ARG, "i_per_lane must be 1, 2 or 4");
+    if (c->j_split > 64) return fail(s, LION_ERR_ARG, "j_split must be <= 64");
+    if (c->chunk_steps > 1000) return fail(s, LION_ERR_ARG, "chunk_steps must be <= 1000");
+    if (!in(c->flush_len, {4, 8, 16})) return fail(s, LION_ERR_ARG, "flush_len must be 4, 8 or 16");
+    if (!in(c->batch_block, {256, 512, 1024}))
+        return fail(s, LION_ERR_ARG, "batch_block must be 256, 512 or 1024");
+    if (!in(c->use_graph, {1, 2})) return fail(s, LION_ERR_ARG, "use_graph must be 1 or 2");
+    if (c->j_split > s->j_max)
+        return fail(s, LION_ERR_ARG, "j_split above " + std::to_string(s->j_max) + " for this size");
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    clear_graphs(s);
+    s->cfg.i_per_lane = c->i_per_lane;
+    s->cfg.j_split = c->j_split;
+    s->cfg.flush_len = c->flush_len;
+    s->cfg.batch_block = c->batch_block;
+    s->cfg.chunk_steps = c->chunk_steps > 0 ? c->chunk_steps : 100;
+    s->cfg.use_graph = c->use_graph > 0 ? c->use_graph : 1;
+    default_shape(s);
+    return LION_OK;
+}
+
+int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
+    if (check_handle(s) || !c) return LION_ERR_ARG;
+    c->i_per_lane = s->ls.i_per_lane;
+    c->j_split = s->ls.j_split;
+    c->chunk_steps = s->cfg.chunk_steps;
+    c->flush_len = s->ls.flush_len;
+    c->batch_block = s->ls.batch_block;
+    c->use_graph = s->cfg.use_graph;
+    return LION_OK;
+}
+
+int lion_time_pair_kernel(lion_sim* s, int32_t reps, double* ms_avg) {
+    if (check_handle(s) || !ms_avg) return LION_ERR_ARG;
+    if (s->batched) return fail(s, LION_ERR_UNSUPPORTED, "single-trap handles only");
+    if (reps < 1 || reps > 10000) return fail(s, LION_ERR_ARG, "reps must be 1..10000");
+    if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
+    LION_HIP(s, hipSetDevice(s->device));
+    hipStream_t st = s->stream;
+    std::vector<hipEvent_t> ev(2 * reps, nullptr);
+    for (auto& e : ev) LION_HIP(s, hipEventCreate(&e));
+    int rc = LION_OK;
+    for (int r = 0; r < reps && rc == LION_OK; ++r) {
+        if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
+            lion::launch_pair(s->d, s->precision, s->ls, false, st) != hipSuccess ||
+            hipEventRecord(ev[2 * r + 1], st) != hipSuccess)
+            rc = fail(s, LION_ERR_HIP, "pair kernel timing launch failed");
+    }
+    double total = 0.0;
+    if (rc == LION_OK && hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(s, LION_ERR_HIP, "hipStreamSynchronize failed");
+    for (int r = 0; r < reps && rc == LION_OK; ++r) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess)
+            rc = fail(s, LION_ERR_HIP, "hipEventElapsedTime failed");
+        total += ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc == LION_OK) *ms_avg = total / reps;
+    return rc;
+}
+
+int lion_time_batch_kernel(lion_sim* s, int32_t reps, int32_t nsteps, double dt, double* ms_avg) {
+    if (check_handle(s) || !ms_avg) return LION_ERR_ARG;
+    if (!s->batched) return fail(s, LION_ERR_UNSUPPORTED, "batched handles only");
+    if (reps < 1 || reps > 10000 || nsteps < 1 || nsteps > 100000)
+        return fail(s, LION_ERR_ARG, "reps must be 1..10000 and nsteps 1..100000");
+    std::vector<double> dts(s->n_traps, dt);
+    // set up clocks, step sizes and damping factors exactly as lion_step does
+    int rc = step_common(s, 0, dts.data());
+    if (rc) return rc;
+    if (!is_fin(dt) || dt <= 0.0) return fail(s, LION_ERR_ARG, "dt must be finite and > 0");
+    for (int k = 0; k < s->n_traps; ++k) {
+        TrapDev& T = s->traps[k];
+        T.dt = dt;
+        T.h = 0.5 * dt;
+        T.f = std::exp(-(T.gamma * dt) * 0.5);
+        T.t_start = s->t_now[k];
+    }
+    rc = upload_traps(s);
+    if (rc) return rc;
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), st));
+    std::vector<hipEvent_t> ev(2 * reps, nullptr);
+    for (auto& e : ev) LION_HIP(s, hipEventCreate(&e));
+    for (int r = 0; r < reps && rc == LION_OK; ++r) {
+        if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
+            lion::launch_batch(s->d, s->precision, s->n_traps, s->max_trap, s->ls, nsteps, 0, st) != hipSuccess ||
+            hipEventRecord(ev[2 * r + 1], st) != hipSuccess ||
+            lion::launch_counter_add(s->d, nsteps, st) != hipSuccess)
+            rc = fail(s, LION_ERR_HIP, "batch kernel timing launch failed");
+    }
+    double total = 0.0;
+    if (rc == LION_OK && hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(s, LION_ERR_HIP, "hipStreamSynchronize failed");
+    for (int r = 0; r < reps && rc == LION_OK; ++r) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess)
+            rc = fail(s, LION_ERR_HIP, "hipEventElapsedTime failed");
+        total += ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc != LION_OK) return rc;
+    for (int k = 0; k < s->n_traps; ++k)
+        s->t_now[k] = s->traps[k].t_start + (double)((int64_t)reps * nsteps) * dt;
+    *ms_avg = total / reps;
+    return LION_OK;
+}
+
+int lion_mathieu_to_voltages(double q_x, double a_x, double M, double Q, double Omega, double r0,
+                             double z0, double kappa, double* V0, double* U0) {
+    if (!V0 || !U0) return LION_ERR_ARG;
+    if (!is_fin(q_x) || !is_fin(a_x) || !is_fin(M) || !is_fin(Q) || !is_fin(Omega) ||
+        !is_fin(r0) || !is_fin(z0) || !is_fin(kappa))
+        return LION_ERR_ARG;
+    if (M <= 0 || Q == 0 || Omega <= 0 || r0 <= 0 || z0 <= 0) return LION_ERR_ARG;
+    if (a_x != 0.0 && kappa == 0.0) return LION_ERR_ARG;
+    // eq. (Mathieuaq): q_x = 2 Q V0 / (M r0^2 Omega^2), a_x = -4 Q kappa U0 / (M z0^2 Omega^2)
+    *V0 = q_x * M * r0 * r0 * Omega * Omega / (2.0 * Q);
+    *U0 = a_x == 0.0 ? 0.0 : -a_x * M * z0 * z0 * Omega * Omega / (4.0 * Q * kappa);
+    return LION_OK;
+}
+
+void lion_constants(double* e_charge, double* eps0, double* amu) {
+    if (e_charge) *e_charge = lion::kElementaryCharge;
+    if (eps0) *eps0 = lion::kEps0;
+    if (amu) *amu = lion::kAmu;
+}
+
+}  // extern "C"

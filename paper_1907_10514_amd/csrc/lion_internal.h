@@ -1,0 +1,102 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lion {
+
+// CODATA 2018 / SI 2019.
+constexpr double kElementaryCharge = 1.602176634e-19;  // C
+constexpr double kEps0 = 8.8541878128e-12;             // F/m
+constexpr double kAmu = 1.66053906660e-27;             // kg
+constexpr double kPi = 3.14159265358979323846;
+
+// Float-float positions of the FP32 pair path are stored in units of
+// 2^-20 m (~0.95 um) so that inter-ion distances are O(1) and r^-3 of close
+// pairs stays far from the FP32 range limits; the power of two keeps the
+// rescaling exact.
+constexpr double kMixedScale = 1048576.0;             // 2^20 per metre
+constexpr double kMixedFieldScale = 1099511627776.0;  // 2^40 = kMixedScale^2
+
+// Lower bound added to r^2 so that the self pair and exactly coincident ions
+// give a finite r^-3 multiplying an exactly zero difference (contribution 0).
+constexpr double kR2FloorF64 = 1e-200;  // m^2
+constexpr float kR2FloorF32 = 1e-20f;   // (2^-20 m)^2
+
+// Per-trap parameters in device memory.  The rf phase uses
+// t = t_start + k dt evaluated in FP64 with k the step index inside the
+// current lion_step call.
+struct TrapDev {
+    double a_rf;     // V0 / R0^2                     (V/m^2)
+    double omega;    // Omega                         (rad/s)
+    double a_dc;     // kappa U0 / Z0^2               (V/m^2)
+    double f;        // exp(-gamma dt / 2)
+    double dt;       // s
+    double h;        // dt / 2
+    double t_start;  // s
+    double gamma;    // 1/s (kept for reference)
+};
+
+// One ion of the FP32 pair stream: high and low float parts of the scaled
+// position and the negated charge in units of e.
+struct MixedSrc {
+    float xh, yh, zh, nq;
+    float xl, yl, zl, pad;
+};
+
+enum UpdateMode : int {
+    kModeAccel = 0,      // a <- a(x, t) only
+    kModeEnd = 1,        // a <- a(x, t); v <- f (v + h a)
+    kModeEndDrift = 2,   // kModeEnd, then the first half of the next step
+};
+
+// Device arrays carved from the caller's workspace.
+struct DevState {
+    int64_t n;        // ions (all traps)
+    int64_t n_pad;    // padded length of the per-ion arrays
+    double4* src;     // [n_pad] {x, y, z, 1.5 q/e}: positions + FP64 source stream
+    MixedSrc* srcm;   // [n_pad] FP32 source stream (mixed precisions only)
+    double* vx;
+    double* vy;
+    double* vz;
+    double* ax;
+    double* ay;
+    double* az;
+    double* qm;       // Q / M per ion
+    double* qe;       // Q / e per ion
+    double* mass;     // kg
+    int32_t* trap_of; // trap index per ion
+    double* part;     // [j_split][3][n_pad] partial field sums
+    double* scratch;  // [n_pad] per-ion diagnostics
+    TrapDev* traps;   // [n_traps]
+    int64_t* offsets; // [n_traps + 1]
+    int32_t* order;   // [n_traps] launch order (largest trap first)
+    int64_t* counter; // step index inside the current call
+    int32_t* flags;   // [4] diagnostics (non-finite count)
+};
+
+struct LaunchShape {
+    int i_per_lane;
+    int j_split;
+    int jps;          // sources per slice (multiple of 4)
+    int flush_len;
+    int batch_block;
+};
+
+// Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_drift(const DevState& s, hipStream_t st);
+hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, bool count_step,
+                       hipStream_t st);
+hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls, int mode,
+                         bool use_counter, hipStream_t st);
+hipError_t launch_pack_mixed(const DevState& s, hipStream_t st);
+hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_trap,
+                        const LaunchShape& ls, int nsteps, int mode_first, hipStream_t st);
+hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int max_trap,
+                              const LaunchShape& ls, hipStream_t st);
+hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
+hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
+hipError_t launch_check_finite(const DevState& s, hipStream_t st);
+
+}  // namespace lion

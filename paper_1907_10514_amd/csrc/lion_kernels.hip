@@ -1,0 +1,779 @@
+// HIP kernels for gfx950 (CDNA4): all-pairs Coulomb field, linear Paul trap
+// field and damped velocity-Verlet update of trapped ions.
+//
+// Physics (paper, "Dynamics of trapped ions" eq. (field) and eq.
+// (fullPotential); "Implementation details": unscreened pair sum, nve
+// integration; "Cooling the motion of ions": viscous laser-cooling force):
+//   S_i   = sum_{j != i} q_j (r_i - r_j) / |r_i - r_j|^3     (q_j = Q_j / e)
+//   a_i   = (Q_i/M_i) [ k_e e S_i + A_rf cos(Omega t)(x, -y, 0) + A_dc (x, y, -2z) ]
+//   step  v <- f v; v <- v + h a; x <- x + dt v; a <- a(x, t+dt); v <- f (v + h a)
+//
+// Layout of the single-trap step (one trap, any N):
+//   pair kernel   grid (ceil(N / (256 I)), J): lane = I target ions held in
+//                 registers, a wave walks one slice of the sources.  Source
+//                 positions are wave-uniform, so they arrive through scalar
+//                 loads straight into SGPRs and feed every lane without LDS
+//                 traffic; each slice writes one partial sum per target.
+//   update kernel per ion: sums the J partials in slice order (deterministic,
+//                 no atomics), adds the trap field at t_{k+1}, applies the
+//                 second half kick and damping and, inside a chunk, the first
+//                 half of the next step (damping, half kick, drift).
+// Batched traps: one workgroup per trap keeps the trap's source stream in LDS
+// and runs many steps in one launch with workgroup barriers only.
+//
+// Pair arithmetic:
+//   FP64  d = x_j - x_i; r2 = |d|^2; y0 = v_rsq_f64(r2) (~2^-24 relative);
+//         q y^3 is formed with one folded Newton correction,
+//         q r^-3 ~ q y0^3 (5/2 - 3/2 r2 y0^2), relative error ~7.5 e0^2 < 1e-13.
+//   FP32  float-float positions (hi + lo, scaled by 2^20/m) give d with ~2 ulp
+//         relative error even for close pairs of far-off-centre ions; r^-3 from
+//         v_rsq_f32; sums in FP32 over short runs flushed to FP64, or Kahan.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lion_internal.h"
+
+namespace lion {
+namespace {
+
+constexpr int kPairBlock = 256;
+constexpr double kKeE = kElementaryCharge / (4.0 * kPi * kEps0);  // k_e e (V m)
+
+// ------------------------------------------------------------------ pair terms
+
+// One FP64 pair term, accumulated into (sx, sy, sz).  p = {x_j, y_j, z_j, 1.5 q_j}.
+__device__ __forceinline__ void pair_f64(const double4 p, double xi, double yi, double zi,
+                                         double& sx, double& sy, double& sz) {
+    const double dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, kR2FloorF64)));
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double a = y * y;
+    const double g = fma(r2, a, -5.0 / 3.0);  // (r2 y^2 - 5/3)
+    const double w = (a * y) * p.w * g;       // 1.5 q y^3 (r2 y^2 - 5/3) = -q r^-3
+    sx = fma(w, dx, sx);
+    sy = fma(w, dy, sy);
+    sz = fma(w, dz, sz);
+}
+
+// Target-side float-float position.
+struct FF {
+    float xh, yh, zh, xl, yl, zl;
+};
+
+// One FP32 pair term on float-float positions; returns the three products.
+__device__ __forceinline__ void pair_f32_terms(const MixedSrc& q, const FF& t, float& tx,
+                                               float& ty, float& tz) {
+    const float dx = (q.xh - t.xh) + (q.xl - t.xl);
+    const float dy = (q.yh - t.yh) + (q.yl - t.yl);
+    const float dz = (q.zh - t.zh) + (q.zl - t.zl);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kR2FloorF32)));
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float w = (q.nq * y) * (y * y);  // -q r^-3
+    tx = w * dx;
+    ty = w * dy;
+    tz = w * dz;
+}
+
+__device__ __forceinline__ void pair_f32(const MixedSrc& q, const FF& t, float& sx, float& sy,
+                                         float& sz) {
+    const float dx = (q.xh - t.xh) + (q.xl - t.xl);
+    const float dy = (q.yh - t.yh) + (q.yl - t.yl);
+    const float dz = (q.zh - t.zh) + (q.zl - t.zl);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kR2FloorF32)));
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float w = (q.nq * y) * (y * y);
+    sx = fmaf(w, dx, sx);
+    sy = fmaf(w, dy, sy);
+    sz = fmaf(w, dz, sz);
+}
+
+// Kahan-compensated FP32 accumulation of one term.
+__device__ __forceinline__ void kahan_add(float term, float& s, float& c) {
+    const float y = term - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+__device__ __forceinline__ FF split_ff(double x, double y, double z) {
+    FF r;
+    const double xs = x * kMixedScale, ys = y * kMixedScale, zs = z * kMixedScale;
+    r.xh = (float)xs;
+    r.yh = (float)ys;
+    r.zh = (float)zs;
+    r.xl = (float)(xs - (double)r.xh);
+    r.yl = (float)(ys - (double)r.yh);
+    r.zl = (float)(zs - (double)r.zh);
+    return r;
+}
+
+__device__ __forceinline__ MixedSrc make_src(double x, double y, double z, double qe) {
+    const FF f = split_ff(x, y, z);
+    MixedSrc m;
+    m.xh = f.xh;
+    m.yh = f.yh;
+    m.zh = f.zh;
+    m.nq = (float)(-qe);
+    m.xl = f.xl;
+    m.yl = f.yl;
+    m.zl = f.zl;
+    m.pad = 0.0f;
+    return m;
+}
+
+// --------------------------------------------------------- first half-step
+
+__device__ __forceinline__ void half_step_drift(const TrapDev& T, double& x, double& y,
+                                                double& z, double& vx, double& vy, double& vz,
+                                                double ax, double ay, double az) {
+#pragma clang fp contract(off)
+    vx = T.f * vx;
+    vy = T.f * vy;
+    vz = T.f * vz;
+    vx = vx + T.h * ax;
+    vy = vy + T.h * ay;
+    vz = vz + T.h * az;
+    x = x + T.dt * vx;
+    y = y + T.dt * vy;
+    z = z + T.dt * vz;
+}
+
+__device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm, double x,
+                                           double y, double z, double Sx, double Sy, double Sz,
+                                           double& ax, double& ay, double& az) {
+#pragma clang fp contract(off)
+    const double c = cos(T.omega * t);
+    const double ex = T.a_rf * c * x + T.a_dc * x;
+    const double ey = -T.a_rf * c * y + T.a_dc * y;
+    const double ez = -2.0 * T.a_dc * z;
+    ax = qm * (kKeE * Sx + ex);
+    ay = qm * (kKeE * Sy + ey);
+    az = qm * (kKeE * Sz + ez);
+}
+
+__device__ __forceinline__ void end_kick(const TrapDev& T, double& vx, double& vy, double& vz,
+                                         double ax, double ay, double az) {
+#pragma clang fp contract(off)
+    vx = vx + T.h * ax;
+    vy = vy + T.h * ay;
+    vz = vz + T.h * az;
+    vx = T.f * vx;
+    vy = T.f * vy;
+    vz = T.f * vz;
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ __launch_bounds__(256) void k_drift(double4* __restrict__ src,
+                                               MixedSrc* __restrict__ srcm,
+                                               double* __restrict__ vx, double* __restrict__ vy,
+                                               double* __restrict__ vz,
+                                               const double* __restrict__ ax,
+                                               const double* __restrict__ ay,
+                                               const double* __restrict__ az,
+                                               const double* __restrict__ qe,
+                                               const TrapDev* __restrict__ traps, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const TrapDev T = traps[0];
+    double4 p = src[i];
+    double u = vx[i], v = vy[i], w = vz[i];
+    half_step_drift(T, p.x, p.y, p.z, u, v, w, ax[i], ay[i], az[i]);
+    src[i] = p;
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+    if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
+}
+
+__global__ __launch_bounds__(256) void k_pack_mixed(const double4* __restrict__ src,
+                                                    MixedSrc* __restrict__ srcm,
+                                                    const double* __restrict__ qe, int64_t n,
+                                                    int64_t n_pad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    if (i < n) {
+        const double4 p = src[i];
+        srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
+    } else {
+        srcm[i] = make_src(0.0, 0.0, 0.0, 0.0);
+    }
+}
+
+// FP64 pair field.  Block b of slice s covers targets [b*256*I, (b+1)*256*I),
+// lane t owning targets base + t + 256 k (k < I), and sources [s*jps, s*jps+jps)
+// clipped to n16 (entries beyond N carry zero charge).
+template <int I>
+__global__ __launch_bounds__(kPairBlock) void k_pair_f64(const double4* __restrict__ src,
+                                                         int64_t n, int n16, int jps,
+                                                         int64_t n_pad,
+                                                         double* __restrict__ part,
+                                                         int64_t* __restrict__ counter) {
+    const int64_t base = (int64_t)blockIdx.x * (kPairBlock * I) + threadIdx.x;
+    const int s = blockIdx.y;
+    const int jb = s * jps;
+    const int je = min(jb + jps, n16);
+    double xi[I], yi[I], zi[I], sx[I], sy[I], sz[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const double4 p = src[base + kPairBlock * k];
+        xi[k] = p.x;
+        yi[k] = p.y;
+        zi[k] = p.z;
+        sx[k] = 0.0;
+        sy[k] = 0.0;
+        sz[k] = 0.0;
+    }
+    for (int j = jb; j < je; j += 4) {
+        const double4 p0 = src[j], p1 = src[j + 1], p2 = src[j + 2], p3 = src[j + 3];
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            pair_f64(p0, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+            pair_f64(p1, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+            pair_f64(p2, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+            pair_f64(p3, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+        }
+    }
+    double* px = part + (int64_t)(3 * s) * n_pad;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const int64_t i = base + kPairBlock * k;
+        if (i < n) {
+            px[i] = sx[k];
+            px[n_pad + i] = sy[k];
+            px[2 * n_pad + i] = sz[k];
+        }
+    }
+    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
+}
+
+// FP32 pair field on float-float positions.  KAHAN = false: FP32 sums over
+// runs of L sources, each run added to FP64 sums.  KAHAN = true: compensated
+// FP32 sums over the whole slice.
+template <int I, int L, bool KAHAN>
+__global__ __launch_bounds__(kPairBlock) void k_pair_mixed(const MixedSrc* __restrict__ srcm,
+                                                           int64_t n, int n16, int jps,
+                                                           int64_t n_pad,
+                                                           double* __restrict__ part,
+                                                           int64_t* __restrict__ counter) {
+    const int64_t base = (int64_t)blockIdx.x * (kPairBlock * I) + threadIdx.x;
+    const int s = blockIdx.y;
+    const int jb = s * jps;
+    const int je = min(jb + jps, n16);
+    FF t[I];
+    double sx[I], sy[I], sz[I];
+    float kx[I], ky[I], kz[I], cx[I], cy[I], cz[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const MixedSrc m = srcm[base + kPairBlock * k];
+        t[k].xh = m.xh;
+        t[k].yh = m.yh;
+        t[k].zh = m.zh;
+        t[k].xl = m.xl;
+        t[k].yl = m.yl;
+        t[k].zl = m.zl;
+        sx[k] = sy[k] = sz[k] = 0.0;
+        kx[k] = ky[k] = kz[k] = 0.0f;
+        cx[k] = cy[k] = cz[k] = 0.0f;
+    }
+    for (int j = jb; j < je; j += L) {
+        if (KAHAN) {
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const MixedSrc q = srcm[j + u];
+#pragma unroll
+                for (int k = 0; k < I; ++k) {
+                    float tx, ty, tz;
+                    pair_f32_terms(q, t[k], tx, ty, tz);
+                    kahan_add(tx, kx[k], cx[k]);
+                    kahan_add(ty, ky[k], cy[k]);
+                    kahan_add(tz, kz[k], cz[k]);
+                }
+            }
+        } else {
+            float fx[I], fy[I], fz[I];
+#pragma unroll
+            for (int k = 0; k < I; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const MixedSrc q = srcm[j + u];
+#pragma unroll
+                for (int k = 0; k < I; ++k) pair_f32(q, t[k], fx[k], fy[k], fz[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                sx[k] += (double)fx[k];
+                sy[k] += (double)fy[k];
+                sz[k] += (double)fz[k];
+            }
+        }
+    }
+    double* px = part + (int64_t)(3 * s) * n_pad;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const int64_t i = base + kPairBlock * k;
+        if (KAHAN) {
+            sx[k] = (double)kx[k] - (double)cx[k];
+            sy[k] = (double)ky[k] - (double)cy[k];
+            sz[k] = (double)kz[k] - (double)cz[k];
+        }
+        if (i < n) {
+            px[i] = sx[k];
+            px[n_pad + i] = sy[k];
+            px[2 * n_pad + i] = sz[k];
+        }
+    }
+    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
+}
+
+// Per-ion epilogue of a step (or a plain force evaluation): reduce the slice
+// partials in slice order, add the trap field, then kick / damp / drift.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
+                                                MixedSrc* __restrict__ srcm,
+                                                double* __restrict__ vx, double* __restrict__ vy,
+                                                double* __restrict__ vz, double* __restrict__ ax,
+                                                double* __restrict__ ay, double* __restrict__ az,
+                                                const double* __restrict__ qm,
+                                                const double* __restrict__ qe,
+                                                const double* __restrict__ part, int j_split,
+                                                int64_t n, int64_t n_pad, double field_scale,
+                                                const TrapDev* __restrict__ traps,
+                                                const int64_t* __restrict__ counter) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    for (int s = 0; s < j_split; ++s) {
+        const double* px = part + (int64_t)(3 * s) * n_pad;
+        Sx += px[i];
+        Sy += px[n_pad + i];
+        Sz += px[2 * n_pad + i];
+    }
+    Sx *= field_scale;
+    Sy *= field_scale;
+    Sz *= field_scale;
+    const TrapDev T = traps[0];
+    const double t = counter ? T.t_start + (double)(*counter) * T.dt : T.t_start;
+    double4 p = src[i];
+    double a_x, a_y, a_z;
+    trap_accel(T, t, qm[i], p.x, p.y, p.z, Sx, Sy, Sz, a_x, a_y, a_z);
+    ax[i] = a_x;
+    ay[i] = a_y;
+    az[i] = a_z;
+    if (MODE == kModeAccel) return;
+    double u = vx[i], v = vy[i], w = vz[i];
+    end_kick(T, u, v, w, a_x, a_y, a_z);
+    if (MODE == kModeEndDrift) {
+        half_step_drift(T, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
+        src[i] = p;
+        if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
+    }
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+}
+
+__global__ void k_counter_add(int64_t* counter, int64_t k) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter += k;
+}
+
+// Coulomb potential sum_{j != i, same trap} q_j / r_ij per ion (1/m), FP64.
+__global__ __launch_bounds__(256) void k_coulomb_potential(const double4* __restrict__ src,
+                                                           const double* __restrict__ qe,
+                                                           const int32_t* __restrict__ trap_of,
+                                                           const int64_t* __restrict__ offsets,
+                                                           int64_t n, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int tr = trap_of[i];
+    const int64_t jb = offsets[tr], je = offsets[tr + 1];
+    const double4 p = src[i];
+    double acc = 0.0;
+    for (int64_t j = jb; j < je; ++j) {
+        if (j == i) continue;
+        const double4 q = src[j];
+        const double dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0) continue;
+        acc += qe[j] / sqrt(r2);
+    }
+    out[i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_check_finite(const double4* __restrict__ src,
+                                                      const double* __restrict__ vx,
+                                                      const double* __restrict__ vy,
+                                                      const double* __restrict__ vz, int64_t n,
+                                                      int32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 p = src[i];
+    const bool ok = isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(vx[i]) &&
+                    isfinite(vy[i]) && isfinite(vz[i]);
+    if (!ok) atomicAdd(flags, 1);
+}
+
+// ------------------------------------------------------------ batched traps
+//
+// One workgroup per trap, launched largest trap first so that the hardware
+// dispatcher hands the long traps out before the short ones.  Threads form
+// (i_slot, j_part) pairs: IS = min(round_up(m, 64), BLOCK) target slots and
+// JP = BLOCK / IS source parts.  Slot owners (j_part 0) keep their ions' state
+// in registers for the whole launch; the trap's source stream lives in LDS.
+
+constexpr int kMaxTrap = 1024;
+
+template <int PREC>
+struct BatchSrc;
+template <>
+struct BatchSrc<0> {
+    using T = double4;
+};
+template <>
+struct BatchSrc<1> {
+    using T = MixedSrc;
+};
+template <>
+struct BatchSrc<2> {
+    using T = MixedSrc;
+};
+
+template <int PREC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
+                                                 double* __restrict__ vx,
+                                                 double* __restrict__ vy,
+                                                 double* __restrict__ vz,
+                                                 double* __restrict__ ax,
+                                                 double* __restrict__ ay,
+                                                 double* __restrict__ az,
+                                                 const double* __restrict__ qm,
+                                                 const double* __restrict__ qe,
+                                                 const TrapDev* __restrict__ traps,
+                                                 const int64_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ order,
+                                                 const int64_t* __restrict__ counter,
+                                                 int nsteps, int accel_only) {
+    constexpr int KMAX = kMaxTrap / BLOCK;  // ions per owner thread at most
+    using S = typename BatchSrc<PREC>::T;
+    __shared__ S lds[kMaxTrap];
+    __shared__ double red[3][BLOCK];
+
+    const int tr = order[blockIdx.x];
+    const int64_t o = offsets[tr];
+    const int m = (int)(offsets[tr + 1] - o);
+    const int m16 = (m + 15) & ~15;
+    const int IS = min((m + 63) & ~63, BLOCK);
+    const int JP = BLOCK / IS;
+    const int tid = threadIdx.x;
+    const int slot = tid % IS;
+    const int jpart = tid / IS;
+    const bool active = jpart < JP;
+    const bool owner = jpart == 0;
+    const int jlen = ((m16 / JP) + 15) & ~15;
+    const int jb = min(jpart * jlen, m16);
+    const int je = min(jb + jlen, m16);
+    const TrapDev T = traps[tr];
+    const int64_t k0 = *counter;
+
+    double x[KMAX], y[KMAX], z[KMAX], u[KMAX], v[KMAX], w[KMAX], a0[KMAX], a1[KMAX], a2[KMAX];
+    double q_m[KMAX], q_e[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int il = slot + IS * k;
+        if (owner && il < m) {
+            const double4 p = src[o + il];
+            x[k] = p.x;
+            y[k] = p.y;
+            z[k] = p.z;
+            u[k] = vx[o + il];
+            v[k] = vy[o + il];
+            w[k] = vz[o + il];
+            a0[k] = ax[o + il];
+            a1[k] = ay[o + il];
+            a2[k] = az[o + il];
+            q_m[k] = qm[o + il];
+            q_e[k] = qe[o + il];
+        } else {
+            x[k] = y[k] = z[k] = u[k] = v[k] = w[k] = a0[k] = a1[k] = a2[k] = 0.0;
+            q_m[k] = q_e[k] = 0.0;
+        }
+    }
+    // zero-charge padding of the source stream
+    for (int il = m + tid; il < m16; il += BLOCK) {
+        if constexpr (PREC == 0) {
+            lds[il] = make_double4(0.0, 0.0, 0.0, 0.0);
+        } else {
+            lds[il] = make_src(0.0, 0.0, 0.0, 0.0);
+        }
+    }
+
+    const int total = accel_only ? 1 : nsteps;
+    for (int step = 0; step < total; ++step) {
+        // first half of the step; positions into the LDS source stream
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int il = slot + IS * k;
+            if (owner && il < m) {
+                if (!accel_only)
+                    half_step_drift(T, x[k], y[k], z[k], u[k], v[k], w[k], a0[k], a1[k], a2[k]);
+                if constexpr (PREC == 0) {
+                    lds[il] = make_double4(x[k], y[k], z[k], 1.5 * q_e[k]);
+                } else {
+                    lds[il] = make_src(x[k], y[k], z[k], q_e[k]);
+                }
+            }
+        }
+        __syncthreads();
+        // pair field of this thread's targets over its source part
+        double Sx[KMAX], Sy[KMAX], Sz[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int il = slot + IS * k;
+            Sx[k] = Sy[k] = Sz[k] = 0.0;
+            if (!active || il >= m) continue;
+            if constexpr (PREC == 0) {
+                const double4 me = lds[il];
+                double sx = 0.0, sy = 0.0, sz = 0.0;
+                for (int j = jb; j < je; j += 4) {
+                    pair_f64(lds[j], me.x, me.y, me.z, sx, sy, sz);
+                    pair_f64(lds[j + 1], me.x, me.y, me.z, sx, sy, sz);
+                    pair_f64(lds[j + 2], me.x, me.y, me.z, sx, sy, sz);
+                    pair_f64(lds[j + 3], me.x, me.y, me.z, sx, sy, sz);
+                }
+                Sx[k] = sx;
+                Sy[k] = sy;
+                Sz[k] = sz;
+            } else {
+                const MixedSrc* LM = lds;
+                const MixedSrc me = LM[il];
+                FF t;
+                t.xh = me.xh;
+                t.yh = me.yh;
+                t.zh = me.zh;
+                t.xl = me.xl;
+                t.yl = me.yl;
+                t.zl = me.zl;
+                if constexpr (PREC == 1) {
+                    double sx = 0.0, sy = 0.0, sz = 0.0;
+                    for (int j = jb; j < je; j += 8) {
+                        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+#pragma unroll
+                        for (int uu = 0; uu < 8; ++uu) pair_f32(LM[j + uu], t, fx, fy, fz);
+                        sx += (double)fx;
+                        sy += (double)fy;
+                        sz += (double)fz;
+                    }
+                    Sx[k] = sx * kMixedFieldScale;
+                    Sy[k] = sy * kMixedFieldScale;
+                    Sz[k] = sz * kMixedFieldScale;
+                } else {
+                    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+                    for (int j = jb; j < je; ++j) {
+                        float tx, ty, tz;
+                        pair_f32_terms(LM[j], t, tx, ty, tz);
+                        kahan_add(tx, sx, cx);
+                        kahan_add(ty, sy, cy);
+                        kahan_add(tz, sz, cz);
+                    }
+                    Sx[k] = ((double)sx - (double)cx) * kMixedFieldScale;
+                    Sy[k] = ((double)sy - (double)cy) * kMixedFieldScale;
+                    Sz[k] = ((double)sz - (double)cz) * kMixedFieldScale;
+                }
+            }
+        }
+        if (JP > 1) {
+            // deterministic reduction over source parts: owners add parts in order
+            // (only KMAX == 1 can have JP > 1, since JP > 1 needs m <= BLOCK / 2)
+            if (active && jpart > 0) {
+                red[0][tid] = Sx[0];
+                red[1][tid] = Sy[0];
+                red[2][tid] = Sz[0];
+            }
+            __syncthreads();
+            if (owner) {
+                for (int p = 1; p < JP; ++p) {
+                    Sx[0] += red[0][slot + p * IS];
+                    Sy[0] += red[1][slot + p * IS];
+                    Sz[0] += red[2][slot + p * IS];
+                }
+            }
+        }
+        __syncthreads();
+        const double t = T.t_start + (double)(k0 + step + (accel_only ? 0 : 1)) * T.dt;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int il = slot + IS * k;
+            if (owner && il < m) {
+                trap_accel(T, t, q_m[k], x[k], y[k], z[k], Sx[k], Sy[k], Sz[k], a0[k], a1[k],
+                           a2[k]);
+                if (!accel_only) end_kick(T, u[k], v[k], w[k], a0[k], a1[k], a2[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int il = slot + IS * k;
+        if (owner && il < m) {
+            src[o + il] = make_double4(x[k], y[k], z[k], 1.5 * q_e[k]);
+            vx[o + il] = u[k];
+            vy[o + il] = v[k];
+            vz[o + il] = w[k];
+            ax[o + il] = a0[k];
+            ay[o + il] = a1[k];
+            az[o + il] = a2[k];
+        }
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int I>
+hipError_t pair_f64_launch(const DevState& s, const LaunchShape& ls, int64_t* ctr,
+                           hipStream_t st) {
+    const int n16 = (int)((s.n + 15) & ~int64_t(15));
+    dim3 grid(blocks_for(s.n, kPairBlock * I), ls.j_split);
+    k_pair_f64<I><<<grid, kPairBlock, 0, st>>>(s.src, s.n, n16, ls.jps, s.n_pad, s.part, ctr);
+    return hipGetLastError();
+}
+
+template <int I, int L, bool KAHAN>
+hipError_t pair_mixed_launch(const DevState& s, const LaunchShape& ls, int64_t* ctr,
+                             hipStream_t st) {
+    const int n16 = (int)((s.n + 15) & ~int64_t(15));
+    dim3 grid(blocks_for(s.n, kPairBlock * I), ls.j_split);
+    k_pair_mixed<I, L, KAHAN>
+        <<<grid, kPairBlock, 0, st>>>(s.srcm, s.n, n16, ls.jps, s.n_pad, s.part, ctr);
+    return hipGetLastError();
+}
+
+template <int I>
+hipError_t pair_mixed_dispatch_l(const DevState& s, const LaunchShape& ls, int64_t* ctr,
+                                 hipStream_t st) {
+    switch (ls.flush_len) {
+        case 4: return pair_mixed_launch<I, 4, false>(s, ls, ctr, st);
+        case 16: return pair_mixed_launch<I, 16, false>(s, ls, ctr, st);
+        default: return pair_mixed_launch<I, 8, false>(s, ls, ctr, st);
+    }
+}
+
+template <int PREC, int BLOCK>
+hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only,
+                        hipStream_t st) {
+    k_batch<PREC, BLOCK><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
+                                                    s.qm, s.qe, s.traps, s.offsets, s.order,
+                                                    s.counter, nsteps, accel_only);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps, int accel_only,
+                          hipStream_t st) {
+    switch (block) {
+        case 512: return batch_launch<PREC, 512>(s, n_traps, nsteps, accel_only, st);
+        case 1024: return batch_launch<PREC, 1024>(s, n_traps, nsteps, accel_only, st);
+        default: return batch_launch<PREC, 256>(s, n_traps, nsteps, accel_only, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_drift(const DevState& s, hipStream_t st) {
+    k_drift<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+                                                  s.az, s.qe, s.traps, s.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_mixed(const DevState& s, hipStream_t st) {
+    if (!s.srcm) return hipSuccess;
+    k_pack_mixed<<<blocks_for(s.n_pad, 256), 256, 0, st>>>(s.src, s.srcm, s.qe, s.n, s.n_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, bool count_step,
+                       hipStream_t st) {
+    int64_t* ctr = count_step ? s.counter : nullptr;
+    if (precision == 0) {
+        switch (ls.i_per_lane) {
+            case 1: return pair_f64_launch<1>(s, ls, ctr, st);
+            case 4: return pair_f64_launch<4>(s, ls, ctr, st);
+            default: return pair_f64_launch<2>(s, ls, ctr, st);
+        }
+    }
+    if (precision == 2) {
+        switch (ls.i_per_lane) {
+            case 1: return pair_mixed_launch<1, 8, true>(s, ls, ctr, st);
+            case 4: return pair_mixed_launch<4, 8, true>(s, ls, ctr, st);
+            default: return pair_mixed_launch<2, 8, true>(s, ls, ctr, st);
+        }
+    }
+    switch (ls.i_per_lane) {
+        case 1: return pair_mixed_dispatch_l<1>(s, ls, ctr, st);
+        case 4: return pair_mixed_dispatch_l<4>(s, ls, ctr, st);
+        default: return pair_mixed_dispatch_l<2>(s, ls, ctr, st);
+    }
+}
+
+hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls, int mode,
+                         bool use_counter, hipStream_t st) {
+    const double scale = precision == 0 ? 1.0 : kMixedFieldScale;
+    const int64_t* ctr = use_counter ? s.counter : nullptr;
+    const unsigned g = blocks_for(s.n, 256);
+    MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
+    switch (mode) {
+        case kModeAccel:
+            k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+                                                    s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
+                                                    s.n_pad, scale, s.traps, ctr);
+            break;
+        case kModeEnd:
+            k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+                                                  s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
+                                                  s.n_pad, scale, s.traps, ctr);
+            break;
+        default:
+            k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
+                                                       s.ay, s.az, s.qm, s.qe, s.part,
+                                                       ls.j_split, s.n, s.n_pad, scale, s.traps,
+                                                       ctr);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_trap,
+                        const LaunchShape& ls, int nsteps, int, hipStream_t st) {
+    (void)max_trap;
+    switch (precision) {
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, st);
+    }
+}
+
+hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int max_trap,
+                              const LaunchShape& ls, hipStream_t st) {
+    (void)max_trap;
+    switch (precision) {
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, st);
+    }
+}
+
+hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st) {
+    k_counter_add<<<1, 64, 0, st>>>(s.counter, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_coulomb_potential(const DevState& s, int, hipStream_t st) {
+    k_coulomb_potential<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.qe, s.trap_of, s.offsets,
+                                                              s.n, s.scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const DevState& s, hipStream_t st) {
+    k_check_finite<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.n, s.flags);
+    return hipGetLastError();
+}
+
+}  // namespace lion

@@ -1,0 +1,317 @@
+"""ctypes binding of ``liblion.so`` (the C ABI declared in ``include/lion.h``).
+
+Functions keep the C names and only marshal arguments: numpy arrays become
+double pointers, torch supplies the device workspace and the HIP stream.  Every
+step of the simulation runs in the library's HIP kernels; if the library is
+missing this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblion.so")
+
+LION_FP64 = 0
+LION_MIXED_F64ACC = 1
+LION_MIXED_KAHAN = 2
+PRECISIONS = {"fp64": LION_FP64, "mixed": LION_MIXED_F64ACC, "mixed_f64acc": LION_MIXED_F64ACC,
+              "mixed_kahan": LION_MIXED_KAHAN}
+
+LION_OK = 0
+LION_ERR_ARG = -1
+LION_ERR_STATE = -2
+LION_ERR_HIP = -3
+LION_ERR_WORKSPACE = -4
+LION_ERR_NONFINITE = -5
+LION_ERR_UNSUPPORTED = -6
+
+
+class LionError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lion error {code}: {msg}")
+        self.code = code
+
+
+class KernelConfig(ctypes.Structure):
+    _fields_ = [("i_per_lane", ctypes.c_int32), ("j_split", ctypes.c_int32),
+                ("chunk_steps", ctypes.c_int32), ("flush_len", ctypes.c_int32),
+                ("batch_block", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1907_10514_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, dp, i32, i64, sz = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                            ctypes.c_int64, ctypes.c_size_t)
+    d = ctypes.c_double
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.lion_workspace_bytes.argtypes = [i64, i32, ctypes.c_int]
+    lib.lion_workspace_bytes.restype = sz
+    lib.lion_create.argtypes = [pp, i64, dp, dp, ctypes.c_int, vp, sz, vp]
+    lib.lion_create_batch.argtypes = [pp, i32, ctypes.POINTER(ctypes.c_int64), dp, dp,
+                                      ctypes.c_int, vp, sz, vp]
+    lib.lion_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, d]
+    lib.lion_set_trap.argtypes = [vp, i32, d, d, d, d, d, d]
+    lib.lion_set_damping.argtypes = [vp, i32, d]
+    lib.lion_step.argtypes = [vp, i64, d]
+    lib.lion_step_batch.argtypes = [vp, i64, dp]
+    lib.lion_get_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    lib.lion_compute_accel.argtypes = [vp, dp, dp, dp]
+    lib.lion_get_energy.argtypes = [vp, dp, dp, dp]
+    lib.lion_check_finite.argtypes = [vp]
+    lib.lion_last_error.argtypes = [vp]
+    lib.lion_last_error.restype = ctypes.c_char_p
+    lib.lion_destroy.argtypes = [vp]
+    lib.lion_destroy.restype = None
+    lib.lion_set_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
+    lib.lion_get_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
+    lib.lion_time_pair_kernel.argtypes = [vp, i32, dp]
+    lib.lion_time_batch_kernel.argtypes = [vp, i32, i32, d, dp]
+    lib.lion_mathieu_to_voltages.argtypes = [d, d, d, d, d, d, d, d, dp, dp]
+    lib.lion_constants.argtypes = [dp, dp, dp]
+    lib.lion_constants.restype = None
+    for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
+                 "lion_set_damping", "lion_step", "lion_step_batch", "lion_get_state",
+                 "lion_compute_accel", "lion_get_energy", "lion_check_finite",
+                 "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
+                 "lion_time_pair_kernel", "lion_time_batch_kernel"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc: int, handle=None):
+    if rc != LION_OK:
+        msg = load().lion_last_error(handle)
+        raise LionError(rc, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------------ raw calls
+
+def lion_workspace_bytes(n_total: int, n_traps: int, precision: int) -> int:
+    return int(load().lion_workspace_bytes(int(n_total), int(n_traps), int(precision)))
+
+
+def lion_create(n, masses, charges, precision, workspace_ptr, ws_bytes, stream_ptr):
+    h = ctypes.c_void_p()
+    m, q = _f64(masses), _f64(charges)
+    _check(load().lion_create(ctypes.byref(h), int(n), _dp(m), _dp(q), int(precision),
+                              ctypes.c_void_p(workspace_ptr), int(ws_bytes),
+                              ctypes.c_void_p(stream_ptr)))
+    return h
+
+
+def lion_create_batch(n_per_trap, masses, charges, precision, workspace_ptr, ws_bytes,
+                      stream_ptr):
+    h = ctypes.c_void_p()
+    npt = np.ascontiguousarray(n_per_trap, dtype=np.int64)
+    m, q = _f64(masses), _f64(charges)
+    _check(load().lion_create_batch(ctypes.byref(h), int(npt.size),
+                                    npt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(m),
+                                    _dp(q), int(precision), ctypes.c_void_p(workspace_ptr),
+                                    int(ws_bytes), ctypes.c_void_p(stream_ptr)))
+    return h
+
+
+def lion_set_state(h, x, y, z, vx, vy, vz, t=0.0):
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz)]
+    _check(load().lion_set_state(h, *[_dp(a) for a in arrs], float(t)), h)
+
+
+def lion_set_trap(h, trap, V_rf, Omega, U_dc, r0, z0, kappa):
+    _check(load().lion_set_trap(h, int(trap), float(V_rf), float(Omega), float(U_dc), float(r0),
+                                float(z0), float(kappa)), h)
+
+
+def lion_set_damping(h, trap, gamma):
+    _check(load().lion_set_damping(h, int(trap), float(gamma)), h)
+
+
+def lion_step(h, nsteps, dt):
+    _check(load().lion_step(h, int(nsteps), float(dt)), h)
+
+
+def lion_step_batch(h, nsteps, dts):
+    d = _f64(dts)
+    _check(load().lion_step_batch(h, int(nsteps), _dp(d)), h)
+
+
+def lion_get_state(h, n):
+    out = [np.empty(n) for _ in range(6)]
+    t = ctypes.c_double()
+    _check(load().lion_get_state(h, *[_dp(a) for a in out], ctypes.byref(t)), h)
+    return dict(zip(("x", "y", "z", "vx", "vy", "vz"), out)), t.value
+
+
+def lion_compute_accel(h, n):
+    out = [np.empty(n) for _ in range(3)]
+    _check(load().lion_compute_accel(h, *[_dp(a) for a in out]), h)
+    return tuple(out)
+
+
+def lion_get_energy(h):
+    k, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().lion_get_energy(h, ctypes.byref(k), ctypes.byref(c), ctypes.byref(d)), h)
+    return k.value, c.value, d.value
+
+
+def lion_check_finite(h) -> int:
+    return int(load().lion_check_finite(h))
+
+
+def lion_last_error(h) -> str:
+    m = load().lion_last_error(h)
+    return m.decode() if m else ""
+
+
+def lion_destroy(h):
+    load().lion_destroy(h)
+
+
+def lion_set_kernel_config(h, **kw):
+    c = KernelConfig(**{k: int(v) for k, v in kw.items()})
+    _check(load().lion_set_kernel_config(h, ctypes.byref(c)), h)
+
+
+def lion_get_kernel_config(h) -> dict:
+    c = KernelConfig()
+    _check(load().lion_get_kernel_config(h, ctypes.byref(c)), h)
+    return c.as_dict()
+
+
+def lion_time_pair_kernel(h, reps) -> float:
+    ms = ctypes.c_double()
+    _check(load().lion_time_pair_kernel(h, int(reps), ctypes.byref(ms)), h)
+    return ms.value
+
+
+def lion_time_batch_kernel(h, reps, nsteps, dt) -> float:
+    ms = ctypes.c_double()
+    _check(load().lion_time_batch_kernel(h, int(reps), int(nsteps), float(dt), ctypes.byref(ms)),
+           h)
+    return ms.value
+
+
+def lion_mathieu_to_voltages(q_x, a_x, M, Q, Omega, r0, z0, kappa):
+    V0, U0 = ctypes.c_double(), ctypes.c_double()
+    _check(load().lion_mathieu_to_voltages(float(q_x), float(a_x), float(M), float(Q),
+                                           float(Omega), float(r0), float(z0), float(kappa),
+                                           ctypes.byref(V0), ctypes.byref(U0)))
+    return V0.value, U0.value
+
+
+def lion_constants():
+    e, eps0, amu = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    load().lion_constants(ctypes.byref(e), ctypes.byref(eps0), ctypes.byref(amu))
+    return e.value, eps0.value, amu.value
+
+
+# ------------------------------------------------------------ object wrapper
+
+class Simulation:
+    """One trap (or a batch of traps) on one GPU.  torch provides the device
+    workspace (a uint8 tensor kept alive by this object) and the stream."""
+
+    def __init__(self, masses, charges, precision="fp64", n_per_trap=None, device=None,
+                 stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the engine runs only on the GPU")
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        m, q = _f64(masses), _f64(charges)
+        self.n = int(m.size)
+        self.batched = n_per_trap is not None
+        self.n_per_trap = (np.ascontiguousarray(n_per_trap, dtype=np.int64) if self.batched
+                           else np.array([self.n], dtype=np.int64))
+        self.n_traps = int(self.n_per_trap.size)
+        ws = lion_workspace_bytes(self.n, self.n_traps, self.precision)
+        if ws == 0:
+            raise LionError(LION_ERR_ARG, "invalid sizes for workspace")
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+            self.stream = stream or torch.cuda.current_stream(self.device)
+            base = self._ws.data_ptr()
+            ptr = (base + 255) // 256 * 256
+            sptr = self.stream.cuda_stream
+            if self.batched:
+                self.h = lion_create_batch(self.n_per_trap, m, q, self.precision, ptr, ws, sptr)
+            else:
+                self.h = lion_create(self.n, m, q, self.precision, ptr, ws, sptr)
+        self.ws_bytes = ws
+
+    def close(self):
+        if getattr(self, "h", None):
+            lion_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, x, y, z, vx, vy, vz, t=0.0):
+        lion_set_state(self.h, x, y, z, vx, vy, vz, t)
+
+    def set_trap(self, V_rf, Omega, U_dc, r0, z0, kappa, trap=-1):
+        lion_set_trap(self.h, trap, V_rf, Omega, U_dc, r0, z0, kappa)
+
+    def set_damping(self, gamma, trap=-1):
+        lion_set_damping(self.h, trap, gamma)
+
+    def step(self, nsteps, dt):
+        if np.ndim(dt):
+            lion_step_batch(self.h, nsteps, dt)
+        else:
+            lion_step(self.h, nsteps, dt)
+
+    def get_state(self):
+        return lion_get_state(self.h, self.n)
+
+    def compute_accel(self):
+        return lion_compute_accel(self.h, self.n)
+
+    def energy(self):
+        return lion_get_energy(self.h)
+
+    def check_finite(self) -> int:
+        return lion_check_finite(self.h)
+
+    def time_pair_kernel(self, reps: int) -> float:
+        return lion_time_pair_kernel(self.h, reps)
+
+    def time_batch_kernel(self, reps: int, nsteps: int, dt: float) -> float:
+        return lion_time_batch_kernel(self.h, reps, nsteps, dt)
+
+    def config(self) -> dict:
+        return lion_get_kernel_config(self.h)
+
+    def set_config(self, **kw):
+        lion_set_kernel_config(self.h, **kw)

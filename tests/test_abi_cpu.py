@@ -1,0 +1,139 @@
+"""The C-ABI library on the host: it loads, exports every declared symbol, and its
+host-only calls (sizes, constants, argument checks that return before any device
+work) behave as documented.  No GPU compute here."""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import lion_inputs as li
+from paper_1907_10514_amd import lion
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lion.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lion_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lion.load()
+    names = _declared_functions()
+    assert "lion_step" in names and "lion_create" in names and len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_constants_match_inputs_and_oracle(oracle_mod):
+    e, eps0, amu = lion.lion_constants()
+    assert e == li.E_CHARGE == oracle_mod.E_CHARGE
+    assert amu == li.AMU == oracle_mod.AMU
+    assert eps0 == oracle_mod.EPS0
+
+
+def test_mathieu_helper_matches_oracle_and_inverts(oracle_mod):
+    """eq. (Mathieuaq): the library's voltages agree with the oracle's, and the
+    oracle's forward map returns the requested (q, a)."""
+    M, Q = 40 * li.AMU, li.E_CHARGE
+    for q, a in [(0.3, -0.001), (0.2, -0.001), (0.6, -0.01), (0.1, 0.0)]:
+        V0, U0 = lion.lion_mathieu_to_voltages(q, a, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
+        V0o, U0o = oracle_mod.voltages_for(q, a, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
+        assert V0 == pytest.approx(V0o, rel=1e-15) and U0 == pytest.approx(U0o, rel=1e-15, abs=0)
+        q2, a2 = oracle_mod.mathieu_coefficients(V0, U0, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
+        assert q2 == pytest.approx(q, rel=1e-14) and a2 == pytest.approx(a, rel=1e-14, abs=1e-18)
+    V0, U0 = lion.lion_mathieu_to_voltages(0.3, -0.001, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
+    assert V0 == pytest.approx(9.097272, abs=1e-6) and U0 == pytest.approx(0.242594, abs=1e-6)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(M=0.0), dict(Q=0.0), dict(Omega=-1.0), dict(r0=0.0), dict(z0=-1.0),
+    dict(kappa=0.0), dict(q_x=math.nan)])
+def test_mathieu_helper_rejects_bad_input(bad):
+    args = dict(q_x=0.3, a_x=-0.001, M=40 * li.AMU, Q=li.E_CHARGE, Omega=li.OMEGA, r0=li.R0,
+                z0=li.Z0, kappa=li.KAPPA)
+    args.update(bad)
+    with pytest.raises(lion.LionError) as ei:
+        lion.lion_mathieu_to_voltages(**args)
+    assert ei.value.code == lion.LION_ERR_ARG
+
+
+def test_workspace_sizes():
+    f = lion.lion_workspace_bytes
+    assert f(0, 1, 0) == 0 and f(10, 0, 0) == 0 and f(10, 1, 3) == 0 and f(10, 1, -1) == 0
+    for n in (1, 7, 1024, 1025, 16384, 65536):
+        a, b = f(n, 1, 0), f(n, 1, 1)
+        assert a > 0 and b > a  # the FP32 source stream comes on top
+        assert a % 256 == 0
+    # larger clouds need more memory; batches hold no partial-sum slices
+    assert f(16384, 1, 0) > f(1024, 1, 0)
+    assert f(131584, 512, 1) < f(131584, 1, 1)
+    # partial sums stay bounded for very large N
+    assert f(1 << 22, 1, 0) < 3 * 2 ** 30
+
+
+def _create(n, masses=None, charges=None, precision=0, ws=None, ws_bytes=None):
+    lib = lion.load()
+    h = ctypes.c_void_p()
+    m = np.full(n, 40 * li.AMU) if masses is None else np.asarray(masses, dtype=np.float64)
+    q = np.full(n, li.E_CHARGE) if charges is None else np.asarray(charges, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.lion_create(ctypes.byref(h), n, m.ctypes.data_as(dp), q.ctypes.data_as(dp),
+                         precision, ctypes.c_void_p(ws), ws_bytes or 0, None)
+    return rc, h
+
+
+@pytest.mark.parametrize("case,code", [
+    (dict(n=0), lion.LION_ERR_ARG),
+    (dict(n=4, masses=[1.0, 0.0, 1.0, 1.0]), lion.LION_ERR_ARG),
+    (dict(n=3, masses=[1.0, math.nan, 1.0]), lion.LION_ERR_ARG),
+    (dict(n=3, charges=[1.0, math.inf, 1.0]), lion.LION_ERR_ARG),
+    (dict(n=3, precision=7), lion.LION_ERR_ARG),
+    (dict(n=3), lion.LION_ERR_WORKSPACE),                                  # NULL workspace
+    (dict(n=3, ws=0x1000 + 8, ws_bytes=1 << 30), lion.LION_ERR_WORKSPACE),  # misaligned
+    (dict(n=3, ws=0x1000, ws_bytes=64), lion.LION_ERR_WORKSPACE),           # too small
+])
+def test_create_rejects_bad_arguments_before_device_work(case, code):
+    rc, h = _create(**case)
+    assert rc == code
+    assert not h.value
+    msg = lion.load().lion_last_error(None).decode()
+    assert msg  # the failed create leaves a message
+
+
+def test_batch_create_rejects_oversized_trap():
+    lib = lion.load()
+    h = ctypes.c_void_p()
+    npt = np.array([4, 2000], dtype=np.int64)
+    m = np.full(2004, 40 * li.AMU)
+    q = np.full(2004, li.E_CHARGE)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.lion_create_batch(ctypes.byref(h), 2, npt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               m.ctypes.data_as(dp), q.ctypes.data_as(dp), 1, None, 0, None)
+    assert rc == lion.LION_ERR_ARG
+    assert "1..1024" in lion.load().lion_last_error(None).decode()
+
+
+def test_null_handle_calls_are_rejected():
+    lib = lion.load()
+    assert lib.lion_step(None, 1, 1e-9) == lion.LION_ERR_ARG
+    assert lib.lion_set_damping(None, -1, 1.0) == lion.LION_ERR_ARG
+    assert lib.lion_check_finite(None) == lion.LION_ERR_ARG
+    lib.lion_destroy(None)  # no-op
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = lion._lib
+    lion._lib = None
+    try:
+        with pytest.raises(RuntimeError):
+            lion.load(str(tmp_path / "missing.so"))
+    finally:
+        lion._lib = saved

@@ -119,6 +119,18 @@ def test_rotation_and_relabelling(oracle_mod):
     assert np.max(err) < 1e-15
 
 
+def test_sampled_accel_equals_full(oracle_mod):
+    """The sampled-target evaluation is the same definition: identical bits."""
+    w = li.random_cloud(300, seed=12)
+    tr = _trap(oracle_mod)
+    ax, ay, az = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 1e-7)
+    sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 1e-7)
+    idx = np.array([0, 5, 17, 299, 150])
+    bx, by, bz, bs = oracle_mod.accel_at(w.x, w.y, w.z, w.charge, w.mass, tr, 1e-7, idx)
+    assert np.array_equal(bx, ax[idx]) and np.array_equal(by, ay[idx])
+    assert np.array_equal(bz, az[idx]) and np.array_equal(bs, sc[idx])
+
+
 def test_coincident_pair_contributes_zero(oracle_mod):
     """Exactly coincident ions feel no mutual force (a select, not softening)."""
     x = np.array([0.0, 0.0, 10e-6])
