@@ -141,11 +141,13 @@ void lion_destroy(lion_sim *sim);
  * Values outside the listed sets -> LION_ERR_ARG. */
 typedef struct {
     int32_t i_per_lane;   /* target ions per lane in the pair kernel: 1, 2 or 4          */
-    int32_t j_split;      /* source slices per step (1..64), partial sums reduced in order */
+    int32_t j_split;      /* source slices per step (1..64; clipped to one per 64 sources),
+                             partial sums reduced in slice order                           */
     int32_t chunk_steps;  /* steps per captured launch graph (1..1000)                     */
     int32_t flush_len;    /* LION_MIXED_F64ACC: sources per FP32 run: 4, 8 or 16           */
     int32_t batch_block;  /* threads per trap in batched mode: 64, 128, 256, 512 or 1024   */
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
+    int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
 } lion_kernel_config;
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);

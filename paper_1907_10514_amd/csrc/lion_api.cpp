@@ -51,11 +51,11 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 int64_t padded(int64_t n) { return round_up(std::max<int64_t>(n, 1), 1024); }
 
-// Upper bound on source slices for n ions: at most 64, at most one slice per 16
+// Upper bound on source slices for n ions: at most 64, at most one slice per 64
 // sources, and partial sums kept under ~400 MB for very large n.
 int j_max_for(int64_t n) {
     int64_t j = std::min<int64_t>(64, std::max<int64_t>(1, (int64_t(1) << 24) / std::max<int64_t>(n, 1)));
-    j = std::min<int64_t>(j, std::max<int64_t>(1, round_up(n, 16) / 16));
+    j = std::min<int64_t>(j, std::max<int64_t>(1, round_up(n, 64) / 64));
     return (int)j;
 }
 
@@ -113,22 +113,24 @@ int hip_fail(lion_sim* s, hipError_t e, const char* where) {
 void default_shape(lion_sim* s) {
     LaunchShape& ls = s->ls;
     const int64_t n = s->n;
-    ls.i_per_lane = s->cfg.i_per_lane > 0 ? s->cfg.i_per_lane : (n >= 8192 ? 2 : 1);
+    const bool mixed = s->precision != LION_FP64;
+    ls.i_per_lane = s->cfg.i_per_lane > 0 ? s->cfg.i_per_lane
+                                          : (n >= 8192 ? (mixed ? 4 : 2) : (n >= 2048 ? 2 : 1));
     ls.flush_len = s->cfg.flush_len > 0 ? s->cfg.flush_len : 8;
     ls.batch_block = s->cfg.batch_block > 0 ? s->cfg.batch_block : 256;
-    const int64_t n16 = round_up(n, 16);
+    ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
+    const int64_t n64 = round_up(n, 64);
+    const int64_t blocks_x = (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane);
     int j;
     if (s->cfg.j_split > 0) {
         j = s->cfg.j_split;
     } else {
-        // aim for ~4096 waves (4 per SIMD on 256 CUs), slices of >= 64 sources
-        const int64_t waves_i = std::max<int64_t>(1, (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane));
-        j = (int)std::max<int64_t>(1, (4096 + waves_i - 1) / waves_i);
-        j = (int)std::min<int64_t>(j, std::max<int64_t>(1, n16 / 64));
+        // aim for ~1024 blocks of 4 waves (4 waves per SIMD on 256 CUs)
+        j = (int)std::max<int64_t>(1, (1024 + blocks_x - 1) / blocks_x);
     }
     j = std::max(1, std::min(j, s->j_max));
-    ls.jps = (int)round_up((n16 + j - 1) / j, 16);
-    ls.j_split = (int)((n16 + ls.jps - 1) / ls.jps);  // slices that hold sources
+    ls.jps = (int)round_up((n64 + j - 1) / j, 64);
+    ls.j_split = (int)((n64 + ls.jps - 1) / ls.jps);  // slices that hold sources
 }
 
 void clear_graphs(lion_sim* s) {
@@ -584,8 +586,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->batch_block, {256, 512, 1024}))
         return fail(s, LION_ERR_ARG, "batch_block must be 256, 512 or 1024");
     if (!in(c->use_graph, {1, 2})) return fail(s, LION_ERR_ARG, "use_graph must be 1 or 2");
-    if (c->j_split > s->j_max)
-        return fail(s, LION_ERR_ARG, "j_split above " + std::to_string(s->j_max) + " for this size");
+    if (!in(c->lds_sources, {1, 2})) return fail(s, LION_ERR_ARG, "lds_sources must be 1 or 2");
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);
@@ -595,6 +596,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.batch_block = c->batch_block;
     s->cfg.chunk_steps = c->chunk_steps > 0 ? c->chunk_steps : 100;
     s->cfg.use_graph = c->use_graph > 0 ? c->use_graph : 1;
+    s->cfg.lds_sources = c->lds_sources;
     default_shape(s);
     return LION_OK;
 }
@@ -607,6 +609,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->flush_len = s->ls.flush_len;
     c->batch_block = s->ls.batch_block;
     c->use_graph = s->cfg.use_graph;
+    c->lds_sources = s->ls.lds_sources ? 2 : 1;
     return LION_OK;
 }
 

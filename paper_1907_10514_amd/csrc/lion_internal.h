@@ -42,7 +42,7 @@ struct TrapDev {
 // position and the negated charge in units of e.
 struct MixedSrc {
     float xh, yh, zh, nq;
-    float xl, yl, zl, pad;
+    float xl, yl, zl, r2floor;  // r2floor = kR2FloorF32 (read as an operand)
 };
 
 enum UpdateMode : int {
@@ -79,9 +79,10 @@ struct DevState {
 struct LaunchShape {
     int i_per_lane;
     int j_split;
-    int jps;          // sources per slice (multiple of 4)
+    int jps;          // sources per slice (multiple of 64)
     int flush_len;
     int batch_block;
+    int lds_sources;  // FP32 pair kernels: 1 = sources staged in LDS, 0 = scalar loads
 };
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.

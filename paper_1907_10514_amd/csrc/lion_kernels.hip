@@ -36,7 +36,6 @@
 namespace lion {
 namespace {
 
-constexpr int kPairBlock = 256;
 constexpr double kKeE = kElementaryCharge / (4.0 * kPi * kEps0);  // k_e e (V m)
 
 // ------------------------------------------------------------------ pair terms
@@ -66,7 +65,7 @@ __device__ __forceinline__ void pair_f32_terms(const MixedSrc& q, const FF& t, f
     const float dx = (q.xh - t.xh) + (q.xl - t.xl);
     const float dy = (q.yh - t.yh) + (q.yl - t.yl);
     const float dz = (q.zh - t.zh) + (q.zl - t.zl);
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kR2FloorF32)));
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, q.r2floor)));
     const float y = __builtin_amdgcn_rsqf(r2);
     const float w = (q.nq * y) * (y * y);  // -q r^-3
     tx = w * dx;
@@ -79,7 +78,7 @@ __device__ __forceinline__ void pair_f32(const MixedSrc& q, const FF& t, float& 
     const float dx = (q.xh - t.xh) + (q.xl - t.xl);
     const float dy = (q.yh - t.yh) + (q.yl - t.yl);
     const float dz = (q.zh - t.zh) + (q.zl - t.zl);
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kR2FloorF32)));
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, q.r2floor)));
     const float y = __builtin_amdgcn_rsqf(r2);
     const float w = (q.nq * y) * (y * y);
     sx = fmaf(w, dx, sx);
@@ -117,7 +116,7 @@ __device__ __forceinline__ MixedSrc make_src(double x, double y, double z, doubl
     m.xl = f.xl;
     m.yl = f.yl;
     m.zl = f.zl;
-    m.pad = 0.0f;
+    m.r2floor = kR2FloorF32;
     return m;
 }
 
@@ -200,29 +199,73 @@ __global__ __launch_bounds__(256) void k_pack_mixed(const double4* __restrict__ 
     }
 }
 
-// FP64 pair field.  Block b of slice s covers targets [b*256*I, (b+1)*256*I),
-// lane t owning targets base + t + 256 k (k < I), and sources [s*jps, s*jps+jps)
-// clipped to n16 (entries beyond N carry zero charge).
+// Pair-field kernels.  A block is 4 waves that share the same 64*I targets
+// (lane l of every wave owns targets base + l + 64 k, k < I) and split the
+// block's source slice [s*jps, s*jps + jps) four ways; the four partial sums
+// are added in wave order through LDS and written once per slice.  Sources
+// beyond N carry zero charge, so every range is a multiple of 64 sources.
+
+constexpr int kWaves = 4;
+
+// Sum the per-wave partials of 64*I targets in wave order; wave 0 stores.
 template <int I>
-__global__ __launch_bounds__(kPairBlock) void k_pair_f64(const double4* __restrict__ src,
-                                                         int64_t n, int n16, int jps,
-                                                         int64_t n_pad,
-                                                         double* __restrict__ part,
-                                                         int64_t* __restrict__ counter) {
-    const int64_t base = (int64_t)blockIdx.x * (kPairBlock * I) + threadIdx.x;
+__device__ __forceinline__ void reduce_store(double (&sx)[I], double (&sy)[I], double (&sz)[I],
+                                             double* __restrict__ part, int s, int64_t n,
+                                             int64_t n_pad, int64_t base) {
+    __shared__ double red[kWaves - 1][3][64 * I];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave > 0) {
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            red[wave - 1][0][lane + 64 * k] = sx[k];
+            red[wave - 1][1][lane + 64 * k] = sy[k];
+            red[wave - 1][2][lane + 64 * k] = sz[k];
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double* px = part + (int64_t)(3 * s) * n_pad;
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            double x = sx[k], y = sy[k], z = sz[k];
+#pragma unroll
+            for (int w = 0; w < kWaves - 1; ++w) {
+                x += red[w][0][lane + 64 * k];
+                y += red[w][1][lane + 64 * k];
+                z += red[w][2][lane + 64 * k];
+            }
+            const int64_t i = base + 64 * k;
+            if (i < n) {
+                px[i] = x;
+                px[n_pad + i] = y;
+                px[2 * n_pad + i] = z;
+            }
+        }
+    }
+}
+
+// FP64: sources through scalar loads (wave-uniform addresses) into SGPRs; FP64
+// VALU issues at the same rate with SGPR or VGPR operands.
+template <int I>
+__global__ __launch_bounds__(256) void k_pair_f64(const double4* __restrict__ src, int64_t n,
+                                                  int n64, int jps, int64_t n_pad,
+                                                  double* __restrict__ part,
+                                                  int64_t* __restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t base = (int64_t)blockIdx.x * (64 * I) + lane;
     const int s = blockIdx.y;
-    const int jb = s * jps;
-    const int je = min(jb + jps, n16);
+    const int part_len = jps / kWaves;
+    const int jb = min(s * jps + wave * part_len, n64);
+    const int je = min(jb + part_len, n64);
     double xi[I], yi[I], zi[I], sx[I], sy[I], sz[I];
 #pragma unroll
     for (int k = 0; k < I; ++k) {
-        const double4 p = src[base + kPairBlock * k];
+        const double4 p = src[base + 64 * k];
         xi[k] = p.x;
         yi[k] = p.y;
         zi[k] = p.z;
-        sx[k] = 0.0;
-        sy[k] = 0.0;
-        sz[k] = 0.0;
+        sx[k] = sy[k] = sz[k] = 0.0;
     }
     for (int j = jb; j < je; j += 4) {
         const double4 p0 = src[j], p1 = src[j + 1], p2 = src[j + 2], p3 = src[j + 3];
@@ -234,102 +277,153 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_f64(const double4* __restri
             pair_f64(p3, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
         }
     }
-    double* px = part + (int64_t)(3 * s) * n_pad;
-#pragma unroll
-    for (int k = 0; k < I; ++k) {
-        const int64_t i = base + kPairBlock * k;
-        if (i < n) {
-            px[i] = sx[k];
-            px[n_pad + i] = sy[k];
-            px[2 * n_pad + i] = sz[k];
-        }
-    }
+    reduce_store<I>(sx, sy, sz, part, s, n, n_pad, base);
     if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
 }
 
-// FP32 pair field on float-float positions.  KAHAN = false: FP32 sums over
-// runs of L sources, each run added to FP64 sums.  KAHAN = true: compensated
-// FP32 sums over the whole slice.
-template <int I, int L, bool KAHAN>
-__global__ __launch_bounds__(kPairBlock) void k_pair_mixed(const MixedSrc* __restrict__ srcm,
-                                                           int64_t n, int n16, int jps,
-                                                           int64_t n_pad,
-                                                           double* __restrict__ part,
-                                                           int64_t* __restrict__ counter) {
-    const int64_t base = (int64_t)blockIdx.x * (kPairBlock * I) + threadIdx.x;
-    const int s = blockIdx.y;
-    const int jb = s * jps;
-    const int je = min(jb + jps, n16);
-    FF t[I];
-    double sx[I], sy[I], sz[I];
-    float kx[I], ky[I], kz[I], cx[I], cy[I], cz[I];
+// Accumulators of the FP32 pair path for I targets.
+template <int I, bool KAHAN>
+struct MixedAcc {
+    double sx[I], sy[I], sz[I];           // FP64 sums (run flushes)
+    float kx[I], ky[I], kz[I];            // Kahan sums
+    float cx[I], cy[I], cz[I];            // Kahan compensations
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            sx[k] = sy[k] = sz[k] = 0.0;
+            kx[k] = ky[k] = kz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        if (KAHAN) {
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                sx[k] = (double)kx[k] - (double)cx[k];
+                sy[k] = (double)ky[k] - (double)cy[k];
+                sz[k] = (double)kz[k] - (double)cz[k];
+            }
+        }
+    }
+};
+
+// One run of L sources from `q` (LDS or global) against I float-float targets.
+template <int I, int L, bool KAHAN, typename Src>
+__device__ __forceinline__ void mixed_run(const Src* __restrict__ q, const FF (&t)[I],
+                                          MixedAcc<I, KAHAN>& A) {
+    if (KAHAN) {
+#pragma unroll
+        for (int u = 0; u < L; ++u) {
+            const MixedSrc m = q[u];
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                float tx, ty, tz;
+                pair_f32_terms(m, t[k], tx, ty, tz);
+                kahan_add(tx, A.kx[k], A.cx[k]);
+                kahan_add(ty, A.ky[k], A.cy[k]);
+                kahan_add(tz, A.kz[k], A.cz[k]);
+            }
+        }
+    } else {
+        float fx[I], fy[I], fz[I];
+#pragma unroll
+        for (int k = 0; k < I; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < L; ++u) {
+            const MixedSrc m = q[u];
+#pragma unroll
+            for (int k = 0; k < I; ++k) pair_f32(m, t[k], fx[k], fy[k], fz[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            A.sx[k] += (double)fx[k];
+            A.sy[k] += (double)fy[k];
+            A.sz[k] += (double)fz[k];
+        }
+    }
+}
+
+template <int I>
+__device__ __forceinline__ void load_targets(const MixedSrc* __restrict__ srcm, int64_t base,
+                                             FF (&t)[I]) {
 #pragma unroll
     for (int k = 0; k < I; ++k) {
-        const MixedSrc m = srcm[base + kPairBlock * k];
+        const MixedSrc m = srcm[base + 64 * k];
         t[k].xh = m.xh;
         t[k].yh = m.yh;
         t[k].zh = m.zh;
         t[k].xl = m.xl;
         t[k].yl = m.yl;
         t[k].zl = m.zl;
-        sx[k] = sy[k] = sz[k] = 0.0;
-        kx[k] = ky[k] = kz[k] = 0.0f;
-        cx[k] = cy[k] = cz[k] = 0.0f;
     }
-    for (int j = jb; j < je; j += L) {
-        if (KAHAN) {
-#pragma unroll
-            for (int u = 0; u < L; ++u) {
-                const MixedSrc q = srcm[j + u];
-#pragma unroll
-                for (int k = 0; k < I; ++k) {
-                    float tx, ty, tz;
-                    pair_f32_terms(q, t[k], tx, ty, tz);
-                    kahan_add(tx, kx[k], cx[k]);
-                    kahan_add(ty, ky[k], cy[k]);
-                    kahan_add(tz, kz[k], cz[k]);
-                }
-            }
-        } else {
-            float fx[I], fy[I], fz[I];
-#pragma unroll
-            for (int k = 0; k < I; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
-#pragma unroll
-            for (int u = 0; u < L; ++u) {
-                const MixedSrc q = srcm[j + u];
-#pragma unroll
-                for (int k = 0; k < I; ++k) pair_f32(q, t[k], fx[k], fy[k], fz[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < I; ++k) {
-                sx[k] += (double)fx[k];
-                sy[k] += (double)fy[k];
-                sz[k] += (double)fz[k];
-            }
-        }
+}
+
+// FP32 pair field, sources through scalar loads into SGPRs.  Every op that
+// reads an SGPR issues at the single rate, so this variant is the reference
+// for the LDS variant below.
+template <int I, int L, bool KAHAN>
+__global__ __launch_bounds__(256) void k_pair_mixed_s(const MixedSrc* __restrict__ srcm,
+                                                      int64_t n, int n64, int jps,
+                                                      int64_t n_pad, double* __restrict__ part,
+                                                      int64_t* __restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t base = (int64_t)blockIdx.x * (64 * I) + lane;
+    const int s = blockIdx.y;
+    const int part_len = jps / kWaves;
+    const int jb = min(s * jps + wave * part_len, n64);
+    const int je = min(jb + part_len, n64);
+    FF t[I];
+    load_targets<I>(srcm, base, t);
+    MixedAcc<I, KAHAN> A;
+    A.init();
+    for (int j = jb; j < je; j += L) mixed_run<I, L, KAHAN>(srcm + j, t, A);
+    A.finish();
+    reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
+    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
+}
+
+// FP32 pair field, sources staged in LDS tiles of kTile and read back with
+// wave-uniform addresses (broadcast) into VGPRs, so that every FP32 op of the
+// pair term has VGPR operands only and can dual-issue.
+constexpr int kTile = 256;
+
+template <int I, int L, bool KAHAN>
+__global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict__ srcm,
+                                                      int64_t n, int n64, int jps,
+                                                      int64_t n_pad, double* __restrict__ part,
+                                                      int64_t* __restrict__ counter) {
+    __shared__ float4 tile[2 * kTile];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * (64 * I) + lane;
+    const int s = blockIdx.y;
+    const int jb = min(s * jps, n64);
+    const int je = min(jb + jps, n64);
+    FF t[I];
+    load_targets<I>(srcm, base, t);
+    MixedAcc<I, KAHAN> A;
+    A.init();
+    const float4* __restrict__ g = reinterpret_cast<const float4*>(srcm);
+    const MixedSrc* tl = reinterpret_cast<const MixedSrc*>(tile);
+    for (int j0 = jb; j0 < je; j0 += kTile) {
+        const int cnt = min(kTile, je - j0);  // multiple of 64
+        __syncthreads();
+        for (int q = threadIdx.x; q < 2 * cnt; q += 256) tile[q] = g[2 * (int64_t)j0 + q];
+        __syncthreads();
+        const int per = cnt / kWaves;  // multiple of 16
+        const MixedSrc* mine = tl + wave * per;
+        for (int u = 0; u < per; u += L) mixed_run<I, L, KAHAN>(mine + u, t, A);
     }
-    double* px = part + (int64_t)(3 * s) * n_pad;
-#pragma unroll
-    for (int k = 0; k < I; ++k) {
-        const int64_t i = base + kPairBlock * k;
-        if (KAHAN) {
-            sx[k] = (double)kx[k] - (double)cx[k];
-            sy[k] = (double)ky[k] - (double)cy[k];
-            sz[k] = (double)kz[k] - (double)cz[k];
-        }
-        if (i < n) {
-            px[i] = sx[k];
-            px[n_pad + i] = sy[k];
-            px[2 * n_pad + i] = sz[k];
-        }
-    }
+    A.finish();
+    reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
     if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
 }
 
 // Per-ion epilogue of a step (or a plain force evaluation): reduce the slice
 // partials in slice order, add the trap field, then kick / damp / drift.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
+__global__ __launch_bounds__(64) void k_update(double4* __restrict__ src,
                                                 MixedSrc* __restrict__ srcm,
                                                 double* __restrict__ vx, double* __restrict__ vy,
                                                 double* __restrict__ vz, double* __restrict__ ax,
@@ -343,6 +437,7 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double Sx = 0.0, Sy = 0.0, Sz = 0.0;
+#pragma unroll 4
     for (int s = 0; s < j_split; ++s) {
         const double* px = part + (int64_t)(3 * s) * n_pad;
         Sx += px[i];
@@ -627,22 +722,26 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+inline int n64_of(int64_t n) { return (int)((n + 63) & ~int64_t(63)); }
+
 template <int I>
 hipError_t pair_f64_launch(const DevState& s, const LaunchShape& ls, int64_t* ctr,
                            hipStream_t st) {
-    const int n16 = (int)((s.n + 15) & ~int64_t(15));
-    dim3 grid(blocks_for(s.n, kPairBlock * I), ls.j_split);
-    k_pair_f64<I><<<grid, kPairBlock, 0, st>>>(s.src, s.n, n16, ls.jps, s.n_pad, s.part, ctr);
+    dim3 grid(blocks_for(s.n, 64 * I), ls.j_split);
+    k_pair_f64<I><<<grid, 256, 0, st>>>(s.src, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr);
     return hipGetLastError();
 }
 
 template <int I, int L, bool KAHAN>
 hipError_t pair_mixed_launch(const DevState& s, const LaunchShape& ls, int64_t* ctr,
                              hipStream_t st) {
-    const int n16 = (int)((s.n + 15) & ~int64_t(15));
-    dim3 grid(blocks_for(s.n, kPairBlock * I), ls.j_split);
-    k_pair_mixed<I, L, KAHAN>
-        <<<grid, kPairBlock, 0, st>>>(s.srcm, s.n, n16, ls.jps, s.n_pad, s.part, ctr);
+    dim3 grid(blocks_for(s.n, 64 * I), ls.j_split);
+    if (ls.lds_sources)
+        k_pair_mixed_l<I, L, KAHAN>
+            <<<grid, 256, 0, st>>>(s.srcm, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr);
+    else
+        k_pair_mixed_s<I, L, KAHAN>
+            <<<grid, 256, 0, st>>>(s.srcm, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr);
     return hipGetLastError();
 }
 
@@ -717,21 +816,21 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
                          bool use_counter, hipStream_t st) {
     const double scale = precision == 0 ? 1.0 : kMixedFieldScale;
     const int64_t* ctr = use_counter ? s.counter : nullptr;
-    const unsigned g = blocks_for(s.n, 256);
+    const unsigned g = blocks_for(s.n, 64);
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
     switch (mode) {
         case kModeAccel:
-            k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+            k_update<kModeAccel><<<g, 64, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                     s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
                                                     s.n_pad, scale, s.traps, ctr);
             break;
         case kModeEnd:
-            k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+            k_update<kModeEnd><<<g, 64, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                   s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
                                                   s.n_pad, scale, s.traps, ctr);
             break;
         default:
-            k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
+            k_update<kModeEndDrift><<<g, 64, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
                                                        s.ay, s.az, s.qm, s.qe, s.part,
                                                        ls.j_split, s.n, s.n_pad, scale, s.traps,
                                                        ctr);

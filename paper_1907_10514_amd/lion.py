@@ -39,7 +39,8 @@ class LionError(RuntimeError):
 class KernelConfig(ctypes.Structure):
     _fields_ = [("i_per_lane", ctypes.c_int32), ("j_split", ctypes.c_int32),
                 ("chunk_steps", ctypes.c_int32), ("flush_len", ctypes.c_int32),
-                ("batch_block", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("batch_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("lds_sources", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -237,7 +238,7 @@ class Simulation:
     workspace (a uint8 tensor kept alive by this object) and the stream."""
 
     def __init__(self, masses, charges, precision="fp64", n_per_trap=None, device=None,
-                 stream=None):
+                 stream=None, autotuned=True):
         import torch
 
         if not torch.cuda.is_available():
@@ -265,6 +266,18 @@ class Simulation:
             else:
                 self.h = lion_create(self.n, m, q, self.precision, ptr, ws, sptr)
         self.ws_bytes = ws
+        self.tuned = None
+        if autotuned:
+            from . import tune
+
+            arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "")
+            cfg = tune.lookup(arch, self.n, self.precision, self.batched)
+            if cfg:
+                try:
+                    self.set_config(**cfg)
+                    self.tuned = cfg
+                except LionError:
+                    self.tuned = None
 
     def close(self):
         if getattr(self, "h", None):

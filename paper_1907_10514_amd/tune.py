@@ -1,0 +1,197 @@
+"""Autotuner for the launch shapes of the pair kernels and the batched kernel.
+
+For a given workload size and precision it times every candidate launch shape
+(targets per lane I, source slices J, FP32 run length L, LDS or scalar source
+feed, batch workgroup size) with the library's own kernel timer, rejects
+candidates whose forces differ from the FP64 path by more than the precision's
+bar on a validation cloud, and stores the fastest in a JSON cache keyed by
+(GPU arch, size bucket, precision, single/batched).  ``Simulation`` applies a
+cached shape when one exists.
+
+Usage:  python -m paper_1907_10514_amd.tune [--n 16384] [--precision mixed]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import time
+
+import numpy as np
+
+from . import lion as L
+
+CACHE_ENV = "LION_TUNE_CACHE"
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+BAR = {L.LION_FP64: 1e-12, L.LION_MIXED_F64ACC: 1e-6, L.LION_MIXED_KAHAN: 1e-6}
+
+
+def cache_path() -> str:
+    return os.environ.get(CACHE_ENV, DEFAULT_CACHE)
+
+
+def size_bucket(n: int) -> int:
+    """Power-of-two bucket of the ion count (a shape tuned at 16384 serves 12k..23k)."""
+    return int(2 ** round(np.log2(max(int(n), 1))))
+
+
+def cache_key(arch: str, n: int, precision: int, batched: bool) -> str:
+    return f"{arch.split(':')[0]}|n{size_bucket(n)}|p{int(precision)}|{'batch' if batched else 'single'}"
+
+
+def load_cache(path: str | None = None) -> dict:
+    try:
+        with open(path or cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(arch: str, n: int, precision: int, batched: bool) -> dict | None:
+    ent = load_cache().get(cache_key(arch, n, precision, batched))
+    return ent.get("config") if ent else None
+
+
+def _arch() -> str:
+    import torch
+
+    return getattr(torch.cuda.get_device_properties(0), "gcnArchName", "unknown")
+
+
+def _scale(x, y, z, q_e):
+    """Sum of |q_j| / r_ij^2 per target (field scale, units of e/m^2) on the host."""
+    p = np.stack([x, y, z], 1)
+    out = np.empty(x.size)
+    for a in range(0, x.size, 256):
+        d = p[a:a + 256, None, :] - p[None, :, :]
+        r2 = np.sum(d * d, -1)
+        r2[r2 == 0] = np.inf
+        out[a:a + 256] = np.sum(np.abs(q_e)[None, :] / r2, 1)
+    return out
+
+
+def single_candidates(n: int, precision: int):
+    js = [j for j in (1, 2, 4, 8, 12, 16, 24, 32, 48, 64)]
+    if precision == L.LION_FP64:
+        for i, j in itertools.product((1, 2, 4), js):
+            yield dict(i_per_lane=i, j_split=j)
+    elif precision == L.LION_MIXED_F64ACC:
+        for i, j, fl, lds in itertools.product((1, 2, 4), js, (8, 16), (1, 2)):
+            yield dict(i_per_lane=i, j_split=j, flush_len=fl, lds_sources=lds)
+    else:
+        for i, j, lds in itertools.product((1, 2, 4), js, (1, 2)):
+            yield dict(i_per_lane=i, j_split=j, lds_sources=lds)
+
+
+def _cloud(n, seed=12345, sigma=200e-6):
+    rng = np.random.default_rng(seed)
+    x, y, z = rng.normal(0, sigma, (3, n))
+    return x, y, z
+
+
+def tune_single(n: int, precision: int, reps: int = 20, verbose: bool = True) -> dict:
+    """Time every candidate for a single trap of n ions; returns the best entry."""
+    e, _, amu = L.lion_constants()
+    mass = np.full(n, 40 * amu)
+    charge = np.full(n, e)
+    x, y, z = _cloud(n)
+    zeros = np.zeros(n)
+    sim = L.Simulation(mass, charge, precision, stream=None)
+    sim.set_state(x, y, z, zeros, zeros, zeros)
+    # validation cloud (smaller) against the FP64 path
+    nv = min(n, 2048)
+    xv, yv, zv = _cloud(nv, seed=7)
+    ref = L.Simulation(np.full(nv, 40 * amu), np.full(nv, e), L.LION_FP64)
+    ref.set_state(xv, yv, zv, np.zeros(nv), np.zeros(nv), np.zeros(nv))
+    a_ref = np.array(ref.compute_accel())
+    ref.close()
+    k_scale = (e / (40 * amu)) * e / (4 * np.pi * 8.8541878128e-12)
+    sc = k_scale * _scale(xv, yv, zv, np.ones(nv))
+    val = L.Simulation(np.full(nv, 40 * amu), np.full(nv, e), precision)
+    val.set_state(xv, yv, zv, np.zeros(nv), np.zeros(nv), np.zeros(nv))
+    results = []
+    for cfg in single_candidates(n, precision):
+        try:
+            sim.set_config(**cfg)
+            val.set_config(**{k: v for k, v in cfg.items() if k != "j_split"},
+                           j_split=min(cfg["j_split"], max(1, (nv + 63) // 64)))
+        except L.LionError:
+            continue
+        a = np.array(val.compute_accel())
+        err = float(np.max(np.linalg.norm(a - a_ref, axis=0) / sc))
+        ms = sim.time_pair_kernel(reps)
+        ent = dict(config=cfg, pair_ms=ms, m1_vs_fp64=err, ok=err <= BAR[precision] * 0.5)
+        results.append(ent)
+        if verbose:
+            print(f"  {cfg} -> {ms * 1e3:8.2f} us  M1 {err:.2e}{'' if ent['ok'] else '  REJECT'}",
+                  flush=True)
+    sim.close()
+    val.close()
+    ok = [r for r in results if r["ok"]]
+    best = min(ok, key=lambda r: r["pair_ms"])
+    return dict(best=best, n=n, precision=precision, candidates=len(results))
+
+
+def tune_batch(n_per_trap, precision: int, steps: int = 100, verbose: bool = True) -> dict:
+    e, _, amu = L.lion_constants()
+    npt = np.asarray(n_per_trap, dtype=np.int64)
+    n = int(npt.sum())
+    x, y, z = _cloud(n, sigma=20e-6)
+    res = []
+    for block in (256, 512, 1024):
+        sim = L.Simulation(np.full(n, 40 * amu), np.full(n, e), precision, n_per_trap=npt)
+        sim.set_config(batch_block=block)
+        sim.set_trap(9.0, 2 * np.pi * 3.85e6, 0.24, 0.5e-3, 1e-3, 0.25)
+        sim.set_state(x, y, z, np.zeros(n), np.zeros(n), np.zeros(n))
+        sim.time_batch_kernel(1, 10, 1.3e-8)
+        ms = sim.time_batch_kernel(3, steps, 1.3e-8)
+        sim.close()
+        res.append(dict(config=dict(batch_block=block), kernel_ms=ms, ok=True))
+        if verbose:
+            print(f"  batch_block={block} -> {ms:.3f} ms / {steps} steps", flush=True)
+    best = min(res, key=lambda r: r["kernel_ms"])
+    return dict(best=best, n=n, precision=precision, candidates=len(res))
+
+
+def store(key: str, entry: dict, path: str | None = None):
+    path = path or cache_path()
+    data = load_cache(path)
+    data[key] = dict(config=entry["best"]["config"], measured=entry["best"],
+                     tuned_at=time.strftime("%Y-%m-%d %H:%M:%S"))
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, nargs="*", default=[16384])
+    ap.add_argument("--precision", nargs="*", default=["fp64", "mixed", "mixed_kahan"])
+    ap.add_argument("--batch", action="store_true", help="tune the 512-trap batch instead")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    import torch
+
+    torch.cuda.set_device(0)
+    arch = _arch()
+    for pname in args.precision:
+        p = L.PRECISIONS[pname]
+        if args.batch:
+            rng = np.random.Generator(np.random.PCG64(3))
+            npt = rng.integers(2, 513, size=512)
+            print(f"[tune] batch {pname}", flush=True)
+            r = tune_batch(npt, p)
+            store(cache_key(arch, int(npt.sum()), p, True), r)
+            print(f"[tune] best {r['best']}", flush=True)
+            continue
+        for n in args.n:
+            print(f"[tune] n={n} {pname}", flush=True)
+            r = tune_single(n, p, reps=args.reps)
+            store(cache_key(arch, n, p, False), r)
+            print(f"[tune] best {r['best']}", flush=True)
+
+
+if __name__ == "__main__":
+    main()
