@@ -40,9 +40,10 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def traffic_for(kernel_key: str):
+def traffic_for(kernel_key: str, launch: dict):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    summary, or None if absent or taken on a different kernel source."""
+    summary, or None if absent, taken on a different kernel source, or taken
+    with a different launch shape."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
@@ -50,6 +51,8 @@ def traffic_for(kernel_key: str):
         return None
     ent = data.get(kernel_key)
     if not ent or ent.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    if any(launch.get(k) != v for k, v in ent.get("launch", {}).items()):
         return None
     return ent.get("bytes_per_launch")
 
@@ -160,6 +163,27 @@ def cpu_baseline(w, seconds):
                        f"N(N-1) pair interactions)")
 
 
+def profile_pass(torch, w, precisions):
+    """Short run for counter collection: each benchmarked pair kernel (tuned
+    launch shape) 5 times plus 3 steps, then a device-to-device copy of 256 MiB
+    whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters."""
+    from paper_1907_10514_amd import runner
+
+    for p in precisions:
+        sim = runner.simulation_for(w, precision=p)
+        sim.time_pair_kernel(5)
+        sim.step(3, w.traps[0].dt)
+        torch.cuda.synchronize()
+        log(f"[profile] {p} launch shape {sim.config()}")
+        sim.close()
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("[profile] done (copy calibration: 256 MiB read + 256 MiB written per copy)")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +196,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--precisions", default="fp64,mixed,mixed_kahan")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="only launch the benchmarked pair kernels a few times and a 256 MiB "
+                         "device copy (for rocprofv3 counter passes), then exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -191,6 +218,9 @@ def main():
     torch.cuda.set_device(0)
     props = torch.cuda.get_device_properties(0)
     w = li.mixed16384()
+    if args.profile_pass:
+        profile_pass(torch, w, [p for p in args.precisions.split(",") if p])
+        return
     n = w.n
     precs = [p for p in args.precisions.split(",") if p]
     res = {}
@@ -236,7 +266,7 @@ def main():
         "peak": PEAK_TFLOPS[head],
         "unit": "TFLOP/s",
         "frac": r["pair_kernel_tflops"] / PEAK_TFLOPS[head],
-        "traffic": traffic_for(kern_key),
+        "traffic": traffic_for(kern_key, r["launch"]),
         "algorithmic_flop_per_launch": FLOP_PER_PAIR * pairs,
         "avg_launch_ms": r["pair_kernel_ms"],
     }

@@ -148,21 +148,25 @@ typedef struct {
     int32_t batch_block;  /* threads per trap in batched mode: 64, 128, 256, 512 or 1024   */
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
+    int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
+                             LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 32768
+                             (else LION_ERR_UNSUPPORTED)                                     */
 } lion_kernel_config;
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);
 int lion_get_kernel_config(const lion_sim *sim, lion_kernel_config *cfg);
 
-/* Measurement helper: launches the pair-field kernel of this handle `reps`
- * times (1..10000) on the handle's stream at the current positions, each launch
- * bracketed by HIP events on that stream, and returns the mean launch
- * duration in *ms_avg.  Changes no state (only the partial-sum scratch).
- * Single-trap handles only (LION_ERR_UNSUPPORTED for batches).  Synchronises. */
+/* Measurement helper: launches the pair-field kernel of this handle once to
+ * warm up, then `reps` times (1..10000) back to back on the handle's stream at
+ * the current positions between two HIP events recorded on that stream, and
+ * returns the mean duration per launch in *ms_avg.  Changes no state (only the
+ * partial-sum scratch).  Single-trap handles only (LION_ERR_UNSUPPORTED for
+ * batches).  Synchronises. */
 int lion_time_pair_kernel(lion_sim *sim, int32_t reps, double *ms_avg);
 
-/* As lion_time_pair_kernel for the batched kernel: `reps` launches of
- * `nsteps` in-kernel steps each.  The state advances by reps * nsteps steps.
- * Batched handles only.  Synchronises. */
+/* As lion_time_pair_kernel for the batched kernel: `reps` back-to-back
+ * launches of `nsteps` in-kernel steps each (no warm-up launch).  The state
+ * advances by reps * nsteps steps.  Batched handles only.  Synchronises. */
 int lion_time_batch_kernel(lion_sim *sim, int32_t reps, int32_t nsteps, double dt,
                            double *ms_avg);
 

@@ -59,6 +59,13 @@ int j_max_for(int64_t n) {
     return (int)j;
 }
 
+// Partial-sum slices the workspace holds: enough for any source split and, up
+// to kMaxSymTiles tiles, for the pair-once kernels (one slice per tile).
+int slices_for(int64_t n) {
+    const int nb = lion::sym_tiles(n);
+    return std::max(j_max_for(n), nb <= lion::kMaxSymTiles ? nb : 0);
+}
+
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
         flags, total;
@@ -81,7 +88,7 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.qe = take(np * sizeof(double));
     L.mass = take(np * sizeof(double));
     L.trap_of = take(np * sizeof(int32_t));
-    L.part = batched ? SIZE_MAX : take((size_t)j_max_for(n) * 3 * np * sizeof(double));
+    L.part = batched ? SIZE_MAX : take((size_t)slices_for(n) * 3 * np * sizeof(double));
     L.scratch = take(np * sizeof(double));
     L.traps = take((size_t)n_traps * sizeof(TrapDev));
     L.offsets = take((size_t)(n_traps + 1) * sizeof(int64_t));
@@ -119,6 +126,8 @@ void default_shape(lion_sim* s) {
     ls.flush_len = s->cfg.flush_len > 0 ? s->cfg.flush_len : 8;
     ls.batch_block = s->cfg.batch_block > 0 ? s->cfg.batch_block : 256;
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
+    const int nb = lion::sym_tiles(n);
+    ls.symmetric = (s->cfg.symmetric == 2 && nb <= lion::kMaxSymTiles) ? 1 : 0;
     const int64_t n64 = round_up(n, 64);
     const int64_t blocks_x = (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane);
     int j;
@@ -131,6 +140,7 @@ void default_shape(lion_sim* s) {
     j = std::max(1, std::min(j, s->j_max));
     ls.jps = (int)round_up((n64 + j - 1) / j, 64);
     ls.j_split = (int)((n64 + ls.jps - 1) / ls.jps);  // slices that hold sources
+    if (ls.symmetric) ls.j_split = nb;               // one partial per tile
 }
 
 void clear_graphs(lion_sim* s) {
@@ -587,6 +597,11 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
         return fail(s, LION_ERR_ARG, "batch_block must be 256, 512 or 1024");
     if (!in(c->use_graph, {1, 2})) return fail(s, LION_ERR_ARG, "use_graph must be 1 or 2");
     if (!in(c->lds_sources, {1, 2})) return fail(s, LION_ERR_ARG, "lds_sources must be 1 or 2");
+    if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");
+    if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
+        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 32768");
+    if (c->symmetric == 2 && s->precision == LION_MIXED_KAHAN)
+        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels exist for FP64 and MIXED_F64ACC");
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);
@@ -597,6 +612,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.chunk_steps = c->chunk_steps > 0 ? c->chunk_steps : 100;
     s->cfg.use_graph = c->use_graph > 0 ? c->use_graph : 1;
     s->cfg.lds_sources = c->lds_sources;
+    s->cfg.symmetric = c->symmetric;
     default_shape(s);
     return LION_OK;
 }
@@ -610,6 +626,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->batch_block = s->ls.batch_block;
     c->use_graph = s->cfg.use_graph;
     c->lds_sources = s->ls.lds_sources ? 2 : 1;
+    c->symmetric = s->ls.symmetric ? 2 : 1;
     return LION_OK;
 }
 
@@ -620,26 +637,27 @@ int lion_time_pair_kernel(lion_sim* s, int32_t reps, double* ms_avg) {
     if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
     LION_HIP(s, hipSetDevice(s->device));
     hipStream_t st = s->stream;
-    std::vector<hipEvent_t> ev(2 * reps, nullptr);
-    for (auto& e : ev) LION_HIP(s, hipEventCreate(&e));
-    int rc = LION_OK;
-    for (int r = 0; r < reps && rc == LION_OK; ++r) {
-        if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
-            lion::launch_pair(s->d, s->precision, s->ls, false, st) != hipSuccess ||
-            hipEventRecord(ev[2 * r + 1], st) != hipSuccess)
-            rc = fail(s, LION_ERR_HIP, "pair kernel timing launch failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LION_HIP(s, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(s, LION_ERR_HIP, "hipEventCreate failed");
     }
-    double total = 0.0;
-    if (rc == LION_OK && hipStreamSynchronize(st) != hipSuccess)
-        rc = fail(s, LION_ERR_HIP, "hipStreamSynchronize failed");
-    for (int r = 0; r < reps && rc == LION_OK; ++r) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess)
-            rc = fail(s, LION_ERR_HIP, "hipEventElapsedTime failed");
-        total += ms;
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    if (rc == LION_OK) *ms_avg = total / reps;
+    // one warm launch, then reps back-to-back launches between two events
+    int rc = lion::launch_pair(s->d, s->precision, s->ls, false, st) == hipSuccess ? LION_OK
+             : fail(s, LION_ERR_HIP, "pair kernel launch failed");
+    if (rc == LION_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(s, LION_ERR_HIP, "hipEventRecord failed");
+    for (int r = 0; r < reps && rc == LION_OK; ++r)
+        if (lion::launch_pair(s->d, s->precision, s->ls, false, st) != hipSuccess)
+            rc = fail(s, LION_ERR_HIP, "pair kernel launch failed");
+    if (rc == LION_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(s, LION_ERR_HIP, "hipEventRecord failed");
+    float ms = 0.0f;
+    if (rc == LION_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(s, LION_ERR_HIP, "hipEventSynchronize failed");
+    if (rc == LION_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = fail(s, LION_ERR_HIP, "hipEventElapsedTime failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == LION_OK) *ms_avg = (double)ms / reps;
     return rc;
 }
 
@@ -664,26 +682,27 @@ int lion_time_batch_kernel(lion_sim* s, int32_t reps, int32_t nsteps, double dt,
     if (rc) return rc;
     hipStream_t st = s->stream;
     LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), st));
-    std::vector<hipEvent_t> ev(2 * reps, nullptr);
-    for (auto& e : ev) LION_HIP(s, hipEventCreate(&e));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LION_HIP(s, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(s, LION_ERR_HIP, "hipEventCreate failed");
+    }
+    if (hipEventRecord(e0, st) != hipSuccess) rc = fail(s, LION_ERR_HIP, "hipEventRecord failed");
     for (int r = 0; r < reps && rc == LION_OK; ++r) {
-        if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
-            lion::launch_batch(s->d, s->precision, s->n_traps, s->max_trap, s->ls, nsteps, 0, st) != hipSuccess ||
-            hipEventRecord(ev[2 * r + 1], st) != hipSuccess ||
+        if (lion::launch_batch(s->d, s->precision, s->n_traps, s->max_trap, s->ls, nsteps, 0, st) != hipSuccess ||
             lion::launch_counter_add(s->d, nsteps, st) != hipSuccess)
             rc = fail(s, LION_ERR_HIP, "batch kernel timing launch failed");
     }
-    double total = 0.0;
-    if (rc == LION_OK && hipStreamSynchronize(st) != hipSuccess)
-        rc = fail(s, LION_ERR_HIP, "hipStreamSynchronize failed");
-    for (int r = 0; r < reps && rc == LION_OK; ++r) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess)
-            rc = fail(s, LION_ERR_HIP, "hipEventElapsedTime failed");
-        total += ms;
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc == LION_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(s, LION_ERR_HIP, "hipEventRecord failed");
+    float ms = 0.0f;
+    if (rc == LION_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(s, LION_ERR_HIP, "hipEventSynchronize failed");
+    if (rc == LION_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = fail(s, LION_ERR_HIP, "hipEventElapsedTime failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != LION_OK) return rc;
+    const double total = ms;
     for (int k = 0; k < s->n_traps; ++k)
         s->t_now[k] = s->traps[k].t_start + (double)((int64_t)reps * nsteps) * dt;
     *ms_avg = total / reps;

@@ -83,7 +83,13 @@ struct LaunchShape {
     int flush_len;
     int batch_block;
     int lds_sources;  // FP32 pair kernels: 1 = sources staged in LDS, 0 = scalar loads
+    int symmetric;    // 1 = each unordered pair once (tile pairs), 0 = all ordered pairs
 };
+
+// Tiles of 256 ions used by the pair kernels that evaluate each pair once; the
+// epilogue then adds one partial per tile.
+inline int sym_tiles(int64_t n) { return (int)((n + 255) / 256); }
+constexpr int kMaxSymTiles = 128;
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_drift(const DevState& s, hipStream_t st);

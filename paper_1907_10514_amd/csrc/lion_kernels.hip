@@ -208,18 +208,19 @@ __global__ __launch_bounds__(256) void k_pack_mixed(const double4* __restrict__ 
 constexpr int kWaves = 4;
 
 // Sum the per-wave partials of 64*I targets in wave order; wave 0 stores.
+// red must hold 3 * 3 * 64 * I doubles of LDS.
 template <int I>
-__device__ __forceinline__ void reduce_store(double (&sx)[I], double (&sy)[I], double (&sz)[I],
-                                             double* __restrict__ part, int s, int64_t n,
-                                             int64_t n_pad, int64_t base) {
-    __shared__ double red[kWaves - 1][3][64 * I];
+__device__ __forceinline__ void reduce_store_in(double (&sx)[I], double (&sy)[I],
+                                                double (&sz)[I], double* __restrict__ part,
+                                                int s, int64_t n, int64_t n_pad, int64_t base,
+                                                double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (wave > 0) {
 #pragma unroll
         for (int k = 0; k < I; ++k) {
-            red[wave - 1][0][lane + 64 * k] = sx[k];
-            red[wave - 1][1][lane + 64 * k] = sy[k];
-            red[wave - 1][2][lane + 64 * k] = sz[k];
+            red[((wave - 1) * 3 + 0) * 64 * I + lane + 64 * k] = sx[k];
+            red[((wave - 1) * 3 + 1) * 64 * I + lane + 64 * k] = sy[k];
+            red[((wave - 1) * 3 + 2) * 64 * I + lane + 64 * k] = sz[k];
         }
     }
     __syncthreads();
@@ -230,9 +231,9 @@ __device__ __forceinline__ void reduce_store(double (&sx)[I], double (&sy)[I], d
             double x = sx[k], y = sy[k], z = sz[k];
 #pragma unroll
             for (int w = 0; w < kWaves - 1; ++w) {
-                x += red[w][0][lane + 64 * k];
-                y += red[w][1][lane + 64 * k];
-                z += red[w][2][lane + 64 * k];
+                x += red[(w * 3 + 0) * 64 * I + lane + 64 * k];
+                y += red[(w * 3 + 1) * 64 * I + lane + 64 * k];
+                z += red[(w * 3 + 2) * 64 * I + lane + 64 * k];
             }
             const int64_t i = base + 64 * k;
             if (i < n) {
@@ -242,6 +243,14 @@ __device__ __forceinline__ void reduce_store(double (&sx)[I], double (&sy)[I], d
             }
         }
     }
+}
+
+template <int I>
+__device__ __forceinline__ void reduce_store(double (&sx)[I], double (&sy)[I], double (&sz)[I],
+                                             double* __restrict__ part, int s, int64_t n,
+                                             int64_t n_pad, int64_t base) {
+    __shared__ double red[(kWaves - 1) * 3 * 64 * I];
+    reduce_store_in<I>(sx, sy, sz, part, s, n, n_pad, base, red);
 }
 
 // FP64: sources through scalar loads (wave-uniform addresses) into SGPRs; FP64
@@ -418,6 +427,237 @@ __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict
     A.finish();
     reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
     if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
+}
+
+// ------------------------------------------------------------------
+// Pair field with Newton's third law: every unordered pair is evaluated once.
+//
+// Ions are cut into tiles of 256.  Block u handles the tile pair (a, b), a <= b
+// (upper triangle, row-major).  Its 4 waves each hold all 256 targets of tile a
+// (4 per lane) and take 64 of the 256 sources of tile b.  For a source j and
+// target i the block adds q_j (r_i - r_j)/r^3 to target i (registers) and
+// q_i (r_j - r_i)/r^3 to source j; the latter is summed over the wave's 64
+// lanes through a per-wave LDS transpose (fixed order).  Diagonal tiles
+// (a == b) evaluate all ordered pairs on the target side only.  Partial sums
+// land in slot b for tile-a ions and in slot a for tile-b ions, so every ion
+// receives exactly one partial per tile and the epilogue adds the nb slots in
+// order: deterministic, no atomics.
+
+constexpr int kSymTile = 256;
+
+__device__ __forceinline__ void sym_unit(int nb, int& a, int& b) {
+    int u = blockIdx.x, row = 0, len = nb;
+    while (u >= len) {
+        u -= len;
+        ++row;
+        --len;
+    }
+    a = row;
+    b = row + u;
+}
+
+// Sum over the 64 lanes of a wave of C columns held lane-major in buf[64][S]
+// (S = C + 1: consecutive lanes write consecutive rows, and a column read by
+// consecutive lanes touches consecutive banks).  P lanes per column each add
+// 64/P rows in FP64 with four independent partial sums, then the P part sums
+// are combined by lane exchanges (P = 2 or 4).  The column total ends up in
+// lanes with (lane % P) == 0, column = lane / P.
+template <int C, int P, typename T>
+__device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int lane) {
+    static_assert(C * P <= 64 && (P == 2 || P == 4), "bad column split");
+    constexpr int E = 64 / P, S = C + 1;
+    const int col = lane / P, q = lane % P;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    if (col < C) {
+        const T* p = buf + (E * q) * S + col;
+#pragma unroll
+        for (int e = 0; e < E; e += 4) {
+            acc0 += (double)p[(e + 0) * S];
+            acc1 += (double)p[(e + 1) * S];
+            acc2 += (double)p[(e + 2) * S];
+            acc3 += (double)p[(e + 3) * S];
+        }
+    }
+    double acc = (acc0 + acc1) + (acc2 + acc3);
+    acc += __shfl_xor(acc, 1);
+    if (P == 4) acc += __shfl_xor(acc, 2);
+    return acc;
+}
+
+template <int L>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
+                      double* __restrict__ part, int64_t* __restrict__ counter) {
+    constexpr int CH = 8;  // sources per reaction-sum chunk
+    __shared__ float4 tile[2 * kSymTile];
+    // per-wave reaction buffers, reused for the final target-side reduction
+    constexpr int S = CH * 3 + 1;  // row stride of the lane-major reaction buffer
+    __shared__ __align__(16) double smem[(kWaves * 64 * S + 1) / 2];
+    static_assert((kWaves * 64 * S + 1) / 2 >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
+    int a, b;
+    sym_unit(nb, a, b);
+    const bool diag = (a == b);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)a * kSymTile + lane;
+    FF t[4];
+    float qi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const MixedSrc m = srcm[base + 64 * k];
+        t[k].xh = m.xh;
+        t[k].yh = m.yh;
+        t[k].zh = m.zh;
+        t[k].xl = m.xl;
+        t[k].yl = m.yl;
+        t[k].zl = m.zl;
+        qi[k] = -m.nq;
+    }
+    {
+        const float4* __restrict__ g = reinterpret_cast<const float4*>(srcm) + 2 * (int64_t)b * kSymTile;
+        for (int q = threadIdx.x; q < 2 * kSymTile; q += 256) tile[q] = g[q];
+    }
+    __syncthreads();
+    const MixedSrc* mine = reinterpret_cast<const MixedSrc*>(tile) + wave * 64;
+    double sx[4], sy[4], sz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sx[k] = sy[k] = sz[k] = 0.0;
+    float* jb = reinterpret_cast<float*>(smem) + wave * 64 * S;
+    for (int s0 = 0; s0 < 64; s0 += CH) {
+        float fx[4], fy[4], fz[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+#pragma unroll 2
+        for (int uu = 0; uu < CH; ++uu) {
+            const MixedSrc m = mine[s0 + uu];
+            float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float dx = (m.xh - t[k].xh) + (m.xl - t[k].xl);
+                const float dy = (m.yh - t[k].yh) + (m.yl - t[k].yl);
+                const float dz = (m.zh - t[k].zh) + (m.zl - t[k].zl);
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, m.r2floor)));
+                const float y = __builtin_amdgcn_rsqf(r2);
+                const float y3 = (y * y) * y;
+                const float wi = m.nq * y3;  // -q_j r^-3
+                fx[k] = fmaf(wi, dx, fx[k]);
+                fy[k] = fmaf(wi, dy, fy[k]);
+                fz[k] = fmaf(wi, dz, fz[k]);
+                if (!diag) {
+                    const float wj = qi[k] * y3;  // q_i r^-3
+                    tx = fmaf(wj, dx, tx);
+                    ty = fmaf(wj, dy, ty);
+                    tz = fmaf(wj, dz, tz);
+                }
+            }
+            if (!diag) {
+                jb[lane * S + 3 * uu + 0] = tx;
+                jb[lane * S + 3 * uu + 1] = ty;
+                jb[lane * S + 3 * uu + 2] = tz;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sx[k] += (double)fx[k];
+            sy[k] += (double)fy[k];
+            sz[k] += (double)fz[k];
+        }
+        if (!diag) {
+            // the wave's LDS writes are visible to all its lanes after this
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double tot = column_sum64<CH * 3, 2>(jb, lane);
+            const int col = lane >> 1;
+            if ((lane & 1) == 0 && col < CH * 3) {
+                const int uu = col / 3, c = col - 3 * uu;
+                const int64_t j = (int64_t)b * kSymTile + wave * 64 + s0 + uu;
+                part[((int64_t)a * 3 + c) * n_pad + j] = tot;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();  // every wave is done with its reaction buffer
+    reduce_store_in<4>(sx, sy, sz, part, b, n, n_pad, base, smem);
+    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
+}
+
+template <int DUMMY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
+                    int nb, int64_t n_pad, double* __restrict__ part,
+                    int64_t* __restrict__ counter) {
+    constexpr int CH = 4;
+    constexpr int S = CH * 3 + 1;
+    __shared__ double smem[kWaves * 64 * S];
+    static_assert(kWaves * 64 * S >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
+    int a, b;
+    sym_unit(nb, a, b);
+    const bool diag = (a == b);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t base = (int64_t)a * kSymTile + lane;
+    double xi[4], yi[4], zi[4], nqi[4], sx[4], sy[4], sz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double4 p = src[base + 64 * k];
+        xi[k] = p.x;
+        yi[k] = p.y;
+        zi[k] = p.z;
+        nqi[k] = -1.5 * qe[base + 64 * k];
+        sx[k] = sy[k] = sz[k] = 0.0;
+    }
+    double* jb = smem + wave * 64 * S;
+    const int64_t j0 = (int64_t)b * kSymTile + wave * 64;
+    for (int s0 = 0; s0 < 64; s0 += CH) {
+#pragma unroll 2
+        for (int uu = 0; uu < CH; ++uu) {
+            const double4 p = src[j0 + s0 + uu];
+            double tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double dx = p.x - xi[k], dy = p.y - yi[k], dz = p.z - zi[k];
+                const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, kR2FloorF64)));
+                const double y = __builtin_amdgcn_rsq(r2);
+                const double a2 = y * y;
+                const double g = fma(r2, a2, -5.0 / 3.0);
+                const double c = (a2 * y) * g;   // -(2/3) r^-3 (one Newton correction)
+                const double wi = c * p.w;       // 1.5 q_j c = -q_j r^-3
+                sx[k] = fma(wi, dx, sx[k]);
+                sy[k] = fma(wi, dy, sy[k]);
+                sz[k] = fma(wi, dz, sz[k]);
+                if (!diag) {
+                    const double wj = c * nqi[k];  // -1.5 q_i c = q_i r^-3
+                    tx = fma(wj, dx, tx);
+                    ty = fma(wj, dy, ty);
+                    tz = fma(wj, dz, tz);
+                }
+            }
+            if (!diag) {
+                jb[lane * S + 3 * uu + 0] = tx;
+                jb[lane * S + 3 * uu + 1] = ty;
+                jb[lane * S + 3 * uu + 2] = tz;
+            }
+        }
+        if (!diag) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double tot = column_sum64<CH * 3, 4>(jb, lane);
+            const int col = lane >> 2;
+            if ((lane & 3) == 0 && col < CH * 3) {
+                const int uu = col / 3, c = col - 3 * uu;
+                part[((int64_t)a * 3 + c) * n_pad + j0 + s0 + uu] = tot;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();  // every wave is done with its reaction buffer
+    reduce_store_in<4>(sx, sy, sz, part, b, n, n_pad, base, smem);
+    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
 // Per-ion epilogue of a step (or a plain force evaluation): reduce the slice
@@ -791,6 +1031,16 @@ hipError_t launch_pack_mixed(const DevState& s, hipStream_t st) {
 hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, bool count_step,
                        hipStream_t st) {
     int64_t* ctr = count_step ? s.counter : nullptr;
+    if (ls.symmetric) {
+        const int nb = sym_tiles(s.n);
+        const unsigned units = (unsigned)(nb * (nb + 1) / 2);
+        if (precision == 0) {
+            k_pair_f64_sym<0><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+        } else {
+            k_pair_mixed_sym<8><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+        }
+        return hipGetLastError();
+    }
     if (precision == 0) {
         switch (ls.i_per_lane) {
             case 1: return pair_f64_launch<1>(s, ls, ctr, st);

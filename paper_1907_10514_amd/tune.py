@@ -75,10 +75,14 @@ def single_candidates(n: int, precision: int):
     js = [j for j in (1, 2, 4, 8, 12, 16, 24, 32, 48, 64)]
     if precision == L.LION_FP64:
         for i, j in itertools.product((1, 2, 4), js):
-            yield dict(i_per_lane=i, j_split=j)
+            yield dict(i_per_lane=i, j_split=j, symmetric=1)
+        if (n + 255) // 256 <= 128:
+            yield dict(symmetric=2)
     elif precision == L.LION_MIXED_F64ACC:
         for i, j, fl, lds in itertools.product((1, 2, 4), js, (8, 16), (1, 2)):
-            yield dict(i_per_lane=i, j_split=j, flush_len=fl, lds_sources=lds)
+            yield dict(i_per_lane=i, j_split=j, flush_len=fl, lds_sources=lds, symmetric=1)
+        if (n + 255) // 256 <= 128:
+            yield dict(symmetric=2)
     else:
         for i, j, lds in itertools.product((1, 2, 4), js, (1, 2)):
             yield dict(i_per_lane=i, j_split=j, lds_sources=lds)
@@ -90,32 +94,36 @@ def _cloud(n, seed=12345, sigma=200e-6):
     return x, y, z
 
 
-def tune_single(n: int, precision: int, reps: int = 20, verbose: bool = True) -> dict:
+def tune_single(n: int, precision: int, reps: int = 20, verbose: bool = True,
+                top_steps: int = 12, step_reps: int = 1000) -> dict:
     """Time every candidate for a single trap of n ions; returns the best entry."""
     e, _, amu = L.lion_constants()
     mass = np.full(n, 40 * amu)
     charge = np.full(n, e)
     x, y, z = _cloud(n)
     zeros = np.zeros(n)
-    sim = L.Simulation(mass, charge, precision, stream=None)
+    sim = L.Simulation(mass, charge, precision, stream=None, autotuned=False)
+    sim.set_trap(9.0, 2 * np.pi * 3.85e6, 0.24, 0.5e-3, 1e-3, 0.25)
     sim.set_state(x, y, z, zeros, zeros, zeros)
     # validation cloud (smaller) against the FP64 path
     nv = min(n, 2048)
     xv, yv, zv = _cloud(nv, seed=7)
-    ref = L.Simulation(np.full(nv, 40 * amu), np.full(nv, e), L.LION_FP64)
+    ref = L.Simulation(np.full(nv, 40 * amu), np.full(nv, e), L.LION_FP64, autotuned=False)
     ref.set_state(xv, yv, zv, np.zeros(nv), np.zeros(nv), np.zeros(nv))
     a_ref = np.array(ref.compute_accel())
     ref.close()
     k_scale = (e / (40 * amu)) * e / (4 * np.pi * 8.8541878128e-12)
     sc = k_scale * _scale(xv, yv, zv, np.ones(nv))
-    val = L.Simulation(np.full(nv, 40 * amu), np.full(nv, e), precision)
+    val = L.Simulation(np.full(nv, 40 * amu), np.full(nv, e), precision, autotuned=False)
     val.set_state(xv, yv, zv, np.zeros(nv), np.zeros(nv), np.zeros(nv))
     results = []
     for cfg in single_candidates(n, precision):
         try:
             sim.set_config(**cfg)
-            val.set_config(**{k: v for k, v in cfg.items() if k != "j_split"},
-                           j_split=min(cfg["j_split"], max(1, (nv + 63) // 64)))
+            vcfg = dict(cfg)
+            if "j_split" in vcfg:
+                vcfg["j_split"] = min(cfg["j_split"], max(1, (nv + 63) // 64))
+            val.set_config(**vcfg)
         except L.LionError:
             continue
         a = np.array(val.compute_accel())
@@ -126,10 +134,26 @@ def tune_single(n: int, precision: int, reps: int = 20, verbose: bool = True) ->
         if verbose:
             print(f"  {cfg} -> {ms * 1e3:8.2f} us  M1 {err:.2e}{'' if ent['ok'] else '  REJECT'}",
                   flush=True)
+    # the fastest pair kernels are timed again as whole steps (pair + epilogue +
+    # launch gaps): more source slices shorten the pair kernel but lengthen the
+    # epilogue's partial-sum reads
+    import torch
+
+    ok = sorted([r for r in results if r["ok"]], key=lambda r: r["pair_ms"])[:top_steps]
+    dt = 1.0 / 3.85e6 / 20
+    for r in ok:
+        sim.set_config(**r["config"])
+        sim.step(200, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(step_reps, dt)
+        torch.cuda.synchronize()
+        r["step_ms"] = 1e3 * (time.perf_counter() - t0) / step_reps
+        if verbose:
+            print(f"  step {r['config']} -> {r['step_ms'] * 1e3:8.2f} us/step", flush=True)
     sim.close()
     val.close()
-    ok = [r for r in results if r["ok"]]
-    best = min(ok, key=lambda r: r["pair_ms"])
+    best = min(ok, key=lambda r: r["step_ms"])
     return dict(best=best, n=n, precision=precision, candidates=len(results))
 
 
@@ -140,7 +164,8 @@ def tune_batch(n_per_trap, precision: int, steps: int = 100, verbose: bool = Tru
     x, y, z = _cloud(n, sigma=20e-6)
     res = []
     for block in (256, 512, 1024):
-        sim = L.Simulation(np.full(n, 40 * amu), np.full(n, e), precision, n_per_trap=npt)
+        sim = L.Simulation(np.full(n, 40 * amu), np.full(n, e), precision, n_per_trap=npt,
+                           autotuned=False)
         sim.set_config(batch_block=block)
         sim.set_trap(9.0, 2 * np.pi * 3.85e6, 0.24, 0.5e-3, 1e-3, 0.25)
         sim.set_state(x, y, z, np.zeros(n), np.zeros(n), np.zeros(n))

@@ -126,6 +126,68 @@ def test_accel_parity_full_size_sampled(torch_gpu, oracle_mod, prec):
     sim.close()
 
 
+SYM_SIZES = [1, 2, 3, 100, 255, 256, 257, 1000, 4097, 8191]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", SYM_SIZES)
+def test_accel_parity_pair_once(torch_gpu, oracle_mod, n, prec):
+    """The kernels that evaluate each unordered pair once (tile pairs, reaction
+    sums through LDS) meet the same bars, for full and ragged tiles."""
+    w = li.random_cloud(n, seed=300 + n, sigma=60e-6, light_fraction=0.2,
+                        charge_e=np.random.default_rng(n).choice([1, 1, 2, -1], n))
+    sim = _sim(w, prec, oracle_mod, symmetric=2)
+    assert sim.config()["symmetric"] == 2
+    a = sim.compute_accel()
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    err = _m1(a, r, sc)
+    print(f"pair-once n={n} {prec} M1={err:.3e}")
+    assert err <= TOL[prec]
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
+    """Pair-once kernels at 16384 ions (sampled targets) and over 45 steps:
+    bitwise reproducible and equal to the all-pairs kernels within the bar."""
+    w = li.mixed16384()
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    sim = _sim(w, prec, oracle_mod, symmetric=2)
+    a = sim.compute_accel()
+    idx = np.random.default_rng(1).choice(w.n, 512, replace=False)
+    rx, ry, rz, sc = oracle_mod.accel_at(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0, idx)
+    err = _m1((a[0][idx], a[1][idx], a[2][idx]), (rx, ry, rz), sc)
+    print(f"pair-once N=16384 {prec} sampled M1={err:.3e}")
+    assert err <= TOL[prec]
+    outs = []
+    for sym in (2, 2, 1):
+        s2 = _sim(w, prec, oracle_mod, symmetric=sym)
+        s2.step(45, w.traps[0].dt)
+        outs.append(s2.get_state()[0])
+        s2.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    ext = np.max(np.abs(w.x))
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(outs[0][k] - outs[2][k])) < tol * ext
+    sim.close()
+
+
+def test_pair_once_rejected_where_unsupported(torch_gpu, oracle_mod):
+    from paper_1907_10514_amd import LionError
+    from paper_1907_10514_amd import lion as L
+
+    w = li.random_cloud(300, seed=1)
+    sim = _sim(w, "mixed_kahan", oracle_mod)
+    with pytest.raises(LionError) as ei:
+        sim.set_config(symmetric=2)
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    sim.close()
+
+
 def test_crystal8_full_run_matches_oracle(torch_gpu, oracle_mod):
     """8 ions, q=0.3, gamma=1e5/s, 20000 steps in FP64: the final state of the
     GPU run equals the oracle's to roundoff growth."""
