@@ -133,6 +133,39 @@ def time_batch(torch, precision, steps, warmup, seq_steps):
                 ordered_pairs_per_step=pairs)
 
 
+def time_clusters(torch, precision, steps, warmup, reps):
+    """The 65536-ion cloud with 64 rigid clusters: intra-cluster pairs left out
+    of the pair sum (body-id exclusion mask); per-ion steps."""
+    import numpy as np
+
+    import lion_inputs as li
+    from paper_1907_10514_amd import runner
+
+    w = li.clusters65536()
+    body = w.notes["body"]
+    sizes = np.bincount(body[body >= 0])
+    pairs = w.n * (w.n - 1) - int(np.sum(sizes * (sizes - 1)))
+    sim = runner.simulation_for(w, precision=precision)
+    sim.set_bodies(body)
+    dt = w.traps[0].dt
+    sim.step(warmup, dt)
+    sync(torch)
+    t0 = time.perf_counter()
+    sim.step(steps, dt)
+    sync(torch)
+    el = time.perf_counter() - t0
+    finite = sim.check_finite() == 0
+    kernel_ms = sim.time_pair_kernel(reps)
+    cfg = sim.config()
+    sim.close()
+    return dict(pairs_per_s=pairs * steps / el, steps_per_s=steps / el,
+                ms_per_step=1e3 * el / steps, pair_kernel_ms=kernel_ms,
+                pair_kernel_tflops=FLOP_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12,
+                pct_vector_peak=100.0 * FLOP_PER_PAIR * pairs * steps / el / 1e12
+                / PEAK_TFLOPS[precision], ordered_pairs_per_step=pairs, n_ions=w.n,
+                finite=finite, launch=cfg)
+
+
 def cpu_baseline(w, seconds):
     """The FP64 oracle on the host cores, on a bounded number of steps of the
     same workload."""
@@ -195,6 +228,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-clusters", action="store_true")
+    ap.add_argument("--cluster-steps", type=int, default=200)
     ap.add_argument("--precisions", default="fp64,mixed,mixed_kahan")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only launch the benchmarked pair kernels a few times and a 256 MiB "
@@ -282,6 +317,15 @@ def main():
         if "mixed" in out["batch512"] and "fp64" in res:
             out["batch512"]["speedup_batched_mixed_over_single_fp64_n16384"] = (
                 out["batch512"]["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"])
+    if not args.no_clusters:
+        out["clusters65536"] = {}
+        for p in ("mixed", "fp64"):
+            if p not in precs:
+                continue
+            log(f"[bench] clusters65536 {p}: {args.cluster_steps} steps")
+            out["clusters65536"][p] = time_clusters(torch, p, args.cluster_steps, 20, 10)
+            log(f"[bench] clusters65536 {p}: {out['clusters65536'][p]['pairs_per_s']:.4e} pairs/s, "
+                f"pair kernel {out['clusters65536'][p]['pair_kernel_ms']:.3f} ms")
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

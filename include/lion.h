@@ -97,6 +97,17 @@ int lion_set_state(lion_sim *sim, const double *x, const double *y, const double
 int lion_set_trap(lion_sim *sim, int32_t trap, double V_rf, double Omega_rad_s, double U_dc,
                   double r0, double z0, double kappa);
 
+/* Rigid bodies as an exclusion mask (section "Charged rigid body": ions of a
+ * group are bound together, so their mutual Coulomb forces are internal to the
+ * body).  body_id[i] >= 0 names the body of ion i, -1 marks a free ion; pairs
+ * of ions with the same body id are left out of the pair sum.  NULL (or all
+ * -1) clears the mask.  Ions keep per-ion integration (rigid-body integration
+ * is not part of this library); energies still count every pair.  Fastest
+ * when each body's ions are consecutive in index order.  Single-trap handles
+ * with the all-pairs kernels only (LION_ERR_UNSUPPORTED otherwise); ids < -1
+ * -> LION_ERR_ARG.  Recomputes the cached accelerations. */
+int lion_set_bodies(lion_sim *sim, const int32_t *body_id);
+
 /* Laser cooling (section "Cooling the motion of ions") as an isotropic viscous
  * force -M gamma v on every ion of trap `trap` (-1 = every trap); gamma in 1/s,
  * >= 0 and finite.  Applied as exact exp(-gamma dt/2) velocity scalings. */

@@ -15,6 +15,8 @@ for measurement:
                      at random, q=0.25 (for Ca-40), sigma 200 um, 10 mK per species
 * ``batch512``       512 independent traps of N ~ U{2..512}, q ~ U[0.1, 0.6],
                      a ~ U[-0.01, 0] (Mathieu-stable draws only), otherwise as crystal8
+* ``clusters65536``  64 rigid clusters of 512 Ca-40 ions (uniform in 5 um balls about
+                     Gaussian centres, sigma 400 um) + 32768 free Ca-40 ions, q=0.3
 
 Trap settings are given as Mathieu coefficients (q_x, a_x) for the reference ion
 (40 u, +e); each side converts them to voltages with its own implementation of
@@ -173,6 +175,33 @@ def batch512(n_traps: int = 512, n_min: int = 2, n_max: int = 512, seed: int = 3
                     "mixed", notes=dict(seed=seed, rejected=rejected, sizes=sizes))
 
 
+def clusters65536(n_clusters: int = 64, per_cluster: int = 512, n_free: int = 32768,
+                  seed: int = 4, cluster_radius: float = 5e-6, sigma: float = 400e-6) -> Workload:
+    """Rigid clusters of Ca-40 ions, each uniform in a ball of radius 5 um about a
+    Gaussian (sigma 400 um) centre, plus free Ca-40 ions (sigma 400 um); q = 0.3,
+    a = -0.001, 10 mK.  Cluster ions come first, each cluster's ions consecutive;
+    notes["body"] holds the body id of every ion (-1 = free)."""
+    rng = _rng(seed)
+    centres = rng.normal(0.0, sigma, size=(n_clusters, 3))
+    d = rng.normal(size=(n_clusters, per_cluster, 3))
+    d /= np.linalg.norm(d, axis=2, keepdims=True)
+    r = cluster_radius * rng.uniform(0.0, 1.0, size=(n_clusters, per_cluster, 1)) ** (1.0 / 3.0)
+    pos_c = (centres[:, None, :] + d * r).reshape(-1, 3)
+    pos_f = rng.normal(0.0, sigma, size=(n_free, 3))
+    pos = np.concatenate([pos_c, pos_f])
+    n = pos.shape[0]
+    mass = np.full(n, REF_MASS)
+    charge = np.full(n, REF_CHARGE)
+    vx, vy, vz = thermal_velocities(rng, mass, 10e-3)
+    body = np.concatenate([np.repeat(np.arange(n_clusters, dtype=np.int32), per_cluster),
+                           np.full(n_free, -1, dtype=np.int32)])
+    trap = TrapSpec(q_x=0.3, a_x=-0.001, gamma=1e5)
+    return Workload("clusters65536", mass, charge, pos[:, 0].copy(), pos[:, 1].copy(),
+                    pos[:, 2].copy(), vx, vy, vz, [trap], np.array([0, n], dtype=np.int64), 5000,
+                    "mixed", notes=dict(seed=seed, body=body, n_clusters=n_clusters,
+                                        per_cluster=per_cluster))
+
+
 def random_cloud(n: int, seed: int, sigma: float = 50e-6, temperature: float = 10e-3,
                  light_fraction: float = 0.0, charge_e=None) -> Workload:
     """Small test cloud in the crystal8 trap; optional per-ion charges in units of e."""
@@ -188,4 +217,5 @@ WORKLOADS = {
     "crystal1024": crystal1024,
     "mixed16384": mixed16384,
     "batch512": batch512,
+    "clusters65536": clusters65536,
 }

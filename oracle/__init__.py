@@ -88,6 +88,13 @@ def bind(path: str):
     lib.oracle_accel_at.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, i64, lp, dp,
                                     dp, dp, dp]
     lib.oracle_accel_at.restype = None
+    lib.oracle_accel_bodies.argtypes = [i64, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int32),
+                                        tp, ctypes.c_double, dp, dp, dp, dp]
+    lib.oracle_accel_bodies.restype = i64
+    lib.oracle_accel_bodies_at.argtypes = [i64, dp, dp, dp, dp, dp,
+                                           ctypes.POINTER(ctypes.c_int32), tp, ctypes.c_double,
+                                           i64, lp, dp, dp, dp, dp]
+    lib.oracle_accel_bodies_at.restype = None
     lib.oracle_step.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
     lib.oracle_step.restype = i64
@@ -173,6 +180,36 @@ def accel_at(x, y, z, charge, mass, trap: Trap, t: float, idx):
     _load().oracle_accel_at(x.size, _d(x), _d(y), _d(z), _d(q), _d(m), ctypes.byref(tr), float(t),
                             k, ii.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(ax), _d(ay),
                             _d(az), _d(sc))
+    return ax, ay, az, sc
+
+
+def accel_bodies(x, y, z, charge, mass, body, trap: Trap, t: float):
+    """``accel`` with the pairs inside each rigid body left out (body[i] >= 0
+    names ion i's body, -1 a free ion).  Returns (ax, ay, az, scale)."""
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    b = np.ascontiguousarray(body, dtype=np.int32)
+    n = x.size
+    ax, ay, az, sc = np.empty(n), np.empty(n), np.empty(n), np.empty(n)
+    tr = trap._c()
+    _load().oracle_accel_bodies(n, _d(x), _d(y), _d(z), _d(q), _d(m),
+                                b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(tr),
+                                float(t), _d(ax), _d(ay), _d(az), _d(sc))
+    return ax, ay, az, sc
+
+
+def accel_bodies_at(x, y, z, charge, mass, body, trap: Trap, t: float, idx):
+    """``accel_bodies`` for the targets ``idx`` only (every source counts)."""
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    b = np.ascontiguousarray(body, dtype=np.int32)
+    ii = np.ascontiguousarray(idx, dtype=np.int64)
+    k = ii.size
+    ax, ay, az, sc = np.empty(k), np.empty(k), np.empty(k), np.empty(k)
+    tr = trap._c()
+    _load().oracle_accel_bodies_at(x.size, _d(x), _d(y), _d(z), _d(q), _d(m),
+                                   b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   ctypes.byref(tr), float(t), k,
+                                   ii.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(ax),
+                                   _d(ay), _d(az), _d(sc))
     return ax, ay, az, sc
 
 

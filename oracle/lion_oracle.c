@@ -165,6 +165,89 @@ void oracle_accel_at(int64_t n, const double *x, const double *y, const double *
     }
 }
 
+/* Acceleration with pairs inside rigid bodies left out (section "Charged rigid
+ * body": ions of one group are bound together, so their mutual forces are
+ * internal to the body).  body[i] >= 0 names the body of ion i, -1 a free ion;
+ * pairs with body[i] == body[j] >= 0 are skipped.  Also returns the rounding
+ * scale of each a_i over the pairs that remain (as oracle_accel_scale). */
+int64_t oracle_accel_bodies(int64_t n, const double *x, const double *y, const double *z,
+                            const double *charge, const double *mass, const int32_t *body,
+                            const oracle_trap *tp, double t, double *ax, double *ay, double *az,
+                            double *scale) {
+    const double ke = oracle_coulomb_constant();
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    double c = cos(tp->Omega * t);
+    int64_t coincident = 0;
+#pragma omp parallel for schedule(static) reduction(+ : coincident) if (n >= 256)
+    for (int64_t i = 0; i < n; ++i) {
+        nsum sx = {0, 0}, sy = {0, 0}, sz = {0, 0}, sm = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            if (body[i] >= 0 && body[j] == body[i]) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) {
+                ++coincident;
+                continue;
+            }
+            double s = charge[j] * (1.0 / (r2 * sqrt(r2)));
+            nsum_add(&sx, s * dx);
+            nsum_add(&sy, s * dy);
+            nsum_add(&sz, s * dz);
+            nsum_add(&sm, fabs(charge[j]) / r2);
+        }
+        double ex, ey, ez;
+        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
+        double qm = charge[i] / mass[i];
+        ax[i] = qm * (ke * nsum_get(&sx) + ex);
+        ay[i] = qm * (ke * nsum_get(&sy) + ey);
+        az[i] = qm * (ke * nsum_get(&sz) + ez);
+        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
+        scale[i] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&sm) + erf + edc);
+    }
+    return coincident;
+}
+
+/* oracle_accel_bodies for the selected targets idx[0..m) only (every source
+ * still counts); used to check very large clouds on a sample of ions. */
+void oracle_accel_bodies_at(int64_t n, const double *x, const double *y, const double *z,
+                            const double *charge, const double *mass, const int32_t *body,
+                            const oracle_trap *tp, double t, int64_t m, const int64_t *idx,
+                            double *ax, double *ay, double *az, double *scale) {
+    const double ke = oracle_coulomb_constant();
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    double c = cos(tp->Omega * t);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = idx[k];
+        nsum sx = {0, 0}, sy = {0, 0}, sz = {0, 0}, sm = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            if (body[i] >= 0 && body[j] == body[i]) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double s = charge[j] * (1.0 / (r2 * sqrt(r2)));
+            nsum_add(&sx, s * dx);
+            nsum_add(&sy, s * dy);
+            nsum_add(&sz, s * dz);
+            nsum_add(&sm, fabs(charge[j]) / r2);
+        }
+        double ex, ey, ez;
+        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
+        double qm = charge[i] / mass[i];
+        ax[k] = qm * (ke * nsum_get(&sx) + ex);
+        ay[k] = qm * (ke * nsum_get(&sy) + ey);
+        az[k] = qm * (ke * nsum_get(&sz) + ez);
+        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
+        scale[k] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&sm) + erf + edc);
+    }
+}
+
 /* Rounding scale of a_i: (|Q_i|/M_i)(k_e sum_j |Q_j|/r_ij^2 + |E_rf,i| + |E_dc,i|),
  * the sum of the magnitudes of every contribution to a_i. */
 void oracle_accel_scale(int64_t n, const double *x, const double *y, const double *z,

@@ -36,6 +36,9 @@ struct lion_sim {
     std::vector<int64_t> offsets;   // [n_traps + 1]
     std::vector<double> mass, charge;
     bool state_set = false;
+    bool has_bodies = false;
+    char* ws = nullptr;
+    size_t body_off[3] = {0, 0, 0};
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (chunk length, kind)
     std::string err;
 };
@@ -68,7 +71,7 @@ int slices_for(int64_t n) {
 
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
-        flags, total;
+        flags, body_code, body_gmin, body_gmax, total;
 };
 
 Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
@@ -95,6 +98,9 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.order = take((size_t)n_traps * sizeof(int32_t));
     L.counter = take(sizeof(int64_t));
     L.flags = take(4 * sizeof(int32_t));
+    L.body_code = take(np * sizeof(int32_t));
+    L.body_gmin = take(np / 16 * sizeof(int32_t));
+    L.body_gmax = take(np / 16 * sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -127,7 +133,7 @@ void default_shape(lion_sim* s) {
     ls.batch_block = s->cfg.batch_block > 0 ? s->cfg.batch_block : 256;
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
     const int nb = lion::sym_tiles(n);
-    ls.symmetric = (s->cfg.symmetric == 2 && nb <= lion::kMaxSymTiles) ? 1 : 0;
+    ls.symmetric = (s->cfg.symmetric == 2 && nb <= lion::kMaxSymTiles && !s->has_bodies) ? 1 : 0;
     const int64_t n64 = round_up(n, 64);
     const int64_t blocks_x = (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane);
     int j;
@@ -290,6 +296,13 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     d.order = (int32_t*)(base + L.order);
     d.counter = (int64_t*)(base + L.counter);
     d.flags = (int32_t*)(base + L.flags);
+    d.body_code = nullptr;  // set by lion_set_bodies
+    d.body_gmin = nullptr;
+    d.body_gmax = nullptr;
+    s->body_off[0] = L.body_code;
+    s->body_off[1] = L.body_gmin;
+    s->body_off[2] = L.body_gmax;
+    s->ws = base;
     s->j_max = batched ? 1 : j_max_for(n);
     s->cfg.chunk_steps = 100;
     s->cfg.use_graph = 1;
@@ -428,6 +441,53 @@ int lion_set_trap(lion_sim* s, int32_t trap, double V_rf, double Omega, double U
     if (rc) return rc;
     if (s->state_set) return refresh_accel(s);
     return LION_OK;
+}
+
+int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (s->batched) return fail(s, LION_ERR_UNSUPPORTED, "rigid-body exclusion is for single traps");
+    const int64_t n = s->n, np = s->d.n_pad;
+    bool any = false;
+    if (body_id) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (body_id[i] < -1) return fail(s, LION_ERR_ARG, "body ids must be >= -1");
+            any = any || body_id[i] >= 0;
+        }
+    }
+    if (s->cfg.symmetric == 2 && any)
+        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels do not apply body exclusion");
+    LION_HIP(s, hipSetDevice(s->device));
+    (void)hipStreamSynchronize(s->stream);
+    clear_graphs(s);  // captured launches carry the mask pointers
+    if (!any) {
+        s->has_bodies = false;
+        s->d.body_code = s->d.body_gmin = s->d.body_gmax = nullptr;
+        default_shape(s);
+        return s->state_set ? refresh_accel(s) : LION_OK;
+    }
+    std::vector<int32_t> code(np), gmin(np / 16, 0x7fffffff), gmax(np / 16, -1);
+    for (int64_t i = 0; i < np; ++i) {
+        const int32_t b = i < n ? body_id[i] : -1;
+        code[i] = b >= 0 ? b : (int32_t)(-1 - i);
+        if (b >= 0) {
+            gmin[i / 16] = std::min(gmin[i / 16], b);
+            gmax[i / 16] = std::max(gmax[i / 16], b);
+        }
+    }
+    int32_t* dc = (int32_t*)(s->ws + s->body_off[0]);
+    int32_t* dmin = (int32_t*)(s->ws + s->body_off[1]);
+    int32_t* dmax = (int32_t*)(s->ws + s->body_off[2]);
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipMemcpyAsync(dc, code.data(), np * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(dmin, gmin.data(), np / 16 * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(dmax, gmax.data(), np / 16 * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    s->d.body_code = dc;
+    s->d.body_gmin = dmin;
+    s->d.body_gmax = dmax;
+    s->has_bodies = true;
+    default_shape(s);
+    return s->state_set ? refresh_accel(s) : LION_OK;
 }
 
 int lion_set_damping(lion_sim* s, int32_t trap, double gamma) {
@@ -600,6 +660,8 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 32768");
+    if (c->symmetric == 2 && s->has_bodies)
+        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels do not apply body exclusion");
     if (c->symmetric == 2 && s->precision == LION_MIXED_KAHAN)
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels exist for FP64 and MIXED_F64ACC");
     (void)hipSetDevice(s->device);

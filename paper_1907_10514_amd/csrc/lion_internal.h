@@ -74,6 +74,10 @@ struct DevState {
     int32_t* order;   // [n_traps] launch order (largest trap first)
     int64_t* counter; // step index inside the current call
     int32_t* flags;   // [4] diagnostics (non-finite count)
+    // rigid-body exclusion (all NULL when no bodies are set)
+    int32_t* body_code;  // [n_pad] body id >= 0, or -1 - i for a free ion i
+    int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions
+    int32_t* body_gmax;  // [n_pad / 16] largest body id (-1 if none)
 };
 
 struct LaunchShape {

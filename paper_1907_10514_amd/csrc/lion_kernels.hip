@@ -86,12 +86,55 @@ __device__ __forceinline__ void pair_f32(const MixedSrc& q, const FF& t, float& 
     sz = fmaf(w, dz, sz);
 }
 
+// As pair_f64 / pair_f32, with the term dropped when source and target share a body.
+__device__ __forceinline__ void pair_f64_masked(const double4 p, double xi, double yi,
+                                                double zi, int ci, int cj, double& sx,
+                                                double& sy, double& sz) {
+    const double dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, kR2FloorF64)));
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double a = y * y;
+    const double g = fma(r2, a, -5.0 / 3.0);
+    const double w = (ci == cj) ? 0.0 : (a * y) * p.w * g;
+    sx = fma(w, dx, sx);
+    sy = fma(w, dy, sy);
+    sz = fma(w, dz, sz);
+}
+
 // Kahan-compensated FP32 accumulation of one term.
 __device__ __forceinline__ void kahan_add(float term, float& s, float& c) {
     const float y = term - c;
     const float t = s + y;
     c = (t - s) - y;
     s = t;
+}
+
+// Rigid-body exclusion.  code[i] is ion i's body id (>= 0) or a negative
+// number unique to the ion, so code[i] == code[j] (i != j) exactly when both
+// ions belong to one body.  gmin/gmax give, per group of 16 consecutive ions,
+// the range of body ids >= 0 present (gmin > gmax when there are none); a
+// 16-source group whose range misses the targets' range needs no per-pair test.
+struct BodyMask {
+    const int32_t* __restrict__ code;
+    const int32_t* __restrict__ gmin;
+    const int32_t* __restrict__ gmax;
+};
+
+// Body-id range of the 64*I targets starting at base0 (a multiple of 64).
+template <int I>
+__device__ __forceinline__ void target_body_range(const BodyMask& bm, int64_t base0, int& lo,
+                                                  int& hi) {
+    lo = 0x7fffffff;
+    hi = -1;
+    for (int g = 0; g < 4 * I; ++g) {
+        lo = min(lo, bm.gmin[base0 / 16 + g]);
+        hi = max(hi, bm.gmax[base0 / 16 + g]);
+    }
+}
+
+__device__ __forceinline__ bool group_may_share_body(const BodyMask& bm, int j16, int lo,
+                                                     int hi) {
+    return bm.code && bm.gmin[j16] <= hi && bm.gmax[j16] >= lo;
 }
 
 __device__ __forceinline__ FF split_ff(double x, double y, double z) {
@@ -259,15 +302,17 @@ template <int I>
 __global__ __launch_bounds__(256) void k_pair_f64(const double4* __restrict__ src, int64_t n,
                                                   int n64, int jps, int64_t n_pad,
                                                   double* __restrict__ part,
-                                                  int64_t* __restrict__ counter) {
+                                                  int64_t* __restrict__ counter, BodyMask bm) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t base = (int64_t)blockIdx.x * (64 * I) + lane;
+    const int64_t base0 = (int64_t)blockIdx.x * (64 * I);
+    const int64_t base = base0 + lane;
     const int s = blockIdx.y;
     const int part_len = jps / kWaves;
     const int jb = min(s * jps + wave * part_len, n64);
     const int je = min(jb + part_len, n64);
     double xi[I], yi[I], zi[I], sx[I], sy[I], sz[I];
+    int ci[I];
 #pragma unroll
     for (int k = 0; k < I; ++k) {
         const double4 p = src[base + 64 * k];
@@ -275,15 +320,30 @@ __global__ __launch_bounds__(256) void k_pair_f64(const double4* __restrict__ sr
         yi[k] = p.y;
         zi[k] = p.z;
         sx[k] = sy[k] = sz[k] = 0.0;
+        ci[k] = bm.code ? bm.code[base + 64 * k] : 0;
     }
-    for (int j = jb; j < je; j += 4) {
-        const double4 p0 = src[j], p1 = src[j + 1], p2 = src[j + 2], p3 = src[j + 3];
+    int tlo = 0, thi = -1;
+    if (bm.code) target_body_range<I>(bm, base0, tlo, thi);
+    for (int j16 = jb; j16 < je; j16 += 16) {
+        if (!group_may_share_body(bm, j16 / 16, tlo, thi)) {
+            for (int j = j16; j < j16 + 16; j += 4) {
+                const double4 p0 = src[j], p1 = src[j + 1], p2 = src[j + 2], p3 = src[j + 3];
 #pragma unroll
-        for (int k = 0; k < I; ++k) {
-            pair_f64(p0, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
-            pair_f64(p1, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
-            pair_f64(p2, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
-            pair_f64(p3, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                for (int k = 0; k < I; ++k) {
+                    pair_f64(p0, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                    pair_f64(p1, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                    pair_f64(p2, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                    pair_f64(p3, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                }
+            }
+        } else {
+            for (int j = j16; j < j16 + 16; ++j) {
+                const double4 p0 = src[j];
+                const int cj = bm.code[j];
+#pragma unroll
+                for (int k = 0; k < I; ++k)
+                    pair_f64_masked(p0, xi[k], yi[k], zi[k], ci[k], cj, sx[k], sy[k], sz[k]);
+            }
         }
     }
     reduce_store<I>(sx, sy, sz, part, s, n, n_pad, base);
@@ -317,17 +377,23 @@ struct MixedAcc {
 };
 
 // One run of L sources from `q` (LDS or global) against I float-float targets.
-template <int I, int L, bool KAHAN, typename Src>
+// With MASK, cq[u] is the body code of source u and ci[k] that of target k;
+// terms of ions sharing a body are dropped.
+template <int I, int L, bool KAHAN, bool MASK = false, typename Src>
 __device__ __forceinline__ void mixed_run(const Src* __restrict__ q, const FF (&t)[I],
-                                          MixedAcc<I, KAHAN>& A) {
+                                          MixedAcc<I, KAHAN>& A,
+                                          const int32_t* __restrict__ cq = nullptr,
+                                          const int* ci = nullptr) {
     if (KAHAN) {
 #pragma unroll
         for (int u = 0; u < L; ++u) {
             const MixedSrc m = q[u];
+            const int cj = MASK ? cq[u] : 0;
 #pragma unroll
             for (int k = 0; k < I; ++k) {
                 float tx, ty, tz;
                 pair_f32_terms(m, t[k], tx, ty, tz);
+                if (MASK && ci[k] == cj) tx = ty = tz = 0.0f;
                 kahan_add(tx, A.kx[k], A.cx[k]);
                 kahan_add(ty, A.ky[k], A.cy[k]);
                 kahan_add(tz, A.kz[k], A.cz[k]);
@@ -340,8 +406,22 @@ __device__ __forceinline__ void mixed_run(const Src* __restrict__ q, const FF (&
 #pragma unroll
         for (int u = 0; u < L; ++u) {
             const MixedSrc m = q[u];
+            if (MASK) {
+                const int cj = cq[u];
 #pragma unroll
-            for (int k = 0; k < I; ++k) pair_f32(m, t[k], fx[k], fy[k], fz[k]);
+                for (int k = 0; k < I; ++k) {
+                    float tx, ty, tz;
+                    pair_f32_terms(m, t[k], tx, ty, tz);
+                    if (ci[k] != cj) {
+                        fx[k] += tx;
+                        fy[k] += ty;
+                        fz[k] += tz;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < I; ++k) pair_f32(m, t[k], fx[k], fy[k], fz[k]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < I; ++k) {
@@ -374,19 +454,32 @@ template <int I, int L, bool KAHAN>
 __global__ __launch_bounds__(256) void k_pair_mixed_s(const MixedSrc* __restrict__ srcm,
                                                       int64_t n, int n64, int jps,
                                                       int64_t n_pad, double* __restrict__ part,
-                                                      int64_t* __restrict__ counter) {
+                                                      int64_t* __restrict__ counter,
+                                                      BodyMask bm) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t base = (int64_t)blockIdx.x * (64 * I) + lane;
+    const int64_t base0 = (int64_t)blockIdx.x * (64 * I);
+    const int64_t base = base0 + lane;
     const int s = blockIdx.y;
     const int part_len = jps / kWaves;
     const int jb = min(s * jps + wave * part_len, n64);
     const int je = min(jb + part_len, n64);
     FF t[I];
     load_targets<I>(srcm, base, t);
+    int ci[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) ci[k] = bm.code ? bm.code[base + 64 * k] : 0;
+    int tlo = 0, thi = -1;
+    if (bm.code) target_body_range<I>(bm, base0, tlo, thi);
     MixedAcc<I, KAHAN> A;
     A.init();
-    for (int j = jb; j < je; j += L) mixed_run<I, L, KAHAN>(srcm + j, t, A);
+    for (int j16 = jb; j16 < je; j16 += 16) {
+        if (!group_may_share_body(bm, j16 / 16, tlo, thi)) {
+            for (int j = j16; j < j16 + 16; j += L) mixed_run<I, L, KAHAN>(srcm + j, t, A);
+        } else {
+            mixed_run<I, 16, KAHAN, true>(srcm + j16, t, A, bm.code + j16, ci);
+        }
+    }
     A.finish();
     reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
     if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
@@ -401,16 +494,23 @@ template <int I, int L, bool KAHAN>
 __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict__ srcm,
                                                       int64_t n, int n64, int jps,
                                                       int64_t n_pad, double* __restrict__ part,
-                                                      int64_t* __restrict__ counter) {
+                                                      int64_t* __restrict__ counter,
+                                                      BodyMask bm) {
     __shared__ float4 tile[2 * kTile];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * (64 * I) + lane;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t base0 = (int64_t)blockIdx.x * (64 * I);
+    const int64_t base = base0 + lane;
     const int s = blockIdx.y;
     const int jb = min(s * jps, n64);
     const int je = min(jb + jps, n64);
     FF t[I];
     load_targets<I>(srcm, base, t);
+    int ci[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) ci[k] = bm.code ? bm.code[base + 64 * k] : 0;
+    int tlo = 0, thi = -1;
+    if (bm.code) target_body_range<I>(bm, base0, tlo, thi);
     MixedAcc<I, KAHAN> A;
     A.init();
     const float4* __restrict__ g = reinterpret_cast<const float4*>(srcm);
@@ -422,7 +522,14 @@ __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict
         __syncthreads();
         const int per = cnt / kWaves;  // multiple of 16
         const MixedSrc* mine = tl + wave * per;
-        for (int u = 0; u < per; u += L) mixed_run<I, L, KAHAN>(mine + u, t, A);
+        const int g0 = j0 + wave * per;  // global index of the wave's first source
+        for (int u16 = 0; u16 < per; u16 += 16) {
+            if (!group_may_share_body(bm, (g0 + u16) / 16, tlo, thi)) {
+                for (int u = u16; u < u16 + 16; u += L) mixed_run<I, L, KAHAN>(mine + u, t, A);
+            } else {
+                mixed_run<I, 16, KAHAN, true>(mine + u16, t, A, bm.code + g0 + u16, ci);
+            }
+        }
     }
     A.finish();
     reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
@@ -662,8 +769,12 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
 
 // Per-ion epilogue of a step (or a plain force evaluation): reduce the slice
 // partials in slice order, add the trap field, then kick / damp / drift.
+// Per-ion epilogue of a step (or a plain force evaluation).  A block covers 64
+// ions with 4 waves: wave g adds the partial slots [g*per, (g+1)*per) in slot
+// order, wave 0 adds the four group sums in group order (deterministic for a
+// given number of slots), then applies the trap field and kick / damp / drift.
 template <int MODE>
-__global__ __launch_bounds__(64) void k_update(double4* __restrict__ src,
+__global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
                                                 MixedSrc* __restrict__ srcm,
                                                 double* __restrict__ vx, double* __restrict__ vy,
                                                 double* __restrict__ vz, double* __restrict__ ax,
@@ -674,15 +785,33 @@ __global__ __launch_bounds__(64) void k_update(double4* __restrict__ src,
                                                 int64_t n, int64_t n_pad, double field_scale,
                                                 const TrapDev* __restrict__ traps,
                                                 const int64_t* __restrict__ counter) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ double red[kWaves - 1][3][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int per = (j_split + kWaves - 1) / kWaves;
+    const int s0 = min(g * per, j_split), s1 = min(s0 + per, j_split);
     double Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    if (i < n) {
 #pragma unroll 4
-    for (int s = 0; s < j_split; ++s) {
-        const double* px = part + (int64_t)(3 * s) * n_pad;
-        Sx += px[i];
-        Sy += px[n_pad + i];
-        Sz += px[2 * n_pad + i];
+        for (int s = s0; s < s1; ++s) {
+            const double* px = part + (int64_t)(3 * s) * n_pad;
+            Sx += px[i];
+            Sy += px[n_pad + i];
+            Sz += px[2 * n_pad + i];
+        }
+    }
+    if (g > 0) {
+        red[g - 1][0][lane] = Sx;
+        red[g - 1][1][lane] = Sy;
+        red[g - 1][2][lane] = Sz;
+    }
+    __syncthreads();
+    if (g > 0 || i >= n) return;
+#pragma unroll
+    for (int w = 0; w < kWaves - 1; ++w) {
+        Sx += red[w][0][lane];
+        Sy += red[w][1][lane];
+        Sz += red[w][2][lane];
     }
     Sx *= field_scale;
     Sy *= field_scale;
@@ -964,11 +1093,20 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 inline int n64_of(int64_t n) { return (int)((n + 63) & ~int64_t(63)); }
 
+inline BodyMask body_mask(const DevState& s) {
+    BodyMask m;
+    m.code = s.body_code;
+    m.gmin = s.body_gmin;
+    m.gmax = s.body_gmax;
+    return m;
+}
+
 template <int I>
 hipError_t pair_f64_launch(const DevState& s, const LaunchShape& ls, int64_t* ctr,
                            hipStream_t st) {
     dim3 grid(blocks_for(s.n, 64 * I), ls.j_split);
-    k_pair_f64<I><<<grid, 256, 0, st>>>(s.src, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr);
+    k_pair_f64<I><<<grid, 256, 0, st>>>(s.src, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr,
+                                         body_mask(s));
     return hipGetLastError();
 }
 
@@ -977,11 +1115,11 @@ hipError_t pair_mixed_launch(const DevState& s, const LaunchShape& ls, int64_t* 
                              hipStream_t st) {
     dim3 grid(blocks_for(s.n, 64 * I), ls.j_split);
     if (ls.lds_sources)
-        k_pair_mixed_l<I, L, KAHAN>
-            <<<grid, 256, 0, st>>>(s.srcm, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr);
+        k_pair_mixed_l<I, L, KAHAN><<<grid, 256, 0, st>>>(s.srcm, s.n, n64_of(s.n), ls.jps,
+                                                          s.n_pad, s.part, ctr, body_mask(s));
     else
-        k_pair_mixed_s<I, L, KAHAN>
-            <<<grid, 256, 0, st>>>(s.srcm, s.n, n64_of(s.n), ls.jps, s.n_pad, s.part, ctr);
+        k_pair_mixed_s<I, L, KAHAN><<<grid, 256, 0, st>>>(s.srcm, s.n, n64_of(s.n), ls.jps,
+                                                          s.n_pad, s.part, ctr, body_mask(s));
     return hipGetLastError();
 }
 
@@ -1066,21 +1204,21 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
                          bool use_counter, hipStream_t st) {
     const double scale = precision == 0 ? 1.0 : kMixedFieldScale;
     const int64_t* ctr = use_counter ? s.counter : nullptr;
-    const unsigned g = blocks_for(s.n, 64);
+    const unsigned g = blocks_for(s.n, 64);  // 64 ions per block of 4 waves
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
     switch (mode) {
         case kModeAccel:
-            k_update<kModeAccel><<<g, 64, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+            k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                     s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
                                                     s.n_pad, scale, s.traps, ctr);
             break;
         case kModeEnd:
-            k_update<kModeEnd><<<g, 64, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+            k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                   s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
                                                   s.n_pad, scale, s.traps, ctr);
             break;
         default:
-            k_update<kModeEndDrift><<<g, 64, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
+            k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
                                                        s.ay, s.az, s.qm, s.qe, s.part,
                                                        ls.j_split, s.n, s.n_pad, scale, s.traps,
                                                        ctr);

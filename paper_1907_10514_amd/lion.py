@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
     lib.lion_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, d]
     lib.lion_set_trap.argtypes = [vp, i32, d, d, d, d, d, d]
     lib.lion_set_damping.argtypes = [vp, i32, d]
+    lib.lion_set_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_step.argtypes = [vp, i64, d]
     lib.lion_step_batch.argtypes = [vp, i64, dp]
     lib.lion_get_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
@@ -88,7 +89,7 @@ def load(path: str = LIB_PATH):
     lib.lion_constants.argtypes = [dp, dp, dp]
     lib.lion_constants.restype = None
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
-                 "lion_set_damping", "lion_step", "lion_step_batch", "lion_get_state",
+                 "lion_set_damping", "lion_set_bodies", "lion_step", "lion_step_batch", "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite",
                  "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
                  "lion_time_pair_kernel", "lion_time_batch_kernel"):
@@ -150,6 +151,14 @@ def lion_set_trap(h, trap, V_rf, Omega, U_dc, r0, z0, kappa):
 
 def lion_set_damping(h, trap, gamma):
     _check(load().lion_set_damping(h, int(trap), float(gamma)), h)
+
+
+def lion_set_bodies(h, body_id):
+    if body_id is None:
+        _check(load().lion_set_bodies(h, None), h)
+        return
+    b = np.ascontiguousarray(body_id, dtype=np.int32)
+    _check(load().lion_set_bodies(h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), h)
 
 
 def lion_step(h, nsteps, dt):
@@ -295,6 +304,9 @@ class Simulation:
 
     def set_trap(self, V_rf, Omega, U_dc, r0, z0, kappa, trap=-1):
         lion_set_trap(self.h, trap, V_rf, Omega, U_dc, r0, z0, kappa)
+
+    def set_bodies(self, body_id):
+        lion_set_bodies(self.h, body_id)
 
     def set_damping(self, gamma, trap=-1):
         lion_set_damping(self.h, trap, gamma)

@@ -23,7 +23,7 @@ def _dsqrt(v: Decimal) -> Decimal:
     return v.sqrt()
 
 
-def decimal_accel(x, y, z, charge, mass, V0, Omega, U0, R0, Z0, kappa, t):
+def decimal_accel(x, y, z, charge, mass, V0, Omega, U0, R0, Z0, kappa, t, body=None):
     """Acceleration of every ion at 40 significant digits: pair Coulomb field of
     eq. (fullPotential) plus eq. (field) with the axially confining dc sign.
     cos(Omega t) is taken from FP64 (it is an FP64 input on both sides).
@@ -48,6 +48,8 @@ def decimal_accel(x, y, z, charge, mass, V0, Omega, U0, R0, Z0, kappa, t):
         mag = D(0)
         for j in range(n):
             if j == i:
+                continue
+            if body is not None and body[i] >= 0 and body[j] == body[i]:
                 continue
             dx, dy, dz = X[i] - X[j], Y[i] - Y[j], Zs[i] - Zs[j]
             r2 = dx * dx + dy * dy + dz * dz

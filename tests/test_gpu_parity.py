@@ -418,3 +418,90 @@ def test_error_paths_on_gpu(torch_gpu, oracle_mod):
     sim.step(2, li.DT)
     assert sim.check_finite() == L.LION_ERR_NONFINITE
     sim.close()
+
+
+# ------------------------------------------------------------ rigid bodies
+
+def _body_cloud(n, seed, contiguous=True):
+    rng = np.random.default_rng(seed)
+    w = li.random_cloud(n, seed=seed, sigma=40e-6, light_fraction=0.2)
+    body = np.full(n, -1, dtype=np.int32)
+    if contiguous:
+        for b, start in enumerate(range(0, n // 2, 37)):
+            body[start:start + 20] = b
+    else:
+        body[rng.permutation(n)[: n // 3]] = rng.integers(0, 7, n // 3)
+    return w, body
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+@pytest.mark.parametrize("contiguous", [True, False])
+def test_body_exclusion_parity(torch_gpu, oracle_mod, prec, contiguous):
+    """Pairs inside a rigid body are left out, for bodies laid out in runs of
+    consecutive ions (fast path) and scattered (per-pair test everywhere)."""
+    w, body = _body_cloud(1500, 41 if contiguous else 43, contiguous)
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    rx, ry, rz, sc = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0)
+    sim = _sim(w, prec, oracle_mod)
+    sim.set_bodies(body)
+    for cfg in ([dict()] + [dict(i_per_lane=i, j_split=j, lds_sources=l)
+                            for i in (1, 4) for j in (1, 7) for l in (1, 2)]):
+        if cfg:
+            sim.set_config(**cfg)
+        err = _m1(sim.compute_accel(), (rx, ry, rz), sc)
+        assert err <= TOL[prec], (cfg, err)
+    # clearing the mask restores the all-pairs field
+    sim.set_bodies(None)
+    r2 = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    sc2 = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    assert _m1(sim.compute_accel(), r2, sc2) <= TOL[prec]
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_clusters65536_sampled(torch_gpu, oracle_mod, prec):
+    """64 rigid clusters of 512 + 32768 free ions (65536): sampled targets in
+    clusters and free, every source counted, intra-cluster pairs left out."""
+    w = li.clusters65536()
+    body = w.notes["body"]
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    sim = _sim(w, prec, oracle_mod)
+    sim.set_bodies(body)
+    a = sim.compute_accel()
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.choice(32768, 96, replace=False),
+                          32768 + rng.choice(32768, 96, replace=False)])
+    rx, ry, rz, sc = oracle_mod.accel_bodies_at(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0,
+                                                idx)
+    err = _m1((a[0][idx], a[1][idx], a[2][idx]), (rx, ry, rz), sc)
+    print(f"clusters65536 {prec} sampled M1={err:.3e} config={sim.config()}")
+    assert err <= TOL[prec]
+    sim.step(3, w.traps[0].dt)
+    assert sim.check_finite() == 0
+    sim.close()
+
+
+def test_bodies_rejected_where_unsupported(torch_gpu, oracle_mod):
+    from paper_1907_10514_amd import LionError
+    from paper_1907_10514_amd import lion as L
+
+    w = li.random_cloud(300, seed=2)
+    sim = _sim(w, "mixed", oracle_mod, symmetric=2)
+    with pytest.raises(LionError) as ei:
+        sim.set_bodies(np.zeros(300, dtype=np.int32))
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    sim.set_config(symmetric=1)
+    with pytest.raises(LionError) as ei:
+        sim.set_bodies(np.full(300, -2, dtype=np.int32))
+    assert ei.value.code == L.LION_ERR_ARG
+    sim.set_bodies(np.zeros(300, dtype=np.int32))
+    with pytest.raises(LionError) as ei:
+        sim.set_config(symmetric=2)
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    sim.close()
+    b = _small_batch(n_traps=3, seed=5, n_max=20)
+    bs = _sim(b, "fp64", oracle_mod)
+    with pytest.raises(LionError) as ei:
+        bs.set_bodies(np.zeros(b.n, dtype=np.int32))
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    bs.close()

@@ -28,6 +28,8 @@ MUTANTS = {
     "coulomb_constant_2x": ("return 1.0 / (4.0 * OR_PI * OR_EPS0);", "return 1.0 / (2.0 * OR_PI * OR_EPS0);"),
     "self_term_kept_as_neighbour": ("if (j == i) continue;\n            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {",
                                     "if (j == i + 1) continue;\n            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {"),
+    "free_ions_share_a_body": ("            if (body[i] >= 0 && body[j] == body[i]) continue;\n            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {",
+                               "            if (body[j] == body[i]) continue;\n            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {"),
 }
 
 PINS = [
@@ -37,6 +39,8 @@ PINS = [
     lambda o: pins.test_single_ion_matches_transfer_matrices(o, "y"),
     lambda o: pins.test_two_ion_spacing_closed_form(o),
     lambda o: pins.test_laser_cooling_free_particle(o),
+    lambda o: pins.test_body_exclusion_matches_40_digit_bruteforce(o),
+    lambda o: pins.test_body_exclusion_special_cases(o),
 ]
 
 

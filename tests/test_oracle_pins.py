@@ -466,3 +466,64 @@ def test_batch_equals_independent_traps(oracle_mod):
         one = oracle_mod.step(sub, w.charge[o:e], w.mass[o:e], traps[k], g[k], 0.0, dt[k], 30)
         for kk in ("x", "y", "z", "vx", "vy", "vz", "ax"):
             assert np.array_equal(out[kk][o:e], one[kk])
+
+
+# ------------------------------------------------------------ rigid bodies
+
+def test_body_exclusion_matches_40_digit_bruteforce(oracle_mod):
+    """Pairs inside a rigid body are left out (section 'Charged rigid body'):
+    4 ions, ions 0 and 2 bound together, against a 40-digit evaluation."""
+    rng = np.random.default_rng(17)
+    x, y, z = rng.normal(0, 20e-6, (3, 4))
+    charge = np.array([1.0, 2.0, 1.0, -1.0]) * E
+    mass = rng.uniform(10, 200, 4) * li.AMU
+    body = np.array([0, -1, 0, -1], dtype=np.int32)
+    tr = _trap(oracle_mod)
+    ax, ay, az, sc = oracle_mod.accel_bodies(x, y, z, charge, mass, body, tr, 2e-8)
+    rx, ry, rz, rs = analytic.decimal_accel(x, y, z, charge, mass, tr.V0, tr.Omega, tr.U0, tr.R0,
+                                            tr.Z0, tr.kappa, 2e-8, body=body)
+    err = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2) / rs
+    assert np.max(err) < 1e-15
+    np.testing.assert_allclose(sc, rs, rtol=1e-14)
+
+
+def test_body_exclusion_special_cases(oracle_mod):
+    """All ions free: identical to accel; one body holding every ion: only the
+    trap field acts; internal forces of the rest still cancel pairwise."""
+    w = li.random_cloud(50, seed=23)
+    tr = _trap(oracle_mod)
+    free = np.full(50, -1, dtype=np.int32)
+    ax, ay, az, sc = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, free, tr, 1e-8)
+    bx, by, bz = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 1e-8)
+    assert np.array_equal(ax, bx) and np.array_equal(ay, by) and np.array_equal(az, bz)
+    assert np.array_equal(sc, oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 1e-8))
+    one = np.zeros(50, dtype=np.int32)
+    cx, cy, cz, _ = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, one, tr, 1e-8)
+    nq = oracle_mod.Trap()  # no field: no force at all
+    dx, dy, dz, _ = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, one, nq, 1e-8)
+    assert np.all(dx == 0) and np.all(dy == 0) and np.all(dz == 0)
+    ex, ey, ez = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 1e-8)
+    fx, fy, fz, _ = oracle_mod.coulomb_field(w.x, w.y, w.z, w.charge)
+    qm = w.charge / w.mass
+    np.testing.assert_allclose(cx, ex - qm * fx, rtol=1e-9, atol=1e-9 * np.max(np.abs(ex)))
+    # bodies of 10 ions: the net internal force on each body vanishes with the
+    # excluded pairs, and the total over all ions still cancels (Newton)
+    groups = (np.arange(50) // 10).astype(np.int32)
+    nofield = oracle_mod.Trap()
+    gx, gy, gz, gs = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, groups, nofield, 0.0)
+    f = w.mass * gx
+    assert abs(f.sum()) < 1e-13 * np.sum(np.abs(f))
+
+
+def test_sampled_body_accel_equals_full(oracle_mod):
+    """The sampled-target body evaluation is the same definition: identical bits."""
+    w = li.random_cloud(200, seed=31)
+    body = (np.arange(200) // 25 - 3).astype(np.int32)  # ids -3.. -> free for negatives
+    body[body < 0] = -1
+    tr = _trap(oracle_mod)
+    ax, ay, az, sc = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, body, tr, 3e-8)
+    idx = np.array([0, 74, 75, 199, 120])
+    bx, by, bz, bs = oracle_mod.accel_bodies_at(w.x, w.y, w.z, w.charge, w.mass, body, tr, 3e-8,
+                                                idx)
+    assert np.array_equal(bx, ax[idx]) and np.array_equal(by, ay[idx])
+    assert np.array_equal(bz, az[idx]) and np.array_equal(bs, sc[idx])
