@@ -47,6 +47,16 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+class _Beam(ctypes.Structure):
+    _fields_ = [("kx", ctypes.c_double), ("ky", ctypes.c_double), ("kz", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("species", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _Bath(ctypes.Structure):
+    _fields_ = [("temperature", ctypes.c_double), ("tau", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("species", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class _Trap(ctypes.Structure):
     _fields_ = [("V0", ctypes.c_double), ("Omega", ctypes.c_double), ("U0", ctypes.c_double),
                 ("R0", ctypes.c_double), ("Z0", ctypes.c_double), ("kappa", ctypes.c_double)]
@@ -95,6 +105,17 @@ def bind(path: str):
                                            ctypes.POINTER(ctypes.c_int32), tp, ctypes.c_double,
                                            i64, lp, dp, dp, dp, dp]
     lib.oracle_accel_bodies_at.restype = None
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_normals3.argtypes = [ctypes.c_uint64, i64, i64, ctypes.c_int32, ctypes.c_int32, dp]
+    lib.oracle_normals3.restype = None
+    lib.oracle_step_cooled.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                       ctypes.POINTER(ctypes.c_int32), tp, ctypes.c_double,
+                                       ctypes.c_int, ctypes.POINTER(_Beam), ctypes.c_int,
+                                       ctypes.POINTER(_Bath), i64, ctypes.c_double,
+                                       ctypes.c_double, i64, dp]
+    lib.oracle_step_cooled.restype = i64
     lib.oracle_step.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
     lib.oracle_step.restype = i64
@@ -226,6 +247,47 @@ def step(state: dict, charge, mass, trap: Trap, gamma: float, t_start: float, dt
     _load().oracle_step(s["x"].size, _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]), _d(s["vy"]),
                         _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q), _d(m), ctypes.byref(tr),
                         float(gamma), float(t_start), float(dt), int(nsteps), ctypes.byref(t_end))
+    s.update(ax=ax, ay=ay, az=az, t=t_end.value)
+    return s
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) of a 4-word counter and 2-word key."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xffffffff for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    _load().oracle_philox4x32_10(c, k, o)
+    return tuple(int(v) for v in o)
+
+
+def normals3(seed, ion, step, bath, half):
+    """The three standard normals a bath draws for one ion in one half-step."""
+    z = np.empty(3)
+    _load().oracle_normals3(int(seed), int(ion), int(step), int(bath), int(half), _d(z))
+    return z
+
+
+def step_cooled(state: dict, charge, mass, species, trap: Trap, gamma: float, beams=(),
+                baths=(), step_base: int = 0, t_start: float = 0.0, dt: float = 1e-8,
+                nsteps: int = 1) -> dict:
+    """``step`` with cooling beams (dicts k=(kx,ky,kz) unit vector, gamma, species)
+    and Langevin baths (dicts temperature, tau, seed, species); see lion_oracle.c."""
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    q, m = _f64(charge), _f64(mass)
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    ax, ay, az = accel(s["x"], s["y"], s["z"], q, m, trap, t_start)
+    bm = (_Beam * max(1, len(beams)))(*[_Beam(b["k"][0], b["k"][1], b["k"][2], b["gamma"],
+                                               b.get("species", -1), 0) for b in beams])
+    bt = (_Bath * max(1, len(baths)))(*[_Bath(b["temperature"], b["tau"], b["seed"],
+                                               b.get("species", -1), 0) for b in baths])
+    t_end = ctypes.c_double(0.0)
+    tr = trap._c()
+    _load().oracle_step_cooled(s["x"].size, _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]),
+                               _d(s["vy"]), _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q), _d(m),
+                               sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               ctypes.byref(tr), float(gamma), len(beams), bm, len(baths), bt,
+                               int(step_base), float(t_start), float(dt), int(nsteps),
+                               ctypes.byref(t_end))
     s.update(ax=ax, ay=ay, az=az, t=t_end.value)
     return s
 

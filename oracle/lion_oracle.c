@@ -37,6 +37,7 @@
 #define OR_ECHARGE 1.602176634e-19
 #define OR_EPS0 8.8541878128e-12
 #define OR_PI 3.14159265358979323846
+#define OR_KB 1.380649e-23
 
 typedef struct {
     double V0;     /* rf amplitude (V) */
@@ -363,5 +364,145 @@ int64_t oracle_accel_batch(int32_t n_traps, const int64_t *offset, const double 
         coincident += oracle_accel(m, x + o, y + o, z + o, charge + o, mass + o, &traps[k], t[k],
                                    ax + o, ay + o, az + o);
     }
+    return coincident;
+}
+
+/* ------------------------------------------------------------------------
+ * Cooling beams and Langevin baths (section "Cooling the motion of ions").
+ *
+ * A beam acts on ions of one species (-1: every species) along unit direction
+ * k with rate gamma: viscous force -M gamma (k.v) k, applied in each velocity
+ * half-step as the exact decay v <- v - (1 - exp(-gamma dt/2)) (k.v) k.
+ * A bath (temperature T, 1/e velocity relaxation time tau) acts on ions of one
+ * species in each half-step as the exact Ornstein-Uhlenbeck update
+ *   v <- c v + sqrt(k_B T / M (1 - c^2)) xi,   c = exp(-dt / (2 tau)),
+ * with xi three standard normal numbers.  The normals come from Philox4x32-10
+ * (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the bath's 64-bit seed, with
+ * counter (ion, step low word, step high word, bath << 8 | half-step), and the
+ * Box-Muller transform of its four outputs (uniforms (r + 1/2) 2^-32).
+ * Order inside one half-step: isotropic damping, beams in index order, baths in
+ * index order.  Steps are numbered from 1 over the whole run: step_base is the
+ * number of steps done before this call.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    double kx, ky, kz, gamma;
+    int32_t species, pad;
+} oracle_beam;
+
+typedef struct {
+    double temperature, tau;
+    uint64_t seed;
+    int32_t species, pad;
+} oracle_bath;
+
+static uint32_t mulhilo32(uint32_t a, uint32_t b, uint32_t *hi) {
+    uint64_t p = (uint64_t)a * (uint64_t)b;
+    *hi = (uint32_t)(p >> 32);
+    return (uint32_t)p;
+}
+
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0, hi1;
+        uint32_t lo0 = mulhilo32(0xD2511F53u, c0, &hi0);
+        uint32_t lo1 = mulhilo32(0xCD9E8D57u, c2, &hi1);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Three standard normals for (seed, ion, step, bath, half-step). */
+void oracle_normals3(uint64_t seed, int64_t ion, int64_t step, int32_t bath, int32_t half,
+                     double z[3]) {
+    uint32_t ctr[4] = {(uint32_t)ion, (uint32_t)((uint64_t)step & 0xffffffffu),
+                       (uint32_t)((uint64_t)step >> 32), ((uint32_t)bath << 8) | (uint32_t)half};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    const double two32 = 1.0 / 4294967296.0;
+    double u1 = ((double)r[0] + 0.5) * two32, u2 = ((double)r[1] + 0.5) * two32;
+    double u3 = ((double)r[2] + 0.5) * two32, u4 = ((double)r[3] + 0.5) * two32;
+    double rad1 = sqrt(-2.0 * log(u1)), rad2 = sqrt(-2.0 * log(u3));
+    z[0] = rad1 * cos(2.0 * OR_PI * u2);
+    z[1] = rad1 * sin(2.0 * OR_PI * u2);
+    z[2] = rad2 * cos(2.0 * OR_PI * u4);
+}
+
+static void velocity_half(int64_t i, double *vx, double *vy, double *vz, double f, double h,
+                          double mass, int32_t species, int nbeams, const oracle_beam *beams,
+                          int nbaths, const oracle_bath *baths, int64_t step, int half) {
+    double u = f * *vx, v = f * *vy, w = f * *vz;
+    for (int b = 0; b < nbeams; ++b) {
+        const oracle_beam *B = &beams[b];
+        if (B->gamma <= 0.0 || (B->species >= 0 && B->species != species)) continue;
+        double fb = exp(-(B->gamma * h));
+        double d = (1.0 - fb) * (B->kx * u + B->ky * v + B->kz * w);
+        u = u - d * B->kx;
+        v = v - d * B->ky;
+        w = w - d * B->kz;
+    }
+    for (int c = 0; c < nbaths; ++c) {
+        const oracle_bath *T = &baths[c];
+        if (T->tau <= 0.0 || (T->species >= 0 && T->species != species)) continue;
+        double c1 = exp(-(h / T->tau));
+        double sig = sqrt(OR_KB * T->temperature / mass * (1.0 - c1 * c1));
+        double z[3];
+        oracle_normals3(T->seed, i, step, c, half, z);
+        u = c1 * u + sig * z[0];
+        v = c1 * v + sig * z[1];
+        w = c1 * w + sig * z[2];
+    }
+    *vx = u;
+    *vy = v;
+    *vz = w;
+}
+
+/* oracle_step with cooling beams and Langevin baths.  The beam directions are
+ * used as given (the caller normalises them).  With nbeams = nbaths = 0 this is
+ * oracle_step exactly. */
+int64_t oracle_step_cooled(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                           double *vz, double *ax, double *ay, double *az, const double *charge,
+                           const double *mass, const int32_t *species, const oracle_trap *tp,
+                           double gamma, int nbeams, const oracle_beam *beams, int nbaths,
+                           const oracle_bath *baths, int64_t step_base, double t_start, double dt,
+                           int64_t nsteps, double *t_end) {
+    const double f = exp(-(gamma * dt) * 0.5);
+    const double h = 0.5 * dt;
+    int64_t coincident = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t s = step_base + k + 1;
+        for (int64_t i = 0; i < n; ++i) {
+            velocity_half(i, &vx[i], &vy[i], &vz[i], f, h, mass[i], species[i], nbeams, beams,
+                          nbaths, baths, s, 0);
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            x[i] = x[i] + dt * vx[i];
+            y[i] = y[i] + dt * vy[i];
+            z[i] = z[i] + dt * vz[i];
+        }
+        double t = t_start + (double)(k + 1) * dt;
+        coincident += oracle_accel(n, x, y, z, charge, mass, tp, t, ax, ay, az);
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            velocity_half(i, &vx[i], &vy[i], &vz[i], f, h, mass[i], species[i], nbeams, beams,
+                          nbaths, baths, s, 1);
+        }
+    }
+    *t_end = t_start + (double)nsteps * dt;
     return coincident;
 }

@@ -44,6 +44,53 @@ PINS = [
 ]
 
 
+COOLING_MUTANTS = {
+    "beam_keeps_decayed_part": ("double d = (1.0 - fb) * (B->kx", "double d = fb * (B->kx"),
+    "bath_variance_not_scaled": ("* (1.0 - c1 * c1));", ");"),
+    "beam_ignores_species": ("if (B->gamma <= 0.0 || (B->species >= 0 && B->species != species)) continue;",
+                             "if (B->gamma <= 0.0) continue;"),
+    "philox_key_not_bumped": ("k0 += 0x9E3779B9u;", "k0 += 0u;"),
+}
+
+COOLING_PINS = [
+    lambda o: pins.test_philox_known_answers(o),
+    lambda o: pins.test_single_beam_cooling_free_ions(o),
+    lambda o: pins.test_langevin_baths_follow_newtons_law_of_cooling(o),
+]
+
+
+def _build_mutant(tmp_path, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation anchor not found"
+    c = tmp_path / "mut.c"
+    so = tmp_path / "libmut.so"
+    c.write_text(src.replace(old, new, 1))
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c99", "-shared", "-fPIC",
+                    str(c), "-o", str(so), "-lm"], check=True)
+    return str(so)
+
+
+def _count_failures(so, pin_list):
+    saved = oracle._lib
+    oracle._lib = oracle.bind(so)
+    failures = 0
+    try:
+        for pin in pin_list:
+            try:
+                pin(oracle)
+            except (AssertionError, ValueError, FloatingPointError):
+                failures += 1
+    finally:
+        oracle._lib = saved
+    return failures
+
+
+@pytest.mark.parametrize("name", sorted(COOLING_MUTANTS))
+def test_cooling_pins_reject_mutant(tmp_path, name, oracle_mod):
+    so = _build_mutant(tmp_path, *COOLING_MUTANTS[name])
+    assert _count_failures(so, COOLING_PINS) >= 1, f"no pin caught mutant {name}"
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_reject_mutant(tmp_path, name, oracle_mod):
     old, new = MUTANTS[name]

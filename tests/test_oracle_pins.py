@@ -527,3 +527,101 @@ def test_sampled_body_accel_equals_full(oracle_mod):
                                                 idx)
     assert np.array_equal(bx, ax[idx]) and np.array_equal(by, ay[idx])
     assert np.array_equal(bz, az[idx]) and np.array_equal(bs, sc[idx])
+
+
+# ------------------------------------------------- cooling beams and baths
+
+def test_philox_known_answers(oracle_mod):
+    """The bath's random numbers: Philox4x32-10 against its published vectors."""
+    for row in _golden("philox_kat.txt"):
+        w = [int(v, 16) for v in row]
+        assert oracle_mod.philox4x32_10(w[0:4], w[4:6]) == tuple(w[6:10])
+
+
+def test_bath_normals_are_standard(oracle_mod):
+    """Box-Muller of Philox outputs: zero mean, unit variance, uncorrelated."""
+    z = np.array([oracle_mod.normals3(12345, i, 7, 1, 0) for i in range(20000)])
+    assert np.all(np.abs(z.mean(0)) < 4 / np.sqrt(20000))
+    assert np.all(np.abs(z.var(0) - 1) < 4 * np.sqrt(2 / 20000))
+    c = np.corrcoef(z.T)
+    assert np.max(np.abs(c - np.eye(3))) < 4 / np.sqrt(20000)
+    # different half-step, step, bath or seed: a different draw
+    base = oracle_mod.normals3(1, 5, 9, 0, 0)
+    for args in ((1, 5, 9, 0, 1), (1, 5, 10, 0, 0), (1, 5, 9, 1, 0), (2, 5, 9, 0, 0),
+                 (1, 6, 9, 0, 0)):
+        assert not np.array_equal(base, oracle_mod.normals3(*args))
+
+
+def test_cooled_step_without_cooling_is_plain_step(oracle_mod):
+    w = li.random_cloud(30, seed=51)
+    tr = _trap(oracle_mod)
+    a = oracle_mod.step(w.state(), w.charge, w.mass, tr, 1e5, 0.0, li.DT, 40)
+    b = oracle_mod.step_cooled(w.state(), w.charge, w.mass, np.zeros(30), tr, 1e5, dt=li.DT,
+                               nsteps=40)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_single_beam_cooling_free_ions(oracle_mod):
+    """Section 'Verifications', cooling mechanisms: free, non-interacting ions
+    cooled along one random axis (tau = 1 us): the velocity along the beam
+    decays as exp(-t/tau), the perpendicular components are untouched, and ions
+    of another species are not cooled at all."""
+    rng = np.random.default_rng(3)
+    k = rng.normal(size=3)
+    k /= np.linalg.norm(k)
+    n = 6
+    st = {p: np.zeros(n) for p in ("x", "y", "z")}
+    v = rng.normal(0, 2.0, (3, n))
+    st.update(vx=v[0], vy=v[1], vz=v[2])
+    species = np.array([0, 0, 0, 1, 1, 0], dtype=np.int32)
+    q0 = np.zeros(n)  # neutral: no Coulomb force
+    m = np.full(n, CA)
+    beam = dict(k=k, gamma=1e6, species=0)
+    out = oracle_mod.step_cooled(st, q0, m, species, oracle_mod.Trap(), 0.0, beams=[beam],
+                                 dt=li.DT, nsteps=800)
+    vin = np.stack([st["vx"], st["vy"], st["vz"]])
+    vout = np.stack([out["vx"], out["vy"], out["vz"]])
+    decay = math.exp(-1e6 * 800 * li.DT)
+    for i in range(n):
+        par_in, par_out = k @ vin[:, i], k @ vout[:, i]
+        perp_in, perp_out = vin[:, i] - par_in * k, vout[:, i] - par_out * k
+        if species[i] == 0:
+            assert par_out == pytest.approx(par_in * decay, rel=1e-11)
+        else:
+            assert np.array_equal(vout[:, i], vin[:, i])
+        assert np.max(np.abs(perp_out - perp_in)) < 1e-14 * np.max(np.abs(vin[:, i]))
+
+
+def test_langevin_baths_follow_newtons_law_of_cooling(oracle_mod):
+    """Section 'Verifications', cooling mechanisms: groups of free,
+    non-interacting ions, each coupled to its own bath (T_j, c_j), reach
+    3 k_B T = M <v^2> along T(t) = T_j + (T0 - T_j) exp(-2 t / c_j)."""
+    groups = [(1e-3, 10e-6), (5e-3, 30e-6), (0.2e-3, 5e-6)]
+    per = 1000
+    n = per * len(groups)
+    T0 = 2e-3
+    m = np.full(n, CA)
+    rng = np.random.default_rng(9)
+    s0 = np.sqrt(li.K_B * T0 / CA)
+    st = {p: np.zeros(n) for p in ("x", "y", "z")}
+    v = rng.normal(0, s0, (3, n))
+    st.update(vx=v[0], vy=v[1], vz=v[2])
+    species = np.repeat(np.arange(len(groups)), per).astype(np.int32)
+    baths = [dict(temperature=T, tau=tau, seed=1000 + g, species=g)
+             for g, (T, tau) in enumerate(groups)]
+    dt = 1e-7
+    cur, done = st, 0
+    temps0 = [CA * np.mean(v[:, species == g] ** 2) / li.K_B for g in range(len(groups))]
+    for chunk in (50, 100, 150):
+        cur = oracle_mod.step_cooled(cur, np.zeros(n), m, species, oracle_mod.Trap(), 0.0,
+                                     baths=baths, step_base=done, t_start=done * dt, dt=dt,
+                                     nsteps=chunk)
+        done += chunk
+        t = done * dt
+        vv = np.stack([cur["vx"], cur["vy"], cur["vz"]])
+        for g, (T, tau) in enumerate(groups):
+            meas = CA * np.mean(vv[:, species == g] ** 2) / li.K_B
+            pred = T + (temps0[g] - T) * math.exp(-2 * t / tau)
+            sigma = pred * math.sqrt(2 / (3 * per))
+            assert abs(meas - pred) < 4 * sigma, (g, t, meas, pred)
