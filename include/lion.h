@@ -113,6 +113,39 @@ int lion_set_bodies(lion_sim *sim, const int32_t *body_id);
  * >= 0 and finite.  Applied as exact exp(-gamma dt/2) velocity scalings. */
 int lion_set_damping(lion_sim *sim, int32_t trap, double gamma_per_s);
 
+/* Species labels (>= 0) used to select ions for beams and baths; NULL sets
+ * every ion to species 0 (the default).  Negative labels -> LION_ERR_ARG. */
+int lion_set_species(lion_sim *sim, const int32_t *species);
+
+/* Single-beam laser cooling (section "Cooling the motion of ions": a viscous
+ * force along the beam direction only, on one species).  Beam `beam` (0..3)
+ * acts on ions of species `species` (-1: every species) with force
+ * -M gamma (k.v) k, k = (kx, ky, kz) normalised here; each velocity half-step
+ * applies it exactly: v <- v - (1 - exp(-gamma dt/2)) (k.v) k.  gamma = 0
+ * turns the beam off.  Applies to every trap of the handle.  Non-finite input,
+ * gamma < 0 or a zero direction with gamma > 0 -> LION_ERR_ARG. */
+int lion_set_beam(lion_sim *sim, int32_t beam, int32_t species, double kx, double ky,
+                  double kz, double gamma_per_s);
+
+/* Langevin bath (section "Cooling the motion of ions": damping plus random kicks
+ * that thermalise the ions at temperature T with 1/e velocity-relaxation time
+ * tau).  Bath `bath` (0..3) acts on ions of species `species` (-1: every
+ * species); each velocity half-step applies the exact Ornstein-Uhlenbeck update
+ * v <- c v + sqrt(k_B T / M (1 - c^2)) xi, c = exp(-dt / (2 tau)), with xi
+ * three standard normals from Philox4x32-10 (Salmon et al. 2011) keyed by
+ * `seed`, counter (ion index, run-wide step number, bath << 8 | half-step),
+ * Box-Muller of the four output words.  tau = 0 turns the bath off.  Order in a
+ * half-step: isotropic damping, beams 0..3, baths 0..3.  Applies to every trap
+ * of the handle (lion_step_batch with unequal dt -> LION_ERR_UNSUPPORTED). */
+int lion_set_bath(lion_sim *sim, int32_t bath, int32_t species, double temperature_K,
+                  double damping_time_s, uint64_t seed);
+
+/* Run-wide step count that numbers the bath draws (steps completed so far; it
+ * grows by nsteps in every lion_step).  Set it when resuming a run so that the
+ * bath draws continue the same sequence.  steps_done < 0 -> LION_ERR_ARG. */
+int lion_set_step_index(lion_sim *sim, int64_t steps_done);
+int64_t lion_get_step_index(const lion_sim *sim);
+
 /* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite).
  * nsteps = 0 is a no-op.  Time afterwards: t + nsteps dt.  Requires
  * lion_set_state first (else LION_ERR_STATE). */

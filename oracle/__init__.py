@@ -113,7 +113,7 @@ def bind(path: str):
     lib.oracle_step_cooled.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
                                        ctypes.POINTER(ctypes.c_int32), tp, ctypes.c_double,
                                        ctypes.c_int, ctypes.POINTER(_Beam), ctypes.c_int,
-                                       ctypes.POINTER(_Bath), i64, ctypes.c_double,
+                                       ctypes.POINTER(_Bath), i64, i64, ctypes.c_double,
                                        ctypes.c_double, i64, dp]
     lib.oracle_step_cooled.restype = i64
     lib.oracle_step.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
@@ -269,9 +269,10 @@ def normals3(seed, ion, step, bath, half):
 
 def step_cooled(state: dict, charge, mass, species, trap: Trap, gamma: float, beams=(),
                 baths=(), step_base: int = 0, t_start: float = 0.0, dt: float = 1e-8,
-                nsteps: int = 1) -> dict:
+                nsteps: int = 1, ion_base: int = 0) -> dict:
     """``step`` with cooling beams (dicts k=(kx,ky,kz) unit vector, gamma, species)
-    and Langevin baths (dicts temperature, tau, seed, species); see lion_oracle.c."""
+    and Langevin baths (dicts temperature, tau, seed, species); see lion_oracle.c.
+    ion_base numbers this trap's first ion in the run (bath draws are keyed by it)."""
     s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
     q, m = _f64(charge), _f64(mass)
     sp = np.ascontiguousarray(species, dtype=np.int32)
@@ -286,7 +287,8 @@ def step_cooled(state: dict, charge, mass, species, trap: Trap, gamma: float, be
                                _d(s["vy"]), _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q), _d(m),
                                sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                ctypes.byref(tr), float(gamma), len(beams), bm, len(baths), bt,
-                               int(step_base), float(t_start), float(dt), int(nsteps),
+                               int(ion_base), int(step_base), float(t_start), float(dt),
+                               int(nsteps),
                                ctypes.byref(t_end))
     s.update(ax=ax, ay=ay, az=az, t=t_end.value)
     return s

@@ -470,22 +470,24 @@ static void velocity_half(int64_t i, double *vx, double *vy, double *vz, double 
 }
 
 /* oracle_step with cooling beams and Langevin baths.  The beam directions are
- * used as given (the caller normalises them).  With nbeams = nbaths = 0 this is
- * oracle_step exactly. */
+ * used as given (the caller normalises them).  Ion i of this trap draws its bath
+ * normals as ion ion_base + i of the run (a trap inside a batch passes the
+ * index of its first ion).  With nbeams = nbaths = 0 this is oracle_step
+ * exactly. */
 int64_t oracle_step_cooled(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                            double *vz, double *ax, double *ay, double *az, const double *charge,
                            const double *mass, const int32_t *species, const oracle_trap *tp,
                            double gamma, int nbeams, const oracle_beam *beams, int nbaths,
-                           const oracle_bath *baths, int64_t step_base, double t_start, double dt,
-                           int64_t nsteps, double *t_end) {
+                           const oracle_bath *baths, int64_t ion_base, int64_t step_base,
+                           double t_start, double dt, int64_t nsteps, double *t_end) {
     const double f = exp(-(gamma * dt) * 0.5);
     const double h = 0.5 * dt;
     int64_t coincident = 0;
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t s = step_base + k + 1;
         for (int64_t i = 0; i < n; ++i) {
-            velocity_half(i, &vx[i], &vy[i], &vz[i], f, h, mass[i], species[i], nbeams, beams,
-                          nbaths, baths, s, 0);
+            velocity_half(ion_base + i, &vx[i], &vy[i], &vz[i], f, h, mass[i], species[i],
+                          nbeams, beams, nbaths, baths, s, 0);
             vx[i] = vx[i] + h * ax[i];
             vy[i] = vy[i] + h * ay[i];
             vz[i] = vz[i] + h * az[i];
@@ -499,8 +501,8 @@ int64_t oracle_step_cooled(int64_t n, double *x, double *y, double *z, double *v
             vx[i] = vx[i] + h * ax[i];
             vy[i] = vy[i] + h * ay[i];
             vz[i] = vz[i] + h * az[i];
-            velocity_half(i, &vx[i], &vy[i], &vz[i], f, h, mass[i], species[i], nbeams, beams,
-                          nbaths, baths, s, 1);
+            velocity_half(ion_base + i, &vx[i], &vy[i], &vz[i], f, h, mass[i], species[i],
+                          nbeams, beams, nbaths, baths, s, 1);
         }
     }
     *t_end = t_start + (double)nsteps * dt;

@@ -37,6 +37,12 @@ struct lion_sim {
     std::vector<double> mass, charge;
     bool state_set = false;
     bool has_bodies = false;
+    int64_t steps_done = 0;           // run-wide step count (numbers the bath draws)
+    struct Beam { double kx, ky, kz, gamma; int32_t species; };
+    struct Bath { double temperature, tau; uint64_t seed; int32_t species; };
+    Beam beams[lion::kMaxBeams] = {};
+    Bath baths[lion::kMaxBaths] = {};
+    lion::CoolDev cool{};
     char* ws = nullptr;
     size_t body_off[3] = {0, 0, 0};
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (chunk length, kind)
@@ -71,7 +77,7 @@ int slices_for(int64_t n) {
 
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
-        flags, body_code, body_gmin, body_gmax, total;
+        flags, body_code, body_gmin, body_gmax, cool, species, total;
 };
 
 Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
@@ -101,6 +107,8 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.body_code = take(np * sizeof(int32_t));
     L.body_gmin = take(np / 16 * sizeof(int32_t));
     L.body_gmax = take(np / 16 * sizeof(int32_t));
+    L.cool = take(sizeof(lion::CoolDev));
+    L.species = take(np * sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -157,6 +165,40 @@ void clear_graphs(lion_sim* s) {
 int upload_traps(lion_sim* s) {
     LION_HIP(s, hipMemcpyAsync(s->d.traps, s->traps.data(), s->traps.size() * sizeof(TrapDev),
                                hipMemcpyHostToDevice, s->stream));
+    return LION_OK;
+}
+
+// Half-step factors of the beams and baths for step size dt, and the run-wide
+// step count, into device memory.  Uses one dt for every trap (the first).
+int upload_cooling(lion_sim* s, double dt) {
+    const double h = 0.5 * dt;
+    lion::CoolDev& C = s->cool;
+    C.nbeams = C.nbaths = 0;
+    for (int b = 0; b < lion::kMaxBeams; ++b) {
+        const auto& B = s->beams[b];
+        lion::BeamDev& D = C.beams[b];
+        D.on = B.gamma > 0.0;
+        D.kx = B.kx;
+        D.ky = B.ky;
+        D.kz = B.kz;
+        D.f = std::exp(-(B.gamma * h));
+        D.species = B.species;
+        if (D.on) C.nbeams = b + 1;
+    }
+    for (int c = 0; c < lion::kMaxBaths; ++c) {
+        const auto& T = s->baths[c];
+        lion::BathDev& D = C.baths[c];
+        D.on = T.tau > 0.0;
+        D.c1 = D.on ? std::exp(-(h / T.tau)) : 1.0;
+        D.kt = lion::kBoltzmann * T.temperature;
+        D.omc2 = 1.0 - D.c1 * D.c1;
+        D.seed = T.seed;
+        D.species = T.species;
+        if (D.on) C.nbaths = c + 1;
+    }
+    C.step_base = s->steps_done;
+    LION_HIP(s, hipMemcpyAsync(s->d.cool, &s->cool, sizeof(lion::CoolDev), hipMemcpyHostToDevice,
+                               s->stream));
     return LION_OK;
 }
 
@@ -296,6 +338,8 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     d.order = (int32_t*)(base + L.order);
     d.counter = (int64_t*)(base + L.counter);
     d.flags = (int32_t*)(base + L.flags);
+    d.cool = (lion::CoolDev*)(base + L.cool);
+    d.species = (int32_t*)(base + L.species);
     d.body_code = nullptr;  // set by lion_set_bodies
     d.body_gmin = nullptr;
     d.body_gmax = nullptr;
@@ -341,6 +385,8 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
               hipMemsetAsync(d.ax, 0, 3 * np * 8, st) == hipSuccess &&
               hipMemsetAsync(d.counter, 0, 8, st) == hipSuccess &&
               hipMemsetAsync(d.flags, 0, 16, st) == hipSuccess &&
+              hipMemsetAsync(d.species, 0, np * 4, st) == hipSuccess &&
+              hipMemcpyAsync(d.cool, &s->cool, sizeof(lion::CoolDev), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemcpyAsync(d.traps, s->traps.data(), n_traps * sizeof(TrapDev), hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok && d.srcm) ok = lion::launch_pack_mixed(d, st) == hipSuccess;
     if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
@@ -490,6 +536,65 @@ int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
     return s->state_set ? refresh_accel(s) : LION_OK;
 }
 
+int lion_set_species(lion_sim* s, const int32_t* species) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    const int64_t n = s->n, np = s->d.n_pad;
+    std::vector<int32_t> sp(np, 0);
+    if (species) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (species[i] < 0) return fail(s, LION_ERR_ARG, "species labels must be >= 0");
+            sp[i] = species[i];
+        }
+    }
+    LION_HIP(s, hipSetDevice(s->device));
+    LION_HIP(s, hipMemcpyAsync(s->d.species, sp.data(), np * 4, hipMemcpyHostToDevice, s->stream));
+    LION_HIP(s, hipStreamSynchronize(s->stream));
+    return LION_OK;
+}
+
+int lion_set_beam(lion_sim* s, int32_t beam, int32_t species, double kx, double ky, double kz,
+                  double gamma) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (beam < 0 || beam >= lion::kMaxBeams) return fail(s, LION_ERR_ARG, "beam index must be 0..3");
+    if (species < -1) return fail(s, LION_ERR_ARG, "species must be >= -1");
+    if (!is_fin(kx) || !is_fin(ky) || !is_fin(kz) || !is_fin(gamma) || gamma < 0.0)
+        return fail(s, LION_ERR_ARG, "beam direction must be finite and gamma finite and >= 0");
+    const double norm = std::sqrt(kx * kx + ky * ky + kz * kz);
+    if (gamma > 0.0 && !(norm > 0.0)) return fail(s, LION_ERR_ARG, "beam direction is zero");
+    auto& B = s->beams[beam];
+    B.gamma = gamma;
+    B.species = species;
+    B.kx = gamma > 0.0 ? kx / norm : 0.0;
+    B.ky = gamma > 0.0 ? ky / norm : 0.0;
+    B.kz = gamma > 0.0 ? kz / norm : 0.0;
+    return LION_OK;
+}
+
+int lion_set_bath(lion_sim* s, int32_t bath, int32_t species, double temperature_K,
+                  double damping_time_s, uint64_t seed) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (bath < 0 || bath >= lion::kMaxBaths) return fail(s, LION_ERR_ARG, "bath index must be 0..3");
+    if (species < -1) return fail(s, LION_ERR_ARG, "species must be >= -1");
+    if (!is_fin(temperature_K) || temperature_K < 0.0 || !is_fin(damping_time_s) ||
+        damping_time_s < 0.0)
+        return fail(s, LION_ERR_ARG, "temperature and damping time must be finite and >= 0");
+    auto& T = s->baths[bath];
+    T.temperature = temperature_K;
+    T.tau = damping_time_s;
+    T.seed = seed;
+    T.species = species;
+    return LION_OK;
+}
+
+int lion_set_step_index(lion_sim* s, int64_t steps_done) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (steps_done < 0) return fail(s, LION_ERR_ARG, "steps_done must be >= 0");
+    s->steps_done = steps_done;
+    return LION_OK;
+}
+
+int64_t lion_get_step_index(const lion_sim* s) { return s ? s->steps_done : -1; }
+
 int lion_set_damping(lion_sim* s, int32_t trap, double gamma) {
     if (check_handle(s)) return LION_ERR_ARG;
     if (trap < -1 || trap >= s->n_traps) return fail(s, LION_ERR_ARG, "trap index out of range");
@@ -515,6 +620,14 @@ static int step_common(lion_sim* s, int64_t nsteps, const double* dts) {
     }
     int rc = upload_traps(s);
     if (rc) return rc;
+    bool cooling = false;
+    for (const auto& B : s->beams) cooling = cooling || B.gamma > 0.0;
+    for (const auto& T : s->baths) cooling = cooling || T.tau > 0.0;
+    for (int k = 1; k < s->n_traps && cooling; ++k)
+        if (dts[k] != dts[0])
+            return fail(s, LION_ERR_UNSUPPORTED, "cooling beams and baths need one dt for all traps");
+    rc = upload_cooling(s, dts[0]);
+    if (rc) return rc;
     LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), s->stream));
     const int64_t S = std::max(1, s->cfg.chunk_steps);
     for (int64_t done = 0; done < nsteps;) {
@@ -524,6 +637,7 @@ static int step_common(lion_sim* s, int64_t nsteps, const double* dts) {
         done += L;
     }
     for (int k = 0; k < s->n_traps; ++k) s->t_now[k] = s->traps[k].t_start + (double)nsteps * dts[k];
+    s->steps_done += nsteps;
     return LION_OK;
 }
 
@@ -742,6 +856,8 @@ int lion_time_batch_kernel(lion_sim* s, int32_t reps, int32_t nsteps, double dt,
     }
     rc = upload_traps(s);
     if (rc) return rc;
+    rc = upload_cooling(s, dt);
+    if (rc) return rc;
     hipStream_t st = s->stream;
     LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -767,6 +883,7 @@ int lion_time_batch_kernel(lion_sim* s, int32_t reps, int32_t nsteps, double dt,
     const double total = ms;
     for (int k = 0; k < s->n_traps; ++k)
         s->t_now[k] = s->traps[k].t_start + (double)((int64_t)reps * nsteps) * dt;
+    s->steps_done += (int64_t)reps * nsteps;
     *ms_avg = total / reps;
     return LION_OK;
 }

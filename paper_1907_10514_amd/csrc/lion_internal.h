@@ -38,6 +38,38 @@ struct TrapDev {
     double gamma;    // 1/s (kept for reference)
 };
 
+// Cooling in the velocity half-steps (applied after the isotropic damping):
+// beams decay the velocity component along k by f = exp(-gamma dt/2); baths
+// apply v <- c1 v + sqrt(k_B T / M (1 - c1^2)) xi with Philox4x32-10 normals.
+constexpr int kMaxBeams = 4;
+constexpr int kMaxBaths = 4;
+constexpr double kBoltzmann = 1.380649e-23;  // J/K
+
+struct BeamDev {
+    double kx, ky, kz;  // unit direction
+    double f;           // exp(-gamma dt / 2) for the current step size
+    int32_t species;    // -1: every species
+    int32_t on;
+    int32_t pad[2];
+};
+
+struct BathDev {
+    double c1;           // exp(-dt / (2 tau))
+    double kt;           // k_B T
+    double omc2;         // 1 - c1^2; the kernel forms sqrt(kt / M * omc2)
+    uint64_t seed;
+    int32_t species;     // -1: every species
+    int32_t on;
+};
+
+struct CoolDev {
+    BeamDev beams[kMaxBeams];
+    BathDev baths[kMaxBaths];
+    int32_t nbeams;      // highest active beam index + 1 (0: none)
+    int32_t nbaths;
+    int64_t step_base;   // steps completed before the current lion_step call
+};
+
 // One ion of the FP32 pair stream: high and low float parts of the scaled
 // position and the negated charge in units of e.
 struct MixedSrc {
@@ -74,6 +106,8 @@ struct DevState {
     int32_t* order;   // [n_traps] launch order (largest trap first)
     int64_t* counter; // step index inside the current call
     int32_t* flags;   // [4] diagnostics (non-finite count)
+    CoolDev* cool;    // beams and baths
+    int32_t* species; // [n_pad] species label per ion (default 0)
     // rigid-body exclusion (all NULL when no bodies are set)
     int32_t* body_code;  // [n_pad] body id >= 0, or -1 - i for a free ion i
     int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions

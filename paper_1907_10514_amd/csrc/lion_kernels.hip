@@ -163,22 +163,7 @@ __device__ __forceinline__ MixedSrc make_src(double x, double y, double z, doubl
     return m;
 }
 
-// --------------------------------------------------------- first half-step
-
-__device__ __forceinline__ void half_step_drift(const TrapDev& T, double& x, double& y,
-                                                double& z, double& vx, double& vy, double& vz,
-                                                double ax, double ay, double az) {
-#pragma clang fp contract(off)
-    vx = T.f * vx;
-    vy = T.f * vy;
-    vz = T.f * vz;
-    vx = vx + T.h * ax;
-    vy = vy + T.h * ay;
-    vz = vz + T.h * az;
-    x = x + T.dt * vx;
-    y = y + T.dt * vy;
-    z = z + T.dt * vz;
-}
+// --------------------------------------------------------- trap field
 
 __device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm, double x,
                                            double y, double z, double Sx, double Sy, double Sz,
@@ -193,15 +178,100 @@ __device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm
     az = qm * (kKeE * Sz + ez);
 }
 
-__device__ __forceinline__ void end_kick(const TrapDev& T, double& vx, double& vy, double& vz,
-                                         double ax, double ay, double az) {
+// ------------------------------------------------------------ cooling
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32
+// multiplications with the round key bumped by the Weyl constants.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Three standard normals for (seed, ion, step, bath, half-step): Box-Muller of
+// the four Philox words taken as uniforms (r + 1/2) 2^-32.
+__device__ __forceinline__ void bath_normals(uint64_t seed, int64_t ion, int64_t step, int bath,
+                                             int half, double& z0, double& z1, double& z2) {
+#pragma clang fp contract(off)
+    uint32_t c[4] = {(uint32_t)ion, (uint32_t)((uint64_t)step & 0xffffffffu),
+                     (uint32_t)((uint64_t)step >> 32), ((uint32_t)bath << 8) | (uint32_t)half};
+    philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    const double s32 = 1.0 / 4294967296.0;
+    const double u1 = ((double)c[0] + 0.5) * s32, u2 = ((double)c[1] + 0.5) * s32;
+    const double u3 = ((double)c[2] + 0.5) * s32, u4 = ((double)c[3] + 0.5) * s32;
+    const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    z0 = r1 * cos(2.0 * kPi * u2);
+    z1 = r1 * sin(2.0 * kPi * u2);
+    z2 = r2 * cos(2.0 * kPi * u4);
+}
+
+// Velocity half-step: isotropic damping f, then beams, then baths (index order).
+__device__ __forceinline__ void velocity_half(const CoolDev* __restrict__ C, int64_t ion,
+                                              int32_t species, double mass, double f,
+                                              int64_t step, int half, double& u, double& v,
+                                              double& w) {
+#pragma clang fp contract(off)
+    u = f * u;
+    v = f * v;
+    w = f * w;
+    if (!C) return;
+    const int nb = C->nbeams, nt = C->nbaths;
+    for (int b = 0; b < nb; ++b) {
+        const BeamDev B = C->beams[b];
+        if (!B.on || (B.species >= 0 && B.species != species)) continue;
+        const double d = (1.0 - B.f) * (B.kx * u + B.ky * v + B.kz * w);
+        u = u - d * B.kx;
+        v = v - d * B.ky;
+        w = w - d * B.kz;
+    }
+    for (int c = 0; c < nt; ++c) {
+        const BathDev T = C->baths[c];
+        if (!T.on || (T.species >= 0 && T.species != species)) continue;
+        const double sig = sqrt(T.kt / mass * T.omc2);
+        double z0, z1, z2;
+        bath_normals(T.seed, ion, step, c, half, z0, z1, z2);
+        u = T.c1 * u + sig * z0;
+        v = T.c1 * v + sig * z1;
+        w = T.c1 * w + sig * z2;
+    }
+}
+
+// First half of a step: velocity half-step (damping, beams, baths), half kick,
+// drift.  `step` numbers steps from 1 over the whole run.
+__device__ __forceinline__ void half_step_drift(const TrapDev& T, const CoolDev* __restrict__ C,
+                                                int64_t ion, int32_t species, double mass,
+                                                int64_t step, double& x, double& y, double& z,
+                                                double& vx, double& vy, double& vz, double ax,
+                                                double ay, double az) {
+#pragma clang fp contract(off)
+    velocity_half(C, ion, species, mass, T.f, step, 0, vx, vy, vz);
+    vx = vx + T.h * ax;
+    vy = vy + T.h * ay;
+    vz = vz + T.h * az;
+    x = x + T.dt * vx;
+    y = y + T.dt * vy;
+    z = z + T.dt * vz;
+}
+
+// Second half of a step: half kick with the new acceleration, velocity half-step.
+__device__ __forceinline__ void end_kick(const TrapDev& T, const CoolDev* __restrict__ C,
+                                         int64_t ion, int32_t species, double mass, int64_t step,
+                                         double& vx, double& vy, double& vz, double ax, double ay,
+                                         double az) {
 #pragma clang fp contract(off)
     vx = vx + T.h * ax;
     vy = vy + T.h * ay;
     vz = vz + T.h * az;
-    vx = T.f * vx;
-    vy = T.f * vy;
-    vz = T.f * vz;
+    velocity_half(C, ion, species, mass, T.f, step, 1, vx, vy, vz);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -214,13 +284,19 @@ __global__ __launch_bounds__(256) void k_drift(double4* __restrict__ src,
                                                const double* __restrict__ ay,
                                                const double* __restrict__ az,
                                                const double* __restrict__ qe,
-                                               const TrapDev* __restrict__ traps, int64_t n) {
+                                               const double* __restrict__ mass,
+                                               const int32_t* __restrict__ species,
+                                               const TrapDev* __restrict__ traps,
+                                               const CoolDev* __restrict__ cool,
+                                               const int64_t* __restrict__ counter, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const TrapDev T = traps[0];
+    const int64_t step = cool->step_base + *counter + 1;
     double4 p = src[i];
     double u = vx[i], v = vy[i], w = vz[i];
-    half_step_drift(T, p.x, p.y, p.z, u, v, w, ax[i], ay[i], az[i]);
+    half_step_drift(T, cool, i, species[i], mass[i], step, p.x, p.y, p.z, u, v, w, ax[i], ay[i],
+                    az[i]);
     src[i] = p;
     vx[i] = u;
     vy[i] = v;
@@ -781,9 +857,12 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
                                                 double* __restrict__ ay, double* __restrict__ az,
                                                 const double* __restrict__ qm,
                                                 const double* __restrict__ qe,
+                                                const double* __restrict__ mass,
+                                                const int32_t* __restrict__ species,
                                                 const double* __restrict__ part, int j_split,
                                                 int64_t n, int64_t n_pad, double field_scale,
                                                 const TrapDev* __restrict__ traps,
+                                                const CoolDev* __restrict__ cool,
                                                 const int64_t* __restrict__ counter) {
     __shared__ double red[kWaves - 1][3][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -825,10 +904,13 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
     ay[i] = a_y;
     az[i] = a_z;
     if (MODE == kModeAccel) return;
+    const int64_t step = cool->step_base + *counter;  // the step this epilogue completes
+    const int32_t sp = species[i];
+    const double mi = mass[i];
     double u = vx[i], v = vy[i], w = vz[i];
-    end_kick(T, u, v, w, a_x, a_y, a_z);
+    end_kick(T, cool, i, sp, mi, step, u, v, w, a_x, a_y, a_z);
     if (MODE == kModeEndDrift) {
-        half_step_drift(T, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
+        half_step_drift(T, cool, i, sp, mi, step + 1, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
         src[i] = p;
         if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
     }
@@ -912,7 +994,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  double* __restrict__ az,
                                                  const double* __restrict__ qm,
                                                  const double* __restrict__ qe,
+                                                 const double* __restrict__ mass,
+                                                 const int32_t* __restrict__ species,
                                                  const TrapDev* __restrict__ traps,
+                                                 const CoolDev* __restrict__ cool,
                                                  const int64_t* __restrict__ offsets,
                                                  const int32_t* __restrict__ order,
                                                  const int64_t* __restrict__ counter,
@@ -940,7 +1025,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const int64_t k0 = *counter;
 
     double x[KMAX], y[KMAX], z[KMAX], u[KMAX], v[KMAX], w[KMAX], a0[KMAX], a1[KMAX], a2[KMAX];
-    double q_m[KMAX], q_e[KMAX];
+    double q_m[KMAX], q_e[KMAX], m_i[KMAX];
+    int32_t sp[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int il = slot + IS * k;
@@ -957,9 +1043,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             a2[k] = az[o + il];
             q_m[k] = qm[o + il];
             q_e[k] = qe[o + il];
+            m_i[k] = mass[o + il];
+            sp[k] = species[o + il];
         } else {
             x[k] = y[k] = z[k] = u[k] = v[k] = w[k] = a0[k] = a1[k] = a2[k] = 0.0;
             q_m[k] = q_e[k] = 0.0;
+            m_i[k] = 1.0;
+            sp[k] = 0;
         }
     }
     // zero-charge padding of the source stream
@@ -972,6 +1062,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     }
 
     const int total = accel_only ? 1 : nsteps;
+    const int64_t step0 = cool->step_base + k0 + 1;  // run-wide number of the first step
     for (int step = 0; step < total; ++step) {
         // first half of the step; positions into the LDS source stream
 #pragma unroll
@@ -979,7 +1070,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             const int il = slot + IS * k;
             if (owner && il < m) {
                 if (!accel_only)
-                    half_step_drift(T, x[k], y[k], z[k], u[k], v[k], w[k], a0[k], a1[k], a2[k]);
+                    half_step_drift(T, cool, o + il, sp[k], m_i[k], step0 + step, x[k], y[k],
+                                    z[k], u[k], v[k], w[k], a0[k], a1[k], a2[k]);
                 if constexpr (PREC == 0) {
                     lds[il] = make_double4(x[k], y[k], z[k], 1.5 * q_e[k]);
                 } else {
@@ -1070,7 +1162,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             if (owner && il < m) {
                 trap_accel(T, t, q_m[k], x[k], y[k], z[k], Sx[k], Sy[k], Sz[k], a0[k], a1[k],
                            a2[k]);
-                if (!accel_only) end_kick(T, u[k], v[k], w[k], a0[k], a1[k], a2[k]);
+                if (!accel_only)
+                    end_kick(T, cool, o + il, sp[k], m_i[k], step0 + step, u[k], v[k], w[k],
+                             a0[k], a1[k], a2[k]);
             }
         }
     }
@@ -1137,8 +1231,9 @@ template <int PREC, int BLOCK>
 hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only,
                         hipStream_t st) {
     k_batch<PREC, BLOCK><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
-                                                    s.qm, s.qe, s.traps, s.offsets, s.order,
-                                                    s.counter, nsteps, accel_only);
+                                                    s.qm, s.qe, s.mass, s.species, s.traps,
+                                                    s.cool, s.offsets, s.order, s.counter,
+                                                    nsteps, accel_only);
     return hipGetLastError();
 }
 
@@ -1156,7 +1251,8 @@ hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps,
 
 hipError_t launch_drift(const DevState& s, hipStream_t st) {
     k_drift<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
-                                                  s.az, s.qe, s.traps, s.n);
+                                                  s.az, s.qe, s.mass, s.species, s.traps, s.cool,
+                                                  s.counter, s.n);
     return hipGetLastError();
 }
 
@@ -1209,19 +1305,21 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
     switch (mode) {
         case kModeAccel:
             k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
-                                                    s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
-                                                    s.n_pad, scale, s.traps, ctr);
+                                                    s.az, s.qm, s.qe, s.mass, s.species, s.part,
+                                                    ls.j_split, s.n, s.n_pad, scale, s.traps,
+                                                    s.cool, ctr);
             break;
         case kModeEnd:
             k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
-                                                  s.az, s.qm, s.qe, s.part, ls.j_split, s.n,
-                                                  s.n_pad, scale, s.traps, ctr);
+                                                  s.az, s.qm, s.qe, s.mass, s.species, s.part,
+                                                  ls.j_split, s.n, s.n_pad, scale, s.traps,
+                                                  s.cool, ctr);
             break;
         default:
             k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
-                                                       s.ay, s.az, s.qm, s.qe, s.part,
-                                                       ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                       ctr);
+                                                       s.ay, s.az, s.qm, s.qe, s.mass, s.species,
+                                                       s.part, ls.j_split, s.n, s.n_pad, scale,
+                                                       s.traps, s.cool, ctr);
             break;
     }
     return hipGetLastError();

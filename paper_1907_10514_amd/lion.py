@@ -71,6 +71,12 @@ def load(path: str = LIB_PATH):
     lib.lion_set_trap.argtypes = [vp, i32, d, d, d, d, d, d]
     lib.lion_set_damping.argtypes = [vp, i32, d]
     lib.lion_set_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lion_set_species.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lion_set_beam.argtypes = [vp, i32, i32, d, d, d, d]
+    lib.lion_set_bath.argtypes = [vp, i32, i32, d, d, ctypes.c_uint64]
+    lib.lion_set_step_index.argtypes = [vp, i64]
+    lib.lion_get_step_index.argtypes = [vp]
+    lib.lion_get_step_index.restype = i64
     lib.lion_step.argtypes = [vp, i64, d]
     lib.lion_step_batch.argtypes = [vp, i64, dp]
     lib.lion_get_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
@@ -89,7 +95,8 @@ def load(path: str = LIB_PATH):
     lib.lion_constants.argtypes = [dp, dp, dp]
     lib.lion_constants.restype = None
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
-                 "lion_set_damping", "lion_set_bodies", "lion_step", "lion_step_batch", "lion_get_state",
+                 "lion_set_damping", "lion_set_bodies", "lion_set_species", "lion_set_beam",
+                 "lion_set_bath", "lion_set_step_index", "lion_step", "lion_step_batch", "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite",
                  "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
                  "lion_time_pair_kernel", "lion_time_batch_kernel"):
@@ -159,6 +166,32 @@ def lion_set_bodies(h, body_id):
         return
     b = np.ascontiguousarray(body_id, dtype=np.int32)
     _check(load().lion_set_bodies(h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), h)
+
+
+def lion_set_species(h, species):
+    if species is None:
+        _check(load().lion_set_species(h, None), h)
+        return
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    _check(load().lion_set_species(h, sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), h)
+
+
+def lion_set_beam(h, beam, species, kx, ky, kz, gamma):
+    _check(load().lion_set_beam(h, int(beam), int(species), float(kx), float(ky), float(kz),
+                                float(gamma)), h)
+
+
+def lion_set_bath(h, bath, species, temperature, damping_time, seed):
+    _check(load().lion_set_bath(h, int(bath), int(species), float(temperature),
+                                float(damping_time), int(seed) & 0xffffffffffffffff), h)
+
+
+def lion_set_step_index(h, steps_done):
+    _check(load().lion_set_step_index(h, int(steps_done)), h)
+
+
+def lion_get_step_index(h) -> int:
+    return int(load().lion_get_step_index(h))
 
 
 def lion_step(h, nsteps, dt):
@@ -307,6 +340,21 @@ class Simulation:
 
     def set_bodies(self, body_id):
         lion_set_bodies(self.h, body_id)
+
+    def set_species(self, species):
+        lion_set_species(self.h, species)
+
+    def set_beam(self, beam, k, gamma, species=-1):
+        lion_set_beam(self.h, beam, species, k[0], k[1], k[2], gamma)
+
+    def set_bath(self, bath, temperature, damping_time, seed, species=-1):
+        lion_set_bath(self.h, bath, species, temperature, damping_time, seed)
+
+    def set_step_index(self, steps_done):
+        lion_set_step_index(self.h, steps_done)
+
+    def step_index(self) -> int:
+        return lion_get_step_index(self.h)
 
     def set_damping(self, gamma, trap=-1):
         lion_set_damping(self.h, trap, gamma)

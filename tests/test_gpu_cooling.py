@@ -1,0 +1,254 @@
+"""Cooling beams and Langevin baths on the GPU against the oracle.
+
+Both sides draw the bath kicks from Philox4x32-10 with the same counter
+(ion, run-wide step, bath and half-step) and key (seed), each from its own
+implementation; the Box-Muller transcendental functions may differ in the last
+bit between the device and host math libraries, so trajectories agree to
+roundoff growth, not bit for bit.  Beams involve no random numbers and match
+the oracle to the last few bits.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import lion_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _oracle_trap(oracle, spec):
+    V0, U0 = oracle.voltages_for(spec.q_x, spec.a_x, spec.ref_mass, spec.ref_charge, spec.omega,
+                                 spec.r0, spec.z0, spec.kappa)
+    return oracle.Trap(V0=V0, Omega=spec.omega, U0=U0, R0=spec.r0, Z0=spec.z0, kappa=spec.kappa)
+
+
+def _unit(v):
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.linalg.norm(v)
+
+
+BEAMS = [dict(k=_unit([1.0, 1.0, 1.0]), gamma=3e5, species=0),
+         dict(k=_unit([0.2, -0.5, 1.0]), gamma=1e5, species=1)]
+BATHS = [dict(temperature=0.5e-3, tau=40e-6, seed=0x1234_5678_9ABC, species=1),
+         dict(temperature=2e-3, tau=80e-6, seed=99, species=-1)]
+
+
+def _envelope(run, state):
+    """Roundoff-growth envelope of a chaotic run: how far the oracle's own
+    trajectory moves when every start position is moved by one ulp.  Returns
+    (max |dx|, max |dv|) between the two oracle runs."""
+    a = run(state)
+    st = {k: v.copy() for k, v in state.items()}
+    for k in ("x", "y", "z"):
+        st[k] = np.nextafter(st[k], np.inf)
+    b = run(st)
+    return (max(np.max(np.abs(a[k] - b[k])) for k in ("x", "y", "z")),
+            max(np.max(np.abs(a[k] - b[k])) for k in ("vx", "vy", "vz")))
+
+
+def _species(w):
+    return (w.mass < 30 * li.AMU).astype(np.int32)
+
+
+def _cooled_sim(w, prec, oracle, species, beams=BEAMS, baths=BATHS, **cfg):
+    from paper_1907_10514_amd import Simulation
+
+    batched = w.n_traps > 1
+    sim = Simulation(w.mass, w.charge, prec, n_per_trap=np.diff(w.offsets) if batched else None)
+    if cfg:
+        sim.set_config(**cfg)
+    for k, spec in enumerate(w.traps):
+        tr = _oracle_trap(oracle, spec)
+        sim.set_trap(tr.V0, tr.Omega, tr.U0, tr.R0, tr.Z0, tr.kappa, trap=k if batched else -1)
+        sim.set_damping(spec.gamma, trap=k if batched else -1)
+    sim.set_species(species)
+    for b, B in enumerate(beams):
+        sim.set_beam(b, B["k"], B["gamma"], species=B["species"])
+    for c, T in enumerate(baths):
+        sim.set_bath(c, T["temperature"], T["tau"], T["seed"], species=T["species"])
+    sim.set_state(w.x, w.y, w.z, w.vx, w.vy, w.vz, 0.0)
+    return sim
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_cooled_run_matches_oracle(torch_gpu, oracle_mod, prec, tol):
+    """Two species, a beam on each and two baths (one species-selective), run in
+    two calls (120 + 80 steps) so the second continues the draw sequence.  The
+    cloud is chaotic: the bar is the larger of tol x displacement and 10x the
+    oracle's own divergence under a one-ulp change of the start positions (a
+    wrong draw, species or factor moves positions by ~1e-8 m)."""
+    w = li.random_cloud(700, seed=41, sigma=200e-6, light_fraction=0.3)
+    sp = _species(w)
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
+    sim = _cooled_sim(w, prec, oracle_mod, sp)
+    sim.step(120, spec.dt)
+    assert sim.step_index() == 120
+    sim.step(80, spec.dt)
+    st, t = sim.get_state()
+    ref = oracle_mod.step_cooled(w.state(), w.charge, w.mass, sp, tr, spec.gamma, beams=BEAMS,
+                                 baths=BATHS, dt=spec.dt, nsteps=120)
+    ref = oracle_mod.step_cooled(ref, w.charge, w.mass, sp, tr, spec.gamma, beams=BEAMS,
+                                 baths=BATHS, step_base=120, t_start=ref["t"], dt=spec.dt,
+                                 nsteps=80)
+    disp = np.max(np.abs(ref["x"] - w.x))
+    err = max(np.max(np.abs(st[k] - ref[k])) for k in ("x", "y", "z"))
+    vscale = np.max(np.abs(ref["vx"]))
+    verr = max(np.max(np.abs(st[k] - ref[k])) for k in ("vx", "vy", "vz"))
+    env_x, env_v = _envelope(
+        lambda s0: oracle_mod.step_cooled(s0, w.charge, w.mass, sp, tr, spec.gamma, beams=BEAMS,
+                                          baths=BATHS, dt=spec.dt, nsteps=200), w.state())
+    print(f"{prec}: |dx| {err:.3e} (disp {disp:.3e}, 1-ulp envelope {env_x:.3e}), "
+          f"|dv| {verr:.3e} (v {vscale:.3e}, envelope {env_v:.3e})")
+    assert err < max(tol * disp, 10 * env_x)
+    assert verr < max(10 * tol * vscale, 10 * env_v)
+    # the baths did act: without them the run differs far beyond the tolerance
+    plain = oracle_mod.step_cooled(w.state(), w.charge, w.mass, sp, tr, spec.gamma, beams=BEAMS,
+                                   dt=spec.dt, nsteps=200)
+    assert np.max(np.abs(plain["vx"] - ref["vx"])) > 0.01 * vscale
+    sim.close()
+
+
+def test_beam_cooling_of_free_ions_is_exact(torch_gpu, oracle_mod):
+    """Neutral ions with no trap field: along the beam the velocity decays as
+    exp(-gamma t), across it nothing changes, and ions of the other species are
+    untouched (bit for bit)."""
+    from paper_1907_10514_amd import Simulation
+
+    rng = np.random.default_rng(3)
+    n = 96
+    k = _unit(rng.normal(size=3))
+    v = rng.normal(0, 2.0, (3, n))
+    sp = (np.arange(n) % 3 == 0).astype(np.int32)
+    m = np.full(n, li.REF_MASS)
+    for prec in ("fp64", "mixed"):
+        sim = Simulation(m, np.zeros(n), prec)
+        sim.set_species(sp)
+        sim.set_beam(2, k * 7.0, 1e6, species=0)  # normalised by the library
+        sim.set_state(np.zeros(n), np.zeros(n), np.zeros(n), v[0], v[1], v[2], 0.0)
+        sim.step(800, li.DT)
+        st, _ = sim.get_state()
+        vout = np.stack([st["vx"], st["vy"], st["vz"]])
+        decay = math.exp(-1e6 * 800 * li.DT)
+        for i in range(n):
+            par_in, par_out = k @ v[:, i], k @ vout[:, i]
+            if sp[i] == 0:
+                assert par_out == pytest.approx(par_in * decay, rel=1e-11), (prec, i)
+                perp = (vout[:, i] - par_out * k) - (v[:, i] - par_in * k)
+                assert np.max(np.abs(perp)) < 1e-14 * np.max(np.abs(v[:, i]))
+            else:
+                assert np.array_equal(vout[:, i], v[:, i]), (prec, i)
+        sim.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec, tol):
+    """Batched traps draw bath kicks by run-wide ion index (trap k's first ion is
+    offsets[k]); each trap matches the oracle run with that ion_base."""
+    w = li.batch512(n_traps=12, n_min=2, n_max=300, seed=23, nsteps=0)
+    rng = np.random.default_rng(4)
+    sp = rng.integers(0, 2, w.n).astype(np.int32)
+    sim = _cooled_sim(w, prec, oracle_mod, sp, chunk_steps=30)
+    dt = w.traps[0].dt
+    sim.step(100, dt)
+    st, _ = sim.get_state()
+    for k, spec in enumerate(w.traps):
+        o, e = int(w.offsets[k]), int(w.offsets[k + 1])
+        sub = {c: v[o:e] for c, v in w.state().items()}
+        ref = oracle_mod.step_cooled(sub, w.charge[o:e], w.mass[o:e], sp[o:e],
+                                     _oracle_trap(oracle_mod, spec), spec.gamma, beams=BEAMS,
+                                     baths=BATHS, dt=dt, nsteps=100, ion_base=o)
+        disp = np.max(np.abs(ref["x"] - sub["x"])) + 1e-12
+        err = max(np.max(np.abs(st[c][o:e] - ref[c])) for c in ("x", "y", "z"))
+        if err >= tol * disp:
+            env_x, _ = _envelope(
+                lambda s0: oracle_mod.step_cooled(s0, w.charge[o:e], w.mass[o:e], sp[o:e],
+                                                  _oracle_trap(oracle_mod, spec), spec.gamma,
+                                                  beams=BEAMS, baths=BATHS, dt=dt, nsteps=100,
+                                                  ion_base=o), sub)
+            assert err < 10 * env_x, (k, err, disp, env_x)
+    sim.close()
+
+
+def test_cooled_batch_rejects_unequal_steps(torch_gpu, oracle_mod):
+    from paper_1907_10514_amd import LionError
+    from paper_1907_10514_amd import lion as L
+
+    w = li.batch512(n_traps=4, n_min=2, n_max=50, seed=5, nsteps=0)
+    sim = _cooled_sim(w, "fp64", oracle_mod, np.zeros(w.n, dtype=np.int32))
+    dts = np.array([s.dt for s in w.traps]) * np.array([1.0, 1.1, 1.0, 1.0])
+    with pytest.raises(LionError) as ei:
+        sim.step(5, dts)
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    sim.set_bath(0, 0.0, 0.0, 0)
+    sim.set_bath(1, 0.0, 0.0, 0)
+    sim.set_beam(0, (1, 0, 0), 0.0)
+    sim.set_beam(1, (1, 0, 0), 0.0)
+    sim.step(5, dts)  # no cooling left: per-trap steps are fine again
+    sim.close()
+
+
+def test_cooled_runs_reproducible_and_resumable(torch_gpu, oracle_mod):
+    """Counter-based draws: reruns, graph vs plain launches and chunk sizes give
+    identical bits, and a run resumed in a fresh handle with set_step_index
+    continues the same draw sequence bit for bit (binary time step)."""
+    w = li.random_cloud(1500, seed=12, sigma=60e-6, light_fraction=0.3)
+    sp = _species(w)
+    dt = 2.0 ** -26
+    outs = []
+    for cfg in (dict(), dict(use_graph=2), dict(chunk_steps=7)):
+        sim = _cooled_sim(w, "mixed", oracle_mod, sp, **cfg)
+        sim.step(45, dt)
+        outs.append(sim.get_state()[0])
+        sim.close()
+    for o in outs[1:]:
+        for k in o:
+            assert np.array_equal(o[k], outs[0][k]), k
+    a = _cooled_sim(w, "fp64", oracle_mod, sp)
+    a.step(100, dt)
+    sa, ta = a.get_state()
+    b = _cooled_sim(w, "fp64", oracle_mod, sp)
+    b.step(60, dt)
+    sb, tb = b.get_state()
+    c = _cooled_sim(w, "fp64", oracle_mod, sp)
+    c.set_state(sb["x"], sb["y"], sb["z"], sb["vx"], sb["vy"], sb["vz"], tb)
+    c.set_step_index(b.step_index())
+    c.step(40, dt)
+    sc, tc = c.get_state()
+    assert tc == ta and c.step_index() == 100
+    for k in sa:
+        assert np.array_equal(sa[k], sc[k]), k
+    for s in (a, b, c):
+        s.close()
+
+
+def test_langevin_bath_thermalises_on_gpu(torch_gpu, oracle_mod):
+    """Free neutral ions in one bath reach k_B T = M <v_x^2> (three axes, 4096
+    ions, after 10 relaxation times), in the batched kernel too."""
+    from paper_1907_10514_amd import Simulation
+
+    n, T, tau, dt = 4096, 1e-3, 2e-6, 1e-7
+    m = np.full(n, li.REF_MASS)
+    z = np.zeros(n)
+    for npt in (None, [1024] * 4):
+        sim = Simulation(m, z, "fp64", n_per_trap=npt)
+        sim.set_bath(3, T, tau, 2024)
+        sim.set_state(z, z, z, z, z, z, 0.0)
+        sim.step(200, dt)
+        st, _ = sim.get_state()
+        v2 = np.stack([st["vx"], st["vy"], st["vz"]]) ** 2
+        temp = li.REF_MASS * v2.mean() / li.K_B
+        assert abs(temp - T) < 4 * T * math.sqrt(2 / (3 * n)), temp
+        sim.close()

@@ -625,3 +625,27 @@ def test_langevin_baths_follow_newtons_law_of_cooling(oracle_mod):
             pred = T + (temps0[g] - T) * math.exp(-2 * t / tau)
             sigma = pred * math.sqrt(2 / (3 * per))
             assert abs(meas - pred) < 4 * sigma, (g, t, meas, pred)
+
+
+def test_bath_draws_follow_run_wide_ion_numbering(oracle_mod):
+    """A trap inside a batch draws its bath kicks as ions ion_base.. of the run:
+    for neutral ions (no coupling) the last five ions of a ten-ion run equal a
+    five-ion run with ion_base = 5, and differ from one with ion_base = 0."""
+    n = 10
+    rng = np.random.default_rng(21)
+    st = {p: rng.normal(0, 1e-5, n) for p in ("x", "y", "z")}
+    st.update({p: rng.normal(0, 0.5, n) for p in ("vx", "vy", "vz")})
+    m = np.full(n, CA)
+    sp = np.zeros(n, dtype=np.int32)
+    bath = [dict(temperature=1e-3, tau=5e-6, seed=77)]
+    tr = _trap(oracle_mod)
+    full = oracle_mod.step_cooled(st, np.zeros(n), m, sp, tr, 1e5, baths=bath, dt=li.DT,
+                                  nsteps=25, step_base=3)
+    tail = {k: v[5:] for k, v in st.items()}
+    part = oracle_mod.step_cooled(tail, np.zeros(5), m[5:], sp[5:], tr, 1e5, baths=bath,
+                                  dt=li.DT, nsteps=25, step_base=3, ion_base=5)
+    wrong = oracle_mod.step_cooled(tail, np.zeros(5), m[5:], sp[5:], tr, 1e5, baths=bath,
+                                   dt=li.DT, nsteps=25, step_base=3, ion_base=0)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(full[k][5:], part[k])
+        assert not np.array_equal(full[k][5:], wrong[k])
