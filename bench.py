@@ -73,17 +73,75 @@ def time_single(torch, w, precision, steps, warmup, reps):
     sync(torch)
     el = time.perf_counter() - t0
     finite = sim.check_finite() == 0
+    chunk = chunk_times(torch, sim, dt)
     kernel_ms = sim.time_pair_kernel(reps)
     cfg = sim.config()
     sim.close()
     n = w.n
     pairs = n * (n - 1)
     return dict(pairs_per_s=pairs * steps / el, steps_per_s=steps / el,
-                ms_per_step=1e3 * el / steps, pair_kernel_ms=kernel_ms,
+                ms_per_step=1e3 * el / steps, chunk_ms_per_step=chunk, pair_kernel_ms=kernel_ms,
                 pair_kernel_tflops=FLOP_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12,
                 pct_vector_peak=100.0 * FLOP_PER_PAIR * pairs * steps / el / 1e12
                 / PEAK_TFLOPS[precision],
                 finite=finite, launch=cfg)
+
+
+def chunk_times(torch, sim, dt, launches=10, steps=100):
+    """ms per step of single 100-step calls (one graph launch each), timed with
+    events on the simulation's stream: median and min over the launches."""
+    import statistics
+
+    ms = []
+    for _ in range(launches):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(steps, dt)
+        e1.record(sim.stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1) / steps)
+    return dict(median=statistics.median(ms), min=min(ms), launches=launches,
+                steps_per_launch=steps)
+
+
+def _parse_clocks(text):
+    try:
+        data = json.loads(text)
+    except ValueError:
+        return None
+    card = next(iter(data.values()), {}) if isinstance(data, dict) else {}
+    return {k: v for k, v in card.items() if "clk" in k.lower() or "clock" in k.lower()} or None
+
+
+def gpu_clocks(torch=None, w=None, precision="mixed", max_s=20.0):
+    """Shader and memory clocks as rocm-smi reports them.  With a workload the
+    reading is taken while that workload steps on the GPU (rocm-smi runs as a
+    child process meanwhile); without one, at idle.  None if the tool is
+    unavailable."""
+    import subprocess
+
+    try:
+        proc = subprocess.Popen(["rocm-smi", "--showclocks", "--json"], stdout=subprocess.PIPE,
+                                stderr=subprocess.DEVNULL, text=True)
+    except OSError:
+        return None
+    if torch is not None and w is not None:
+        from paper_1907_10514_amd import runner
+
+        sim = runner.simulation_for(w, precision=precision)
+        t0 = time.perf_counter()
+        while proc.poll() is None and time.perf_counter() - t0 < max_s:
+            sim.step(500, w.traps[0].dt)
+            sync(torch)
+        sim.close()
+    try:
+        out, _ = proc.communicate(timeout=30)
+    except subprocess.SubprocessError:
+        proc.kill()
+        proc.communicate()
+        return None
+    return _parse_clocks(out)
 
 
 def time_batch(torch, precision, steps, warmup, seq_steps):
@@ -188,12 +246,32 @@ def cpu_baseline(w, seconds):
     el = time.perf_counter() - t0
     steps, evals = k, k + 1
     n = w.n
+    cores = oracle.num_threads()
+    # the same oracle on one core: one step (two force evaluations)
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.step(st, w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, 1)
+    el1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
     return dict(value=n * (n - 1) * evals / el, unit="pair-interactions/s",
-                cores=oracle.num_threads(), kind="oracle",
+                cores=cores, kind="oracle",
                 steps_per_s=steps / el,
+                single_core_value=n * (n - 1) * 2 / el1,
                 sample=f"{steps} steps of the {n}-ion workload in {el:.1f} s (FP64 oracle, "
                        f"OpenMP over targets; {evals} all-pairs force evaluations, each "
-                       f"N(N-1) pair interactions)")
+                       f"N(N-1) pair interactions); single_core_value: 1 step (2 evaluations) "
+                       f"on one thread in {el1:.1f} s")
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def profile_pass(torch, w, precisions):
@@ -330,7 +408,9 @@ def main():
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     out["device"] = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
-                     "cu": props.multi_processor_count}
+                     "cu": props.multi_processor_count,
+                     "clocks_under_load": gpu_clocks(torch, w, head),
+                     "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 

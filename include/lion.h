@@ -146,6 +146,23 @@ int lion_set_bath(lion_sim *sim, int32_t bath, int32_t species, double temperatu
 int lion_set_step_index(lion_sim *sim, int64_t steps_done);
 int64_t lion_get_step_index(const lion_sim *sim);
 
+/* Time average of the ion velocities (section "Writing/reading data": timeAvg,
+ * a per-ion average over a duration such as one rf period, written once per
+ * duration).  window_steps >= 1 starts averaging at the current run-wide step
+ * count S0 (see lion_get_step_index): window k covers steps S0 + (k-1) W + 1 ..
+ * S0 + k W, each contributing the velocity at the end of that step, and the
+ * average of a window is the plain mean of its W samples.  0 turns it off.
+ * Each call clears the sums and the last average.  Later changes of the step
+ * index do not move S0: call this again after lion_set_step_index.
+ * window_steps < 0 -> LION_ERR_ARG. */
+int lion_set_time_average(lion_sim *sim, int32_t window_steps);
+
+/* Average velocities [n] of the last completed window and the run-wide step at
+ * which it closed.  Averaging off, or no window completed yet ->
+ * LION_ERR_STATE; NULL outputs -> LION_ERR_ARG. */
+int lion_get_time_average(lion_sim *sim, double *vx, double *vy, double *vz,
+                          int64_t *window_end_step);
+
 /* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite).
  * nsteps = 0 is a no-op.  Time afterwards: t + nsteps dt.  Requires
  * lion_set_state first (else LION_ERR_STATE). */

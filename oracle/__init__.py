@@ -89,6 +89,8 @@ def bind(path: str):
     tp = ctypes.POINTER(_Trap)
     lib.oracle_coulomb_constant.restype = ctypes.c_double
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     lib.oracle_coulomb_field.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp]
     lib.oracle_coulomb_field.restype = i64
     lib.oracle_accel.argtypes = [i64, dp, dp, dp, dp, dp, tp, ctypes.c_double, dp, dp, dp]
@@ -116,6 +118,9 @@ def bind(path: str):
                                        ctypes.POINTER(_Bath), i64, i64, ctypes.c_double,
                                        ctypes.c_double, i64, dp]
     lib.oracle_step_cooled.restype = i64
+    lib.oracle_time_average.argtypes = [i64, i64, dp, i64, i64, i64, i64, dp,
+                                        ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_time_average.restype = i64
     lib.oracle_step.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
     lib.oracle_step.restype = i64
@@ -150,6 +155,11 @@ def _f64(a) -> np.ndarray:
 def num_threads() -> int:
     """OpenMP threads the oracle's loops run on."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count for the oracle's later loops (timing on one core)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def coulomb_constant() -> float:
@@ -292,6 +302,22 @@ def step_cooled(state: dict, charge, mass, species, trap: Trap, gamma: float, be
                                ctypes.byref(t_end))
     s.update(ax=ax, ay=ay, az=az, t=t_end.value)
     return s
+
+
+def time_average(samples, first_step: int, origin: int, window: int):
+    """timeAvg: means of the windows of ``window`` steps closing at origin + m W
+    that lie wholly among ``samples`` (rows taken at the end of run-wide steps
+    first_step, first_step + 1, ...).  Returns (end_steps, means[n_windows, n])."""
+    a = np.ascontiguousarray(samples, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    ns, n = a.shape
+    maxw = max(1, ns // max(1, int(window)) + 1)
+    means = np.empty((maxw, n))
+    ends = np.empty(maxw, dtype=np.int64)
+    k = _load().oracle_time_average(n, ns, _d(a), int(first_step), int(origin), int(window), maxw,
+                                    _d(means), ends.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return ends[:k].copy(), means[:k].copy()
 
 
 def energy(state: dict, charge, mass, trap: Trap):

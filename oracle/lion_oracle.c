@@ -59,6 +59,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Sets the thread count of later OpenMP loops (for timing the oracle on one
+ * core); n < 1 is ignored. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Neumaier running sum: value s, compensation c. */
 typedef struct { double s, c; } nsum;
 
@@ -507,4 +517,35 @@ int64_t oracle_step_cooled(int64_t n, double *x, double *y, double *z, double *v
     }
     *t_end = t_start + (double)nsteps * dt;
     return coincident;
+}
+
+/* Time average of a per-ion quantity (section "Writing/reading data": timeAvg
+ * averages a variable over a duration, e.g. one rf period).  samples holds
+ * nsamples rows of n values; row k was taken at the end of run-wide step
+ * first_step + k.  Averaging windows of W steps close at steps origin + m W
+ * (m = 1, 2, ...); window m covers the W steps origin + (m-1) W + 1 .. origin + m W.
+ * Every window whose steps all lie among the samples is written, in order: its
+ * mean (plain sum in step order, divided by W) to a row of `means` and its
+ * closing step to end_steps.  Returns the number of windows written (at most
+ * max_windows). */
+int64_t oracle_time_average(int64_t n, int64_t nsamples, const double *samples,
+                            int64_t first_step, int64_t origin, int64_t W, int64_t max_windows,
+                            double *means, int64_t *end_steps) {
+    int64_t count = 0;
+    if (W < 1) return 0;
+    const int64_t last_step = first_step + nsamples - 1;
+    for (int64_t m = 1; count < max_windows; ++m) {
+        const int64_t end = origin + m * W;
+        const int64_t start = end - W + 1;
+        if (end > last_step) break;
+        if (start < first_step) continue;
+        for (int64_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int64_t s = start; s < start + W; ++s) acc = acc + samples[(s - first_step) * n + i];
+            means[count * n + i] = acc / (double)W;
+        }
+        end_steps[count] = end;
+        ++count;
+    }
+    return count;
 }

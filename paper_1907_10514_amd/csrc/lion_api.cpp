@@ -38,6 +38,8 @@ struct lion_sim {
     bool state_set = false;
     bool has_bodies = false;
     int64_t steps_done = 0;           // run-wide step count (numbers the bath draws)
+    int32_t avg_window = 0;           // velocity time average: window in steps (0: off)
+    int64_t avg_origin = 0;           // steps_done when the averaging was (re)started
     struct Beam { double kx, ky, kz, gamma; int32_t species; };
     struct Bath { double temperature, tau; uint64_t seed; int32_t species; };
     Beam beams[lion::kMaxBeams] = {};
@@ -77,7 +79,7 @@ int slices_for(int64_t n) {
 
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
-        flags, body_code, body_gmin, body_gmax, cool, species, total;
+        flags, body_code, body_gmin, body_gmax, cool, species, vacc, vavg, total;
 };
 
 Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
@@ -109,6 +111,8 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.body_gmax = take(np / 16 * sizeof(int32_t));
     L.cool = take(sizeof(lion::CoolDev));
     L.species = take(np * sizeof(int32_t));
+    L.vacc = take(3 * np * sizeof(double));
+    L.vavg = take(3 * np * sizeof(double));
     L.total = o;
     return L;
 }
@@ -197,6 +201,8 @@ int upload_cooling(lion_sim* s, double dt) {
         if (D.on) C.nbaths = c + 1;
     }
     C.step_base = s->steps_done;
+    C.avg_window = s->avg_window;
+    C.avg_origin = s->avg_origin;
     LION_HIP(s, hipMemcpyAsync(s->d.cool, &s->cool, sizeof(lion::CoolDev), hipMemcpyHostToDevice,
                                s->stream));
     return LION_OK;
@@ -340,6 +346,8 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     d.flags = (int32_t*)(base + L.flags);
     d.cool = (lion::CoolDev*)(base + L.cool);
     d.species = (int32_t*)(base + L.species);
+    d.vacc = (double*)(base + L.vacc);
+    d.vavg = (double*)(base + L.vavg);
     d.body_code = nullptr;  // set by lion_set_bodies
     d.body_gmin = nullptr;
     d.body_gmax = nullptr;
@@ -386,6 +394,8 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
               hipMemsetAsync(d.counter, 0, 8, st) == hipSuccess &&
               hipMemsetAsync(d.flags, 0, 16, st) == hipSuccess &&
               hipMemsetAsync(d.species, 0, np * 4, st) == hipSuccess &&
+              hipMemsetAsync(d.vacc, 0, 3 * np * 8, st) == hipSuccess &&
+              hipMemsetAsync(d.vavg, 0, 3 * np * 8, st) == hipSuccess &&
               hipMemcpyAsync(d.cool, &s->cool, sizeof(lion::CoolDev), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemcpyAsync(d.traps, s->traps.data(), n_traps * sizeof(TrapDev), hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok && d.srcm) ok = lion::launch_pack_mixed(d, st) == hipSuccess;
@@ -594,6 +604,36 @@ int lion_set_step_index(lion_sim* s, int64_t steps_done) {
 }
 
 int64_t lion_get_step_index(const lion_sim* s) { return s ? s->steps_done : -1; }
+
+int lion_set_time_average(lion_sim* s, int32_t window_steps) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (window_steps < 0) return fail(s, LION_ERR_ARG, "window_steps must be >= 0");
+    s->avg_window = window_steps;
+    s->avg_origin = s->steps_done;
+    const int64_t np = s->d.n_pad;
+    LION_HIP(s, hipSetDevice(s->device));
+    LION_HIP(s, hipMemsetAsync(s->d.vacc, 0, 3 * np * 8, s->stream));
+    LION_HIP(s, hipMemsetAsync(s->d.vavg, 0, 3 * np * 8, s->stream));
+    LION_HIP(s, hipStreamSynchronize(s->stream));
+    return LION_OK;
+}
+
+int lion_get_time_average(lion_sim* s, double* vx, double* vy, double* vz,
+                          int64_t* window_end_step) {
+    if (check_handle(s) || !vx || !vy || !vz || !window_end_step)
+        return fail(s, LION_ERR_ARG, "null output pointer");
+    if (s->avg_window <= 0) return fail(s, LION_ERR_STATE, "time averaging is off");
+    const int64_t done = s->steps_done - s->avg_origin;
+    if (done < s->avg_window) return fail(s, LION_ERR_STATE, "no averaging window completed yet");
+    const int64_t n = s->n, np = s->d.n_pad;
+    LION_HIP(s, hipSetDevice(s->device));
+    LION_HIP(s, hipMemcpyAsync(vx, s->d.vavg, n * 8, hipMemcpyDeviceToHost, s->stream));
+    LION_HIP(s, hipMemcpyAsync(vy, s->d.vavg + np, n * 8, hipMemcpyDeviceToHost, s->stream));
+    LION_HIP(s, hipMemcpyAsync(vz, s->d.vavg + 2 * np, n * 8, hipMemcpyDeviceToHost, s->stream));
+    LION_HIP(s, hipStreamSynchronize(s->stream));
+    *window_end_step = s->avg_origin + (done / s->avg_window) * s->avg_window;
+    return LION_OK;
+}
 
 int lion_set_damping(lion_sim* s, int32_t trap, double gamma) {
     if (check_handle(s)) return LION_ERR_ARG;

@@ -68,6 +68,11 @@ struct CoolDev {
     int32_t nbeams;      // highest active beam index + 1 (0: none)
     int32_t nbaths;
     int64_t step_base;   // steps completed before the current lion_step call
+    // time average of the velocities: window length in steps (0: off) and the
+    // run-wide step count at which the averaging was (re)started
+    int32_t avg_window;
+    int32_t avg_pad;
+    int64_t avg_origin;
 };
 
 // One ion of the FP32 pair stream: high and low float parts of the scaled
@@ -106,8 +111,10 @@ struct DevState {
     int32_t* order;   // [n_traps] launch order (largest trap first)
     int64_t* counter; // step index inside the current call
     int32_t* flags;   // [4] diagnostics (non-finite count)
-    CoolDev* cool;    // beams and baths
+    CoolDev* cool;    // beams, baths and the velocity time average
     int32_t* species; // [n_pad] species label per ion (default 0)
+    double* vacc;     // [3][n_pad] velocity sums of the open averaging window
+    double* vavg;     // [3][n_pad] average of the last completed window
     // rigid-body exclusion (all NULL when no bodies are set)
     int32_t* body_code;  // [n_pad] body id >= 0, or -1 - i for a free ion i
     int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions

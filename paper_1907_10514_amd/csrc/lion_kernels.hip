@@ -245,6 +245,32 @@ __device__ __forceinline__ void velocity_half(const CoolDev* __restrict__ C, int
     }
 }
 
+// Velocity time average over windows of W steps: the velocity at the end of
+// each step is added to the open window's sums; the step that closes a window
+// publishes sums / W and restarts the sums.  `step` is the run-wide number of
+// the step just completed.
+__device__ __forceinline__ void time_average(const CoolDev* __restrict__ C, int64_t i,
+                                             int64_t n_pad, int64_t step, double* __restrict__ acc,
+                                             double* __restrict__ avg, double u, double v,
+                                             double w) {
+#pragma clang fp contract(off)
+    const int W = C->avg_window;
+    if (W <= 0) return;
+    const double sx = acc[i] + u, sy = acc[n_pad + i] + v, sz = acc[2 * n_pad + i] + w;
+    if ((step - C->avg_origin) % W == 0) {
+        avg[i] = sx / (double)W;
+        avg[n_pad + i] = sy / (double)W;
+        avg[2 * n_pad + i] = sz / (double)W;
+        acc[i] = 0.0;
+        acc[n_pad + i] = 0.0;
+        acc[2 * n_pad + i] = 0.0;
+    } else {
+        acc[i] = sx;
+        acc[n_pad + i] = sy;
+        acc[2 * n_pad + i] = sz;
+    }
+}
+
 // First half of a step: velocity half-step (damping, beams, baths), half kick,
 // drift.  `step` numbers steps from 1 over the whole run.
 __device__ __forceinline__ void half_step_drift(const TrapDev& T, const CoolDev* __restrict__ C,
@@ -863,7 +889,9 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
                                                 int64_t n, int64_t n_pad, double field_scale,
                                                 const TrapDev* __restrict__ traps,
                                                 const CoolDev* __restrict__ cool,
-                                                const int64_t* __restrict__ counter) {
+                                                const int64_t* __restrict__ counter,
+                                                double* __restrict__ vacc,
+                                                double* __restrict__ vavg) {
     __shared__ double red[kWaves - 1][3][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
@@ -909,6 +937,7 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
     const double mi = mass[i];
     double u = vx[i], v = vy[i], w = vz[i];
     end_kick(T, cool, i, sp, mi, step, u, v, w, a_x, a_y, a_z);
+    time_average(cool, i, n_pad, step, vacc, vavg, u, v, w);
     if (MODE == kModeEndDrift) {
         half_step_drift(T, cool, i, sp, mi, step + 1, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
         src[i] = p;
@@ -1001,6 +1030,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  const int64_t* __restrict__ offsets,
                                                  const int32_t* __restrict__ order,
                                                  const int64_t* __restrict__ counter,
+                                                 double* __restrict__ vacc,
+                                                 double* __restrict__ vavg, int64_t n_pad,
                                                  int nsteps, int accel_only) {
     constexpr int KMAX = kMaxTrap / BLOCK;  // ions per owner thread at most
     using S = typename BatchSrc<PREC>::T;
@@ -1162,9 +1193,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             if (owner && il < m) {
                 trap_accel(T, t, q_m[k], x[k], y[k], z[k], Sx[k], Sy[k], Sz[k], a0[k], a1[k],
                            a2[k]);
-                if (!accel_only)
+                if (!accel_only) {
                     end_kick(T, cool, o + il, sp[k], m_i[k], step0 + step, u[k], v[k], w[k],
                              a0[k], a1[k], a2[k]);
+                    time_average(cool, o + il, n_pad, step0 + step, vacc, vavg, u[k], v[k],
+                                 w[k]);
+                }
             }
         }
     }
@@ -1233,7 +1267,7 @@ hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_on
     k_batch<PREC, BLOCK><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
                                                     s.qm, s.qe, s.mass, s.species, s.traps,
                                                     s.cool, s.offsets, s.order, s.counter,
-                                                    nsteps, accel_only);
+                                                    s.vacc, s.vavg, s.n_pad, nsteps, accel_only);
     return hipGetLastError();
 }
 
@@ -1307,19 +1341,19 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
             k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                     s.az, s.qm, s.qe, s.mass, s.species, s.part,
                                                     ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                    s.cool, ctr);
+                                                    s.cool, ctr, s.vacc, s.vavg);
             break;
         case kModeEnd:
             k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                   s.az, s.qm, s.qe, s.mass, s.species, s.part,
                                                   ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                  s.cool, ctr);
+                                                  s.cool, ctr, s.vacc, s.vavg);
             break;
         default:
             k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
                                                        s.ay, s.az, s.qm, s.qe, s.mass, s.species,
                                                        s.part, ls.j_split, s.n, s.n_pad, scale,
-                                                       s.traps, s.cool, ctr);
+                                                       s.traps, s.cool, ctr, s.vacc, s.vavg);
             break;
     }
     return hipGetLastError();

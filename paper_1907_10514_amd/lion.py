@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH):
     lib.lion_set_step_index.argtypes = [vp, i64]
     lib.lion_get_step_index.argtypes = [vp]
     lib.lion_get_step_index.restype = i64
+    lib.lion_set_time_average.argtypes = [vp, i32]
+    lib.lion_get_time_average.argtypes = [vp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lion_step.argtypes = [vp, i64, d]
     lib.lion_step_batch.argtypes = [vp, i64, dp]
     lib.lion_get_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
@@ -96,7 +98,8 @@ def load(path: str = LIB_PATH):
     lib.lion_constants.restype = None
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
                  "lion_set_damping", "lion_set_bodies", "lion_set_species", "lion_set_beam",
-                 "lion_set_bath", "lion_set_step_index", "lion_step", "lion_step_batch", "lion_get_state",
+                 "lion_set_bath", "lion_set_step_index", "lion_set_time_average",
+                 "lion_get_time_average", "lion_step", "lion_step_batch", "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite",
                  "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
                  "lion_time_pair_kernel", "lion_time_batch_kernel"):
@@ -192,6 +195,17 @@ def lion_set_step_index(h, steps_done):
 
 def lion_get_step_index(h) -> int:
     return int(load().lion_get_step_index(h))
+
+
+def lion_set_time_average(h, window_steps):
+    _check(load().lion_set_time_average(h, int(window_steps)), h)
+
+
+def lion_get_time_average(h, n):
+    out = [np.empty(int(n)) for _ in range(3)]
+    end = ctypes.c_int64(-1)
+    _check(load().lion_get_time_average(h, *[_dp(a) for a in out], ctypes.byref(end)), h)
+    return out, int(end.value)
 
 
 def lion_step(h, nsteps, dt):
@@ -355,6 +369,14 @@ class Simulation:
 
     def step_index(self) -> int:
         return lion_get_step_index(self.h)
+
+    def set_time_average(self, window_steps):
+        """Average the velocities over windows of window_steps steps (0: off)."""
+        lion_set_time_average(self.h, window_steps)
+
+    def time_average(self):
+        """((vx, vy, vz) averages of the last completed window, its end step)."""
+        return lion_get_time_average(self.h, self.n)
 
     def set_damping(self, gamma, trap=-1):
         lion_set_damping(self.h, trap, gamma)

@@ -85,6 +85,27 @@ def _count_failures(so, pin_list):
     return failures
 
 
+AVERAGE_MUTANTS = {
+    "window_starts_one_step_early": ("const int64_t start = end - W + 1;",
+                                     "const int64_t start = end - W;"),
+    "mean_divides_by_w_minus_1": ("means[count * n + i] = acc / (double)W;",
+                                  "means[count * n + i] = acc / (double)(W - 1);"),
+    "windows_aligned_to_step_zero": ("const int64_t end = origin + m * W;",
+                                     "const int64_t end = m * W;"),
+}
+
+AVERAGE_PINS = [
+    lambda o: pins.test_time_average_of_damped_free_ion_closed_form(o),
+    lambda o: pins.test_time_average_window_alignment(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(AVERAGE_MUTANTS))
+def test_time_average_pins_reject_mutant(tmp_path, name, oracle_mod):
+    so = _build_mutant(tmp_path, *AVERAGE_MUTANTS[name])
+    assert _count_failures(so, AVERAGE_PINS) >= 1, f"no pin caught mutant {name}"
+
+
 @pytest.mark.parametrize("name", sorted(COOLING_MUTANTS))
 def test_cooling_pins_reject_mutant(tmp_path, name, oracle_mod):
     so = _build_mutant(tmp_path, *COOLING_MUTANTS[name])

@@ -649,3 +649,41 @@ def test_bath_draws_follow_run_wide_ion_numbering(oracle_mod):
     for k in ("x", "y", "z", "vx", "vy", "vz"):
         assert np.array_equal(full[k][5:], part[k])
         assert not np.array_equal(full[k][5:], wrong[k])
+
+
+def test_time_average_of_damped_free_ion_closed_form(oracle_mod):
+    """timeAvg over windows of W steps: for a free ion under isotropic damping
+    the velocity after step s is v0 r^s with r = exp(-gamma dt) (each step
+    applies two exact half-step factors), so the mean over the window of steps
+    a .. a + W - 1 is the geometric sum (v0 / W) r^a (1 - r^W) / (1 - r).
+    Averaging started at step 3: windows close at steps 23 and 43."""
+    gamma, dt, W, origin = 1e6, li.DT, 20, 3
+    st = {k: np.array([v]) for k, v in
+          (("x", 0.0), ("y", 0.0), ("z", 0.0), ("vx", 2.5), ("vy", -1.0), ("vz", 0.25))}
+    samples, t = [], 0.0
+    for _ in range(60):
+        st = oracle_mod.step(st, [li.E_CHARGE], [li.REF_MASS], oracle_mod.Trap(), gamma, t, dt, 1)
+        t = st["t"]
+        samples.append([st["vx"][0], st["vy"][0], st["vz"][0]])
+    ends, means = oracle_mod.time_average(np.array(samples), 1, origin, W)
+    assert list(ends) == [23, 43]
+    r = math.exp(-gamma * dt)
+    for end, mean in zip(ends, means):
+        a = end - W + 1
+        geo = r ** a * (1 - r ** W) / (1 - r) / W
+        for v0, m in zip((2.5, -1.0, 0.25), mean):
+            assert m == pytest.approx(v0 * geo, rel=1e-12)
+
+
+def test_time_average_window_alignment(oracle_mod):
+    """Samples equal to their step number average to the window's mid-step
+    exactly; windows reaching before the first sample are skipped; constant
+    samples average to themselves bit for bit."""
+    steps = np.arange(10, 31, dtype=np.float64)  # samples of steps 10 .. 30
+    ends, means = oracle_mod.time_average(steps, 10, 0, 4)
+    assert list(ends) == [16, 20, 24, 28]  # the window 9 .. 12 starts before step 10
+    assert np.array_equal(means[:, 0], (ends - 1.5).astype(np.float64))
+    c = np.full((12, 3), 0.1)
+    ends, means = oracle_mod.time_average(c, 1, 0, 3)
+    assert list(ends) == [3, 6, 9, 12]
+    assert np.all(np.abs(means - 0.1) <= 2 * np.finfo(float).eps * 0.1)
