@@ -118,6 +118,11 @@ def bind(path: str):
                                        ctypes.POINTER(_Bath), i64, i64, ctypes.c_double,
                                        ctypes.c_double, i64, dp]
     lib.oracle_step_cooled.restype = i64
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_step_rigid.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip, dp,
+                                      ctypes.c_int32, dp, dp, dp, dp, dp, dp, tp, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, i64, dp]
+    lib.oracle_step_rigid.restype = i64
     lib.oracle_time_average.argtypes = [i64, i64, dp, i64, i64, i64, i64, dp,
                                         ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_time_average.restype = i64
@@ -302,6 +307,112 @@ def step_cooled(state: dict, charge, mass, species, trap: Trap, gamma: float, be
                                ctypes.byref(t_end))
     s.update(ax=ax, ay=ay, az=az, t=t_end.value)
     return s
+
+
+def _matrix_to_quaternion(A):
+    """Unit quaternion (w, x, y, z) of the rotation matrix A (Shepperd's choice of
+    the largest diagonal term for a well-conditioned square root)."""
+    tr = A[0, 0] + A[1, 1] + A[2, 2]
+    if tr > 0:
+        s = math.sqrt(tr + 1.0) * 2
+        q = [0.25 * s, (A[2, 1] - A[1, 2]) / s, (A[0, 2] - A[2, 0]) / s, (A[1, 0] - A[0, 1]) / s]
+    elif A[0, 0] > A[1, 1] and A[0, 0] > A[2, 2]:
+        s = math.sqrt(1.0 + A[0, 0] - A[1, 1] - A[2, 2]) * 2
+        q = [(A[2, 1] - A[1, 2]) / s, 0.25 * s, (A[0, 1] + A[1, 0]) / s, (A[0, 2] + A[2, 0]) / s]
+    elif A[1, 1] > A[2, 2]:
+        s = math.sqrt(1.0 + A[1, 1] - A[0, 0] - A[2, 2]) * 2
+        q = [(A[0, 2] - A[2, 0]) / s, (A[0, 1] + A[1, 0]) / s, 0.25 * s, (A[1, 2] + A[2, 1]) / s]
+    else:
+        s = math.sqrt(1.0 + A[2, 2] - A[0, 0] - A[1, 1]) * 2
+        q = [(A[1, 0] - A[0, 1]) / s, (A[0, 2] + A[2, 0]) / s, (A[1, 2] + A[2, 1]) / s, 0.25 * s]
+    q = np.array(q)
+    return q / np.linalg.norm(q)
+
+
+def quaternion_matrix(q):
+    """Rotation matrix of the unit quaternion (w, x, y, z): body frame to space."""
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+RIGID_MOMENT_FLOOR = 1e-10  # principal moments below this fraction of the largest count as 0
+
+
+def rigid_setup(state: dict, mass, body) -> dict:
+    """Body state of the rigid groups (ions with equal body id >= 0), from the
+    ions' positions and velocities: mass, centre of mass, COM velocity, angular
+    momentum about the COM, principal axes of the inertia tensor (numpy eigh)
+    as the body frame (right-handed), inverse principal moments (0 below
+    RIGID_MOMENT_FLOOR of the largest), body-frame offsets of the members, and
+    member velocities replaced by the rigid motion V + omega x d."""
+    m = _f64(mass)
+    body = np.ascontiguousarray(body, dtype=np.int32)
+    pos = np.stack([_f64(state["x"]), _f64(state["y"]), _f64(state["z"])], 1)
+    vel = np.stack([_f64(state["vx"]), _f64(state["vy"]), _f64(state["vz"])], 1)
+    ids = np.unique(body[body >= 0])
+    n, nb = body.size, ids.size
+    rb = np.full(n, -1, dtype=np.int32)
+    M, R, V, L = np.zeros(max(nb, 1)), np.zeros((max(nb, 1), 3)), np.zeros((max(nb, 1), 3)), \
+        np.zeros((max(nb, 1), 3))
+    Q, inv_i = np.zeros((max(nb, 1), 4)), np.zeros((max(nb, 1), 3))
+    dbody = np.zeros((n, 3))
+    vel_out = vel.copy()
+    for k, b in enumerate(ids):
+        idx = np.nonzero(body == b)[0]
+        rb[idx] = k
+        mk = m[idx]
+        M[k] = mk.sum()
+        R[k] = (mk[:, None] * pos[idx]).sum(0) / M[k]
+        V[k] = (mk[:, None] * vel[idx]).sum(0) / M[k]
+        d = pos[idx] - R[k]
+        inertia = np.zeros((3, 3))
+        for mi, di in zip(mk, d):
+            inertia += mi * (np.dot(di, di) * np.eye(3) - np.outer(di, di))
+        evals, E = np.linalg.eigh(inertia)
+        if np.linalg.det(E) < 0:
+            E[:, 2] = -E[:, 2]
+        top = max(evals.max(), 0.0)
+        inv_i[k] = [1.0 / e if top > 0 and e > RIGID_MOMENT_FLOOR * top else 0.0 for e in evals]
+        Q[k] = _matrix_to_quaternion(E)
+        A = quaternion_matrix(Q[k])
+        dbody[idx] = d @ A
+        L[k] = (mk[:, None] * np.cross(d, vel[idx] - V[k])).sum(0)
+        w = A @ (inv_i[k] * (A.T @ L[k]))
+        vel_out[idx] = V[k] + np.cross(w, d)
+    return dict(rb=rb, body=body, nb=nb, M=M, R=R, V=V, L=L, q=Q, inv_i=inv_i, dbody=dbody,
+                vx=vel_out[:, 0].copy(), vy=vel_out[:, 1].copy(), vz=vel_out[:, 2].copy())
+
+
+def step_rigid(state: dict, charge, mass, body, trap: Trap, gamma: float, t_start: float,
+               dt: float, nsteps: int, rigid: dict | None = None) -> tuple[dict, dict]:
+    """``step`` with rigid bodies (see lion_oracle.c).  With rigid=None the body
+    state is set up from ``state`` by rigid_setup (member velocities become the
+    rigid motion); pass the returned body state to continue a run.  Returns
+    (ion state with accelerations and t, body state)."""
+    q_, m = _f64(charge), _f64(mass)
+    if rigid is None:
+        rigid = rigid_setup(state, m, body)
+        s = {k: _f64(state[k]).copy() for k in ("x", "y", "z")}
+        s.update(vx=rigid["vx"].copy(), vy=rigid["vy"].copy(), vz=rigid["vz"].copy())
+    else:
+        s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    rg = {k: (np.ascontiguousarray(v).copy() if isinstance(v, np.ndarray) else v)
+          for k, v in rigid.items()}
+    ax, ay, az, _ = accel_bodies(s["x"], s["y"], s["z"], q_, m, rg["body"], trap, t_start)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    t_end = ctypes.c_double(0.0)
+    tr = trap._c()
+    _load().oracle_step_rigid(s["x"].size, _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]),
+                              _d(s["vy"]), _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q_), _d(m),
+                              rg["body"].ctypes.data_as(ip), rg["rb"].ctypes.data_as(ip),
+                              _d(rg["dbody"]), int(rg["nb"]), _d(rg["M"]), _d(rg["inv_i"]),
+                              _d(rg["q"]), _d(rg["R"]), _d(rg["V"]), _d(rg["L"]),
+                              ctypes.byref(tr), float(gamma), float(t_start), float(dt),
+                              int(nsteps), ctypes.byref(t_end))
+    s.update(ax=ax, ay=ay, az=az, t=t_end.value)
+    return s, rg
 
 
 def time_average(samples, first_step: int, origin: int, window: int):

@@ -29,6 +29,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -548,4 +549,198 @@ int64_t oracle_time_average(int64_t n, int64_t nsamples, const double *samples,
         ++count;
     }
     return count;
+}
+
+/* ------------------------------------------------------------ rigid bodies
+ *
+ * Rigid clusters of ions (sections "Charged rigid body" and "Integration": the
+ * ions of a rigid group keep their relative positions and the group moves and
+ * rotates under the sum of the forces on its ions).  Each body b carries its
+ * mass M, centre of mass R, COM velocity V, angular momentum L about R (space
+ * frame), orientation quaternion q = (w, x, y, z) that turns body-frame vectors
+ * into space-frame ones, and inverse principal moments 1/I_k (0 for a moment
+ * that vanishes, e.g. along a rod).  Member i sits at R + A(q) d_i with d_i
+ * fixed in the body frame, and moves with V + omega x A(q) d_i where
+ * omega = A diag(1/I) A^T L.
+ *
+ * One step is the velocity-Verlet scheme for rigid bodies, with the damping
+ * half-steps of the free ions applied to V and L (scaling every member
+ * velocity by f scales both):
+ *   V <- f V, L <- f L;  V <- V + (dt/2) F/M,  L <- L + (dt/2) tau;  R <- R + dt V;
+ *   q advanced over dt with L held fixed (below);  members placed;
+ *   forces at t_{k+1} (pairs inside one body left out);
+ *   F = sum m_i a_i,  tau = sum A(q) d_i x m_i a_i;
+ *   V <- V + (dt/2) F/M,  L <- L + (dt/2) tau;  V <- f V, L <- f L.
+ * The orientation follows dq/dt = (1/2) (0, omega(q)) q (Hamilton product).  It
+ * is advanced by Richardson extrapolation of normalised Euler steps: one step
+ * of dt and two of dt/2 (omega re-evaluated at the midpoint), combined as
+ * 2 q_half - q_full and normalised.  This uses only the space-frame inertia
+ * tensor, so the result does not depend on how principal axes are chosen
+ * inside a degenerate eigenspace. */
+
+static void quat_matrix(const double q[4], double A[9]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    A[0] = 1.0 - 2.0 * (y * y + z * z);
+    A[1] = 2.0 * (x * y - w * z);
+    A[2] = 2.0 * (x * z + w * y);
+    A[3] = 2.0 * (x * y + w * z);
+    A[4] = 1.0 - 2.0 * (x * x + z * z);
+    A[5] = 2.0 * (y * z - w * x);
+    A[6] = 2.0 * (x * z - w * y);
+    A[7] = 2.0 * (y * z + w * x);
+    A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* omega = A diag(inv_i) A^T L */
+static void body_omega(const double q[4], const double inv_i[3], const double L[3],
+                       double w[3]) {
+    double A[9], p[3];
+    quat_matrix(q, A);
+    for (int k = 0; k < 3; ++k) p[k] = (A[k] * L[0] + A[3 + k] * L[1] + A[6 + k] * L[2]) * inv_i[k];
+    for (int r = 0; r < 3; ++r) w[r] = A[3 * r] * p[0] + A[3 * r + 1] * p[1] + A[3 * r + 2] * p[2];
+}
+
+/* q + s (0, w) q, normalised */
+static void quat_euler(const double q[4], const double w[3], double s, double out[4]) {
+    const double dw = -(w[0] * q[1] + w[1] * q[2] + w[2] * q[3]);
+    const double dx = w[0] * q[0] + (w[1] * q[3] - w[2] * q[2]);
+    const double dy = w[1] * q[0] + (w[2] * q[1] - w[0] * q[3]);
+    const double dz = w[2] * q[0] + (w[0] * q[2] - w[1] * q[1]);
+    double r[4] = {q[0] + s * dw, q[1] + s * dx, q[2] + s * dy, q[3] + s * dz};
+    double nrm = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    for (int k = 0; k < 4; ++k) out[k] = r[k] / nrm;
+}
+
+static void rotate_richardson(double q[4], const double L[3], const double inv_i[3], double dt) {
+    double w0[3], w1[3], qf[4], qh[4], qh2[4];
+    body_omega(q, inv_i, L, w0);
+    quat_euler(q, w0, 0.5 * dt, qf);
+    quat_euler(q, w0, 0.25 * dt, qh);
+    body_omega(qh, inv_i, L, w1);
+    quat_euler(qh, w1, 0.25 * dt, qh2);
+    double r[4];
+    for (int k = 0; k < 4; ++k) r[k] = 2.0 * qh2[k] - qf[k];
+    double nrm = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    for (int k = 0; k < 4; ++k) q[k] = r[k] / nrm;
+}
+
+/* Space-frame offset A(q) d of member i. */
+static void member_offset(const double *q, const double *dbody, int64_t i, double o[3]) {
+    double A[9];
+    quat_matrix(q, A);
+    const double *d = dbody + 3 * i;
+    for (int r = 0; r < 3; ++r) o[r] = A[3 * r] * d[0] + A[3 * r + 1] * d[1] + A[3 * r + 2] * d[2];
+}
+
+/* F_b = sum m_i a_i, tau_b = sum A d_i x m_i a_i over the members, ascending i. */
+static void body_wrench(int64_t n, const double *ax, const double *ay, const double *az,
+                        const double *mass, const int32_t *rb, const double *dbody,
+                        int32_t nb, const double *q, double *F, double *T) {
+    for (int32_t b = 0; b < nb; ++b)
+        for (int k = 0; k < 3; ++k) F[3 * b + k] = T[3 * b + k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t b = rb[i];
+        if (b < 0) continue;
+        double o[3];
+        member_offset(q + 4 * b, dbody, i, o);
+        const double fx = mass[i] * ax[i], fy = mass[i] * ay[i], fz = mass[i] * az[i];
+        F[3 * b] += fx;
+        F[3 * b + 1] += fy;
+        F[3 * b + 2] += fz;
+        T[3 * b] += o[1] * fz - o[2] * fy;
+        T[3 * b + 1] += o[2] * fx - o[0] * fz;
+        T[3 * b + 2] += o[0] * fy - o[1] * fx;
+    }
+}
+
+static void place_members(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                          double *vz, const int32_t *rb, const double *dbody, const double *R,
+                          const double *V, const double *L, const double *q,
+                          const double *inv_i) {
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t b = rb[i];
+        if (b < 0) continue;
+        double o[3], w[3];
+        member_offset(q + 4 * b, dbody, i, o);
+        body_omega(q + 4 * b, inv_i + 3 * b, L + 3 * b, w);
+        x[i] = R[3 * b] + o[0];
+        y[i] = R[3 * b + 1] + o[1];
+        z[i] = R[3 * b + 2] + o[2];
+        vx[i] = V[3 * b] + (w[1] * o[2] - w[2] * o[1]);
+        vy[i] = V[3 * b + 1] + (w[2] * o[0] - w[0] * o[2]);
+        vz[i] = V[3 * b + 2] + (w[0] * o[1] - w[1] * o[0]);
+    }
+}
+
+/* nsteps steps with rigid bodies.  rb[i] is the body index (0..nb-1) of ion i,
+ * or -1 for a free ion; body[i] the exclusion id passed to the force (pairs of
+ * ions with equal body[i] >= 0 are left out).  ax..az hold the accelerations
+ * at the starting state and t_start; member positions and velocities are
+ * written from the body state after every step.  Returns the number of
+ * coincident pairs met. */
+int64_t oracle_step_rigid(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                          double *vz, double *ax, double *ay, double *az, const double *charge,
+                          const double *mass, const int32_t *body, const int32_t *rb,
+                          const double *dbody, int32_t nb, const double *Mb, const double *inv_i,
+                          double *q, double *R, double *V, double *L, const oracle_trap *tp,
+                          double gamma, double t_start, double dt, int64_t nsteps,
+                          double *t_end) {
+    const double f = exp(-(gamma * dt) * 0.5);
+    const double h = 0.5 * dt;
+    int64_t coincident = 0;
+    double *F = (double *)malloc(sizeof(double) * 3 * (size_t)(nb > 0 ? nb : 1));
+    double *T = (double *)malloc(sizeof(double) * 3 * (size_t)(nb > 0 ? nb : 1));
+    double *sc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    body_wrench(n, ax, ay, az, mass, rb, dbody, nb, q, F, T);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (rb[i] >= 0) continue;
+            vx[i] = f * vx[i];
+            vy[i] = f * vy[i];
+            vz[i] = f * vz[i];
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            x[i] = x[i] + dt * vx[i];
+            y[i] = y[i] + dt * vy[i];
+            z[i] = z[i] + dt * vz[i];
+        }
+        for (int32_t b = 0; b < nb; ++b) {
+            for (int c = 0; c < 3; ++c) {
+                V[3 * b + c] = f * V[3 * b + c];
+                L[3 * b + c] = f * L[3 * b + c];
+                V[3 * b + c] = V[3 * b + c] + h * (F[3 * b + c] / Mb[b]);
+                L[3 * b + c] = L[3 * b + c] + h * T[3 * b + c];
+                R[3 * b + c] = R[3 * b + c] + dt * V[3 * b + c];
+            }
+            rotate_richardson(q + 4 * b, L + 3 * b, inv_i + 3 * b, dt);
+        }
+        place_members(n, x, y, z, vx, vy, vz, rb, dbody, R, V, L, q, inv_i);
+        double t = t_start + (double)(k + 1) * dt;
+        coincident += oracle_accel_bodies(n, x, y, z, charge, mass, body, tp, t, ax, ay, az, sc);
+        for (int64_t i = 0; i < n; ++i) {
+            if (rb[i] >= 0) continue;
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            vx[i] = f * vx[i];
+            vy[i] = f * vy[i];
+            vz[i] = f * vz[i];
+        }
+        body_wrench(n, ax, ay, az, mass, rb, dbody, nb, q, F, T);
+        for (int32_t b = 0; b < nb; ++b) {
+            for (int c = 0; c < 3; ++c) {
+                V[3 * b + c] = V[3 * b + c] + h * (F[3 * b + c] / Mb[b]);
+                L[3 * b + c] = L[3 * b + c] + h * T[3 * b + c];
+                V[3 * b + c] = f * V[3 * b + c];
+                L[3 * b + c] = f * L[3 * b + c];
+            }
+        }
+        place_members(n, x, y, z, vx, vy, vz, rb, dbody, R, V, L, q, inv_i);
+    }
+    free(F);
+    free(T);
+    free(sc);
+    *t_end = t_start + (double)nsteps * dt;
+    return coincident;
 }

@@ -46,9 +46,9 @@ def test_mathieu_helper_matches_oracle_and_inverts(oracle_mod):
     for q, a in [(0.3, -0.001), (0.2, -0.001), (0.6, -0.01), (0.1, 0.0)]:
         V0, U0 = lion.lion_mathieu_to_voltages(q, a, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
         V0o, U0o = oracle_mod.voltages_for(q, a, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
-        assert V0 == pytest.approx(V0o, rel=1e-15) and U0 == pytest.approx(U0o, rel=1e-15, abs=0)
+        assert V0 == pytest.approx(V0o, rel=1e-15, abs=0) and U0 == pytest.approx(U0o, rel=1e-15, abs=0)
         q2, a2 = oracle_mod.mathieu_coefficients(V0, U0, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
-        assert q2 == pytest.approx(q, rel=1e-14) and a2 == pytest.approx(a, rel=1e-14, abs=1e-18)
+        assert q2 == pytest.approx(q, rel=1e-14, abs=0) and a2 == pytest.approx(a, rel=1e-14, abs=1e-18)
     V0, U0 = lion.lion_mathieu_to_voltages(0.3, -0.001, M, Q, li.OMEGA, li.R0, li.Z0, li.KAPPA)
     assert V0 == pytest.approx(9.097272, abs=1e-6) and U0 == pytest.approx(0.242594, abs=1e-6)
 

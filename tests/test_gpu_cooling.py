@@ -145,7 +145,11 @@ def test_beam_cooling_of_free_ions_is_exact(torch_gpu, oracle_mod):
         for i in range(n):
             par_in, par_out = k @ v[:, i], k @ vout[:, i]
             if sp[i] == 0:
-                assert par_out == pytest.approx(par_in * decay, rel=1e-11), (prec, i)
+                # every half-step rounds each velocity component to ~u |v|;
+                # on the decayed parallel part these add up like a random walk
+                # over the 1600 half-steps (~40 u |v|): bound 10x that
+                assert par_out == pytest.approx(par_in * decay, rel=1e-11,
+                                                abs=1e-13 * np.max(np.abs(v[:, i]))), (prec, i)
                 perp = (vout[:, i] - par_out * k) - (v[:, i] - par_in * k)
                 assert np.max(np.abs(perp)) < 1e-14 * np.max(np.abs(v[:, i]))
             else:

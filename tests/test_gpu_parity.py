@@ -250,7 +250,7 @@ def test_free_ion_damping_exact(torch_gpu, oracle_mod):
     sim.set_state([0.0], [0.0], [0.0], [3.0], [-1.0], [0.5], 0.0)
     sim.step(1000, li.DT)
     st, _ = sim.get_state()
-    assert st["vx"][0] == pytest.approx(3.0 * math.exp(-1e6 * 1000 * li.DT), rel=1e-12)
+    assert st["vx"][0] == pytest.approx(3.0 * math.exp(-1e6 * 1000 * li.DT), rel=1e-12, abs=0)
     sim.close()
 
 
@@ -260,9 +260,9 @@ def test_energy_matches_oracle(torch_gpu, oracle_mod):
     sim = _sim(w, "fp64", oracle_mod)
     k, c, d = sim.energy()
     ko, co, do = oracle_mod.energy(w.state(), w.charge, w.mass, tr)
-    assert k == pytest.approx(ko, rel=1e-13)
-    assert c == pytest.approx(co, rel=1e-12)
-    assert d == pytest.approx(do, rel=1e-12)
+    assert k == pytest.approx(ko, rel=1e-13, abs=0)
+    assert c == pytest.approx(co, rel=1e-12, abs=0)
+    assert d == pytest.approx(do, rel=1e-12, abs=0)
     sim.close()
 
 

@@ -100,6 +100,39 @@ AVERAGE_PINS = [
 ]
 
 
+RIGID_MUTANTS = {
+    "torque_component_sign": ("T[3 * b] += o[1] * fz - o[2] * fy;",
+                              "T[3 * b] += o[2] * fy - o[1] * fz;"),
+    "full_angle_in_quaternion_step": ("quat_euler(q, w0, 0.5 * dt, qf);",
+                                      "quat_euler(q, w0, dt, qf);"),
+    "no_richardson_extrapolation": ("for (int k = 0; k < 4; ++k) r[k] = 2.0 * qh2[k] - qf[k];",
+                                    "for (int k = 0; k < 4; ++k) r[k] = qf[k];"),
+    "angular_momentum_not_damped": ("                L[3 * b + c] = f * L[3 * b + c];\n                V[3 * b + c] = V[3 * b + c] + h",
+                                    "                V[3 * b + c] = V[3 * b + c] + h"),
+    "body_frame_momentum_from_rows": ("p[k] = (A[k] * L[0] + A[3 + k] * L[1] + A[6 + k] * L[2]) * inv_i[k];",
+                                      "p[k] = (A[3 * k] * L[0] + A[3 * k + 1] * L[1] + A[3 * k + 2] * L[2]) * inv_i[k];"),
+    "member_velocity_without_spin": ("vx[i] = V[3 * b] + (w[1] * o[2] - w[2] * o[1]);",
+                                     "vx[i] = V[3 * b];"),
+    "force_not_mass_weighted": ("const double fx = mass[i] * ax[i], fy = mass[i] * ay[i], fz = mass[i] * az[i];",
+                                "const double fx = ax[i], fy = ay[i], fz = az[i];"),
+}
+
+RIGID_PINS = [
+    lambda o: pins.test_rigid_singleton_bodies_are_free_ions(o),
+    lambda o: pins.test_rigid_body_com_follows_single_ion(o),
+    lambda o: pins.test_rigid_rod_spin_is_uniform_rotation(o),
+    lambda o: pins.test_rigid_asymmetric_top_converges_to_euler_equations(o),
+    lambda o: pins.test_rigid_spin_down_under_damping(o),
+    lambda o: pins.test_rigid_coulomb_explosion_conserves_momenta(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(RIGID_MUTANTS))
+def test_rigid_pins_reject_mutant(tmp_path, name, oracle_mod):
+    so = _build_mutant(tmp_path, *RIGID_MUTANTS[name])
+    assert _count_failures(so, RIGID_PINS) >= 1, f"no pin caught mutant {name}"
+
+
 @pytest.mark.parametrize("name", sorted(AVERAGE_MUTANTS))
 def test_time_average_pins_reject_mutant(tmp_path, name, oracle_mod):
     so = _build_mutant(tmp_path, *AVERAGE_MUTANTS[name])
