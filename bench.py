@@ -192,8 +192,9 @@ def time_batch(torch, precision, steps, warmup, seq_steps):
 
 
 def time_clusters(torch, precision, steps, warmup, reps):
-    """The 65536-ion cloud with 64 rigid clusters: intra-cluster pairs left out
-    of the pair sum (body-id exclusion mask); per-ion steps."""
+    """The 65536-ion cloud with 64 rigid clusters integrated as rigid bodies:
+    intra-cluster pairs left out of the pair sum (body-id exclusion mask), body
+    force/torque reductions and rigid-body steps every step."""
     import numpy as np
 
     import lion_inputs as li
@@ -204,7 +205,7 @@ def time_clusters(torch, precision, steps, warmup, reps):
     sizes = np.bincount(body[body >= 0])
     pairs = w.n * (w.n - 1) - int(np.sum(sizes * (sizes - 1)))
     sim = runner.simulation_for(w, precision=precision)
-    sim.set_bodies(body)
+    sim.set_rigid_bodies(body)
     dt = w.traps[0].dt
     sim.step(warmup, dt)
     sync(torch)

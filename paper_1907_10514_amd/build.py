@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblion.so")
-SOURCES = ["lion_kernels.hip", "lion_api.cpp"]
+SOURCES = ["lion_kernels.hip", "lion_api.cpp", "lion_rigid_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

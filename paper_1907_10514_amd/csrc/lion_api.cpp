@@ -38,6 +38,9 @@ struct lion_sim {
     bool state_set = false;
     bool has_bodies = false;
     int64_t steps_done = 0;           // run-wide step count (numbers the bath draws)
+    bool rigid_on = false;            // rigid-body integration of the body groups
+    std::vector<int32_t> rigid_ids;   // [n] body id per ion while rigid_on
+    size_t rigid_off[5] = {0, 0, 0, 0, 0};  // workspace offsets: bodies, rb, dbody, members, start
     int32_t avg_window = 0;           // velocity time average: window in steps (0: off)
     int64_t avg_origin = 0;           // steps_done when the averaging was (re)started
     struct Beam { double kx, ky, kz, gamma; int32_t species; };
@@ -79,7 +82,8 @@ int slices_for(int64_t n) {
 
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
-        flags, body_code, body_gmin, body_gmax, cool, species, vacc, vavg, total;
+        flags, body_code, body_gmin, body_gmax, cool, species, vacc, vavg, rigid, rb, dbody,
+        rmembers, rstart, total;
 };
 
 Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
@@ -113,6 +117,12 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.species = take(np * sizeof(int32_t));
     L.vacc = take(3 * np * sizeof(double));
     L.vavg = take(3 * np * sizeof(double));
+    // rigid bodies (single trap only): room for one body per ion
+    L.rigid = batched ? SIZE_MAX : take(np * sizeof(lion::RigidDev));
+    L.rb = batched ? SIZE_MAX : take(np * sizeof(int32_t));
+    L.dbody = batched ? SIZE_MAX : take(3 * np * sizeof(double));
+    L.rmembers = batched ? SIZE_MAX : take(np * sizeof(int32_t));
+    L.rstart = batched ? SIZE_MAX : take((np + 1) * sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -232,14 +242,33 @@ hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
         if (e != hipSuccess) return e;
         return lion::launch_counter_add(s->d, L, st);
     }
+    const bool rigid = s->d.nbodies > 0;
+    if (rigid) {
+        // force and torque at the starting positions, then the bodies' first half-step
+        e = lion::launch_rigid_wrench(s->d, false, st);
+        if (e != hipSuccess) return e;
+    }
     e = lion::launch_drift(s->d, st);
     if (e != hipSuccess) return e;
+    if (rigid) {
+        e = lion::launch_rigid_drift(s->d, st);
+        if (e == hipSuccess) e = lion::launch_rigid_place(s->d, s->precision, st);
+        if (e != hipSuccess) return e;
+    }
     for (int64_t k = 0; k < L; ++k) {
         e = lion::launch_pair(s->d, s->precision, s->ls, true, st);
         if (e != hipSuccess) return e;
         const int mode = (k + 1 < L) ? lion::kModeEndDrift : lion::kModeEnd;
         e = lion::launch_update(s->d, s->precision, s->ls, mode, true, st);
         if (e != hipSuccess) return e;
+        if (rigid) {
+            e = lion::launch_rigid_wrench(s->d, true, st);
+            if (e == hipSuccess && k + 1 < L) {
+                e = lion::launch_rigid_drift(s->d, st);
+                if (e == hipSuccess) e = lion::launch_rigid_place(s->d, s->precision, st);
+            }
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -348,6 +377,17 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     d.species = (int32_t*)(base + L.species);
     d.vacc = (double*)(base + L.vacc);
     d.vavg = (double*)(base + L.vavg);
+    d.nbodies = 0;  // set by lion_set_rigid_bodies
+    d.rigid = nullptr;
+    d.rb = nullptr;
+    d.dbody = nullptr;
+    d.rmembers = nullptr;
+    d.rstart = nullptr;
+    s->rigid_off[0] = L.rigid;
+    s->rigid_off[1] = L.rb;
+    s->rigid_off[2] = L.dbody;
+    s->rigid_off[3] = L.rmembers;
+    s->rigid_off[4] = L.rstart;
     d.body_code = nullptr;  // set by lion_set_bodies
     d.body_gmin = nullptr;
     d.body_gmax = nullptr;
@@ -410,6 +450,71 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
 }
 
 int check_handle(const lion_sim* s) { return s ? LION_OK : LION_ERR_ARG; }
+
+void rigid_off(lion_sim* s) {
+    s->rigid_on = false;
+    s->rigid_ids.clear();
+    s->d.nbodies = 0;
+    s->d.rigid = nullptr;
+    s->d.rb = nullptr;
+    s->d.dbody = nullptr;
+    s->d.rmembers = nullptr;
+    s->d.rstart = nullptr;
+}
+
+// Body state from the current device state (positions and velocities), into
+// the workspace; member velocities become the rigid motion.
+int rigid_setup(lion_sim* s) {
+    const int64_t n = s->n, np = s->d.n_pad;
+    hipStream_t st = s->stream;
+    std::vector<double4> src(n);
+    std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
+    LION_HIP(s, hipMemcpyAsync(src.data(), s->d.src, n * sizeof(double4), hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(vx.data(), s->d.vx, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(vy.data(), s->d.vy, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(vz.data(), s->d.vz, n * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = src[i].x;
+        y[i] = src[i].y;
+        z[i] = src[i].z;
+    }
+    lion::RigidHost h;
+    if (lion::rigid_build(n, s->mass.data(), x.data(), y.data(), z.data(), vx.data(), vy.data(),
+                          vz.data(), s->rigid_ids.data(), h) != 0)
+        return fail(s, LION_ERR_ARG, "a rigid body has no mass");
+    char* base = s->ws;
+    auto* bodies = (lion::RigidDev*)(base + s->rigid_off[0]);
+    auto* rb = (int32_t*)(base + s->rigid_off[1]);
+    auto* dbody = (double*)(base + s->rigid_off[2]);
+    auto* members = (int32_t*)(base + s->rigid_off[3]);
+    auto* start = (int32_t*)(base + s->rigid_off[4]);
+    std::vector<int32_t> rbp(np, -1);
+    std::copy(h.rb.begin(), h.rb.end(), rbp.begin());
+    std::vector<double> db(3 * np, 0.0);
+    for (int c = 0; c < 3; ++c)
+        std::copy(h.dbody.begin() + c * n, h.dbody.begin() + (c + 1) * n, db.begin() + c * np);
+    if (h.nbodies > 0) {
+        LION_HIP(s, hipMemcpyAsync(bodies, h.bodies.data(), h.nbodies * sizeof(lion::RigidDev),
+                                   hipMemcpyHostToDevice, st));
+        LION_HIP(s, hipMemcpyAsync(members, h.members.data(), h.members.size() * 4,
+                                   hipMemcpyHostToDevice, st));
+    }
+    LION_HIP(s, hipMemcpyAsync(rb, rbp.data(), np * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(dbody, db.data(), 3 * np * 8, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(start, h.start.data(), h.start.size() * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(s->d.vx, h.vx.data(), n * 8, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(s->d.vy, h.vy.data(), n * 8, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(s->d.vz, h.vz.data(), n * 8, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    s->d.nbodies = h.nbodies;
+    s->d.rigid = bodies;
+    s->d.rb = rb;
+    s->d.dbody = dbody;
+    s->d.rmembers = members;
+    s->d.rstart = start;
+    return LION_OK;
+}
 
 }  // namespace
 
@@ -474,6 +579,7 @@ int lion_set_state(lion_sim* s, const double* x, const double* y, const double* 
     if (rc) return rc;
     LION_HIP(s, hipStreamSynchronize(st));
     s->state_set = true;
+    if (s->rigid_on) return rigid_setup(s);
     return LION_OK;
 }
 
@@ -515,6 +621,7 @@ int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
     LION_HIP(s, hipSetDevice(s->device));
     (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);  // captured launches carry the mask pointers
+    rigid_off(s);
     if (!any) {
         s->has_bodies = false;
         s->d.body_code = s->d.body_gmin = s->d.body_gmax = nullptr;
@@ -544,6 +651,43 @@ int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
     s->has_bodies = true;
     default_shape(s);
     return s->state_set ? refresh_accel(s) : LION_OK;
+}
+
+int lion_set_rigid_bodies(lion_sim* s, const int32_t* body_id) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (s->batched) return fail(s, LION_ERR_UNSUPPORTED, "rigid bodies are for single traps");
+    if (body_id && !s->state_set) return fail(s, LION_ERR_STATE, "set the state before the bodies");
+    int rc = lion_set_bodies(s, body_id);  // exclusion mask; turns rigid integration off
+    if (rc) return rc;
+    if (!s->has_bodies) return LION_OK;
+    s->rigid_ids.assign(body_id, body_id + s->n);
+    s->rigid_on = true;
+    rc = rigid_setup(s);
+    if (rc) {
+        rigid_off(s);
+        return rc;
+    }
+    return LION_OK;
+}
+
+int lion_get_rigid_state(lion_sim* s, int32_t* nbodies, double* com, double* com_velocity,
+                         double* angular_momentum, double* quaternion) {
+    if (check_handle(s) || !nbodies) return fail(s, LION_ERR_ARG, "null output pointer");
+    *nbodies = s->d.nbodies;
+    if (s->d.nbodies == 0) return LION_OK;
+    std::vector<lion::RigidDev> b(s->d.nbodies);
+    LION_HIP(s, hipSetDevice(s->device));
+    LION_HIP(s, hipMemcpyAsync(b.data(), s->d.rigid, b.size() * sizeof(lion::RigidDev),
+                               hipMemcpyDeviceToHost, s->stream));
+    LION_HIP(s, hipStreamSynchronize(s->stream));
+    for (size_t k = 0; k < b.size(); ++k)
+        for (int c = 0; c < 4; ++c) {
+            if (c < 3 && com) com[3 * k + c] = b[k].R[c];
+            if (c < 3 && com_velocity) com_velocity[3 * k + c] = b[k].V[c];
+            if (c < 3 && angular_momentum) angular_momentum[3 * k + c] = b[k].L[c];
+            if (quaternion) quaternion[4 * k + c] = b[k].q[c];
+        }
+    return LION_OK;
 }
 
 int lion_set_species(lion_sim* s, const int32_t* species) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace lion {
 
 // CODATA 2018 / SI 2019.
@@ -75,6 +77,38 @@ struct CoolDev {
     int64_t avg_origin;
 };
 
+// Rigid body: a group of ions that keeps its shape.  Member i sits at
+// R + A(q) d_i (d_i fixed in the body frame) and moves with V + w x A(q) d_i.
+struct RigidDev {
+    double M;         // mass (kg)
+    double inv_i[3];  // inverse principal moments (0 for a vanishing moment)
+    double q[4];      // orientation quaternion (w, x, y, z), body frame -> space
+    double R[3];      // centre of mass
+    double V[3];      // COM velocity
+    double L[3];      // angular momentum about the COM (space frame)
+    double F[3];      // total force on the members at the current positions
+    double T[3];      // torque about the COM at the current positions
+    double w[3];      // angular velocity (space frame)
+    double pad;
+};
+
+// Body state built on the host from ion positions and velocities.
+struct RigidHost {
+    int32_t nbodies = 0;
+    std::vector<RigidDev> bodies;   // [nbodies]
+    std::vector<int32_t> rb;        // [n] dense body index per ion, -1 for free ions
+    std::vector<int32_t> members;   // ion indices grouped by body, ascending within a body
+    std::vector<int32_t> start;     // [nbodies + 1] offsets into members
+    std::vector<double> dbody;      // [3][n] body-frame offsets (0 for free ions)
+    std::vector<double> vx, vy, vz; // [n] velocities with members set to the rigid motion
+};
+
+// Builds the body state of the groups body[i] >= 0 (lion_rigid_host.cpp).
+// Returns 0, or -1 when a body has a non-positive total mass.
+int rigid_build(int64_t n, const double* mass, const double* x, const double* y,
+                const double* z, const double* vx, const double* vy, const double* vz,
+                const int32_t* body, RigidHost& out);
+
 // One ion of the FP32 pair stream: high and low float parts of the scaled
 // position and the negated charge in units of e.
 struct MixedSrc {
@@ -115,6 +149,13 @@ struct DevState {
     int32_t* species; // [n_pad] species label per ion (default 0)
     double* vacc;     // [3][n_pad] velocity sums of the open averaging window
     double* vavg;     // [3][n_pad] average of the last completed window
+    // rigid-body integration (NULL / 0 when off)
+    int32_t nbodies;
+    RigidDev* rigid;     // [nbodies]
+    int32_t* rb;         // [n_pad] dense body index per ion, -1 for free ions
+    double* dbody;       // [3][n_pad] body-frame offsets of the members
+    int32_t* rmembers;   // [n_pad] member ions grouped by body
+    int32_t* rstart;     // [nbodies + 1]
     // rigid-body exclusion (all NULL when no bodies are set)
     int32_t* body_code;  // [n_pad] body id >= 0, or -1 - i for a free ion i
     int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions
@@ -147,6 +188,9 @@ hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_t
                         const LaunchShape& ls, int nsteps, int mode_first, hipStream_t st);
 hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int max_trap,
                               const LaunchShape& ls, hipStream_t st);
+hipError_t launch_rigid_wrench(const DevState& s, bool end_kick, hipStream_t st);
+hipError_t launch_rigid_drift(const DevState& s, hipStream_t st);
+hipError_t launch_rigid_place(const DevState& s, int precision, hipStream_t st);
 hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
 hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
 hipError_t launch_check_finite(const DevState& s, hipStream_t st);

@@ -314,9 +314,11 @@ __global__ __launch_bounds__(256) void k_drift(double4* __restrict__ src,
                                                const int32_t* __restrict__ species,
                                                const TrapDev* __restrict__ traps,
                                                const CoolDev* __restrict__ cool,
-                                               const int64_t* __restrict__ counter, int64_t n) {
+                                               const int64_t* __restrict__ counter,
+                                               const int32_t* __restrict__ rb, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (rb && rb[i] >= 0) return;  // rigid-body members move with their body
     const TrapDev T = traps[0];
     const int64_t step = cool->step_base + *counter + 1;
     double4 p = src[i];
@@ -891,7 +893,8 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
                                                 const CoolDev* __restrict__ cool,
                                                 const int64_t* __restrict__ counter,
                                                 double* __restrict__ vacc,
-                                                double* __restrict__ vavg) {
+                                                double* __restrict__ vavg,
+                                                const int32_t* __restrict__ rb) {
     __shared__ double red[kWaves - 1][3][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
@@ -932,6 +935,7 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
     ay[i] = a_y;
     az[i] = a_z;
     if (MODE == kModeAccel) return;
+    if (rb && rb[i] >= 0) return;  // rigid-body members: kicked through their body
     const int64_t step = cool->step_base + *counter;  // the step this epilogue completes
     const int32_t sp = species[i];
     const double mi = mass[i];
@@ -1217,6 +1221,224 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     }
 }
 
+// ------------------------------------------------------------ rigid bodies
+
+__device__ __forceinline__ void quat_rot(const double q[4], double A[9]) {
+#pragma clang fp contract(off)
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    A[0] = 1.0 - 2.0 * (y * y + z * z);
+    A[1] = 2.0 * (x * y - w * z);
+    A[2] = 2.0 * (x * z + w * y);
+    A[3] = 2.0 * (x * y + w * z);
+    A[4] = 1.0 - 2.0 * (x * x + z * z);
+    A[5] = 2.0 * (y * z - w * x);
+    A[6] = 2.0 * (x * z - w * y);
+    A[7] = 2.0 * (y * z + w * x);
+    A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Angular velocity w = A diag(inv_i) A^T L for orientation q.
+__device__ __forceinline__ void rigid_omega(const double q[4], const double inv_i[3],
+                                            const double L[3], double w[3]) {
+#pragma clang fp contract(off)
+    double A[9], p[3];
+    quat_rot(q, A);
+    for (int k = 0; k < 3; ++k) p[k] = (A[k] * L[0] + A[3 + k] * L[1] + A[6 + k] * L[2]) * inv_i[k];
+    for (int r = 0; r < 3; ++r) w[r] = A[3 * r] * p[0] + A[3 * r + 1] * p[1] + A[3 * r + 2] * p[2];
+}
+
+// Normalised Euler step q + s (0, w) q of dq/dt = (1/2) (0, w) q.
+__device__ __forceinline__ void quat_euler_step(const double q[4], const double w[3], double s,
+                                                double out[4]) {
+#pragma clang fp contract(off)
+    const double dw = -(w[0] * q[1] + w[1] * q[2] + w[2] * q[3]);
+    const double dx = w[0] * q[0] + (w[1] * q[3] - w[2] * q[2]);
+    const double dy = w[1] * q[0] + (w[2] * q[1] - w[0] * q[3]);
+    const double dz = w[2] * q[0] + (w[0] * q[2] - w[1] * q[1]);
+    const double r0 = q[0] + s * dw, r1 = q[1] + s * dx, r2 = q[2] + s * dy, r3 = q[3] + s * dz;
+    const double nrm = sqrt(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+    out[0] = r0 / nrm;
+    out[1] = r1 / nrm;
+    out[2] = r2 / nrm;
+    out[3] = r3 / nrm;
+}
+
+// Orientation over dt with L fixed: Richardson extrapolation of one Euler
+// step of dt and two of dt/2 (w re-evaluated at the midpoint orientation).
+__device__ __forceinline__ void rigid_rotate(double q[4], const double L[3],
+                                             const double inv_i[3], double dt) {
+#pragma clang fp contract(off)
+    double w0[3], w1[3], qf[4], qh[4], qh2[4];
+    rigid_omega(q, inv_i, L, w0);
+    quat_euler_step(q, w0, 0.5 * dt, qf);
+    quat_euler_step(q, w0, 0.25 * dt, qh);
+    rigid_omega(qh, inv_i, L, w1);
+    quat_euler_step(qh, w1, 0.25 * dt, qh2);
+    double r[4];
+    for (int k = 0; k < 4; ++k) r[k] = 2.0 * qh2[k] - qf[k];
+    const double nrm = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    for (int k = 0; k < 4; ++k) q[k] = r[k] / nrm;
+}
+
+// Force and torque on each body from its members' accelerations (one
+// workgroup per body, members strided over the threads, tree reduction in a
+// fixed order).  With END, also the end of the step for the body: half kick,
+// damping half-step, angular velocity, and the members' velocities (with
+// their time averages).
+template <bool END>
+__global__ __launch_bounds__(256) void k_rigid_wrench(RigidDev* __restrict__ bodies,
+                                                      const int32_t* __restrict__ rstart,
+                                                      const int32_t* __restrict__ rmembers,
+                                                      const double* __restrict__ dbody,
+                                                      const double* __restrict__ ax,
+                                                      const double* __restrict__ ay,
+                                                      const double* __restrict__ az,
+                                                      const double* __restrict__ mass,
+                                                      double* __restrict__ vx,
+                                                      double* __restrict__ vy,
+                                                      double* __restrict__ vz,
+                                                      const TrapDev* __restrict__ traps,
+                                                      const CoolDev* __restrict__ cool,
+                                                      const int64_t* __restrict__ counter,
+                                                      double* __restrict__ vacc,
+                                                      double* __restrict__ vavg, int64_t n_pad) {
+#pragma clang fp contract(off)
+    __shared__ double red[6][256];
+    __shared__ double shared_state[9];  // V, w, (pad)
+    const int b = blockIdx.x, tid = threadIdx.x;
+    RigidDev* B = bodies + b;
+    double q[4] = {B->q[0], B->q[1], B->q[2], B->q[3]};
+    double A[9];
+    quat_rot(q, A);
+    const int m0 = rstart[b], m1 = rstart[b + 1];
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    for (int m = m0 + tid; m < m1; m += 256) {
+        const int i = rmembers[m];
+        const double d0 = dbody[i], d1 = dbody[n_pad + i], d2 = dbody[2 * n_pad + i];
+        const double o0 = A[0] * d0 + A[1] * d1 + A[2] * d2;
+        const double o1 = A[3] * d0 + A[4] * d1 + A[5] * d2;
+        const double o2 = A[6] * d0 + A[7] * d1 + A[8] * d2;
+        const double fx = mass[i] * ax[i], fy = mass[i] * ay[i], fz = mass[i] * az[i];
+        f[0] += fx;
+        f[1] += fy;
+        f[2] += fz;
+        f[3] += o1 * fz - o2 * fy;
+        f[4] += o2 * fx - o0 * fz;
+        f[5] += o0 * fy - o1 * fx;
+    }
+    for (int c = 0; c < 6; ++c) red[c][tid] = f[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int c = 0; c < 6; ++c) red[c][tid] += red[c][tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double F[3] = {red[0][0], red[1][0], red[2][0]}, Tq[3] = {red[3][0], red[4][0], red[5][0]};
+        for (int c = 0; c < 3; ++c) {
+            B->F[c] = F[c];
+            B->T[c] = Tq[c];
+        }
+        if (END) {
+            const TrapDev T = traps[0];
+            double V[3], L[3], w[3];
+            for (int c = 0; c < 3; ++c) {
+                V[c] = B->V[c] + T.h * (F[c] / B->M);
+                L[c] = B->L[c] + T.h * Tq[c];
+                V[c] = T.f * V[c];
+                L[c] = T.f * L[c];
+            }
+            const double inv_i[3] = {B->inv_i[0], B->inv_i[1], B->inv_i[2]};
+            rigid_omega(q, inv_i, L, w);
+            for (int c = 0; c < 3; ++c) {
+                B->V[c] = V[c];
+                B->L[c] = L[c];
+                B->w[c] = w[c];
+                shared_state[c] = V[c];
+                shared_state[3 + c] = w[c];
+            }
+        }
+    }
+    if (!END) return;
+    __syncthreads();
+    const double V0 = shared_state[0], V1 = shared_state[1], V2 = shared_state[2];
+    const double w0 = shared_state[3], w1 = shared_state[4], w2 = shared_state[5];
+    const int64_t step = cool->step_base + *counter;
+    for (int m = m0 + tid; m < m1; m += 256) {
+        const int i = rmembers[m];
+        const double d0 = dbody[i], d1 = dbody[n_pad + i], d2 = dbody[2 * n_pad + i];
+        const double o0 = A[0] * d0 + A[1] * d1 + A[2] * d2;
+        const double o1 = A[3] * d0 + A[4] * d1 + A[5] * d2;
+        const double o2 = A[6] * d0 + A[7] * d1 + A[8] * d2;
+        const double u = V0 + (w1 * o2 - w2 * o1);
+        const double v = V1 + (w2 * o0 - w0 * o2);
+        const double w = V2 + (w0 * o1 - w1 * o0);
+        vx[i] = u;
+        vy[i] = v;
+        vz[i] = w;
+        time_average(cool, i, n_pad, step, vacc, vavg, u, v, w);
+    }
+}
+
+// First half of a step for each body: damping half-step, half kick, COM drift
+// and the orientation update (one thread per body).
+__global__ __launch_bounds__(64) void k_rigid_drift(RigidDev* __restrict__ bodies, int nbodies,
+                                                    const TrapDev* __restrict__ traps) {
+#pragma clang fp contract(off)
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbodies) return;
+    const TrapDev T = traps[0];
+    RigidDev* B = bodies + b;
+    double V[3], L[3], R[3], q[4] = {B->q[0], B->q[1], B->q[2], B->q[3]};
+    const double inv_i[3] = {B->inv_i[0], B->inv_i[1], B->inv_i[2]};
+    for (int c = 0; c < 3; ++c) {
+        V[c] = T.f * B->V[c];
+        L[c] = T.f * B->L[c];
+        V[c] = V[c] + T.h * (B->F[c] / B->M);
+        L[c] = L[c] + T.h * B->T[c];
+        R[c] = B->R[c] + T.dt * V[c];
+    }
+    rigid_rotate(q, L, inv_i, T.dt);
+    double w[3];
+    rigid_omega(q, inv_i, L, w);
+    for (int c = 0; c < 3; ++c) {
+        B->V[c] = V[c];
+        B->L[c] = L[c];
+        B->R[c] = R[c];
+        B->w[c] = w[c];
+    }
+    for (int k = 0; k < 4; ++k) B->q[k] = q[k];
+}
+
+// Members placed at R + A(q) d (positions and both source streams).
+__global__ __launch_bounds__(256) void k_rigid_place(const RigidDev* __restrict__ bodies,
+                                                     const int32_t* __restrict__ rb,
+                                                     const double* __restrict__ dbody,
+                                                     double4* __restrict__ src,
+                                                     MixedSrc* __restrict__ srcm,
+                                                     const double* __restrict__ qe, int64_t n,
+                                                     int64_t n_pad) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = rb[i];
+    if (b < 0) return;
+    const RigidDev* B = bodies + b;
+    const double q[4] = {B->q[0], B->q[1], B->q[2], B->q[3]};
+    double A[9];
+    quat_rot(q, A);
+    const double d0 = dbody[i], d1 = dbody[n_pad + i], d2 = dbody[2 * n_pad + i];
+    const double x = B->R[0] + (A[0] * d0 + A[1] * d1 + A[2] * d2);
+    const double y = B->R[1] + (A[3] * d0 + A[4] * d1 + A[5] * d2);
+    const double z = B->R[2] + (A[6] * d0 + A[7] * d1 + A[8] * d2);
+    double4 p = src[i];
+    p.x = x;
+    p.y = y;
+    p.z = z;
+    src[i] = p;
+    if (srcm) srcm[i] = make_src(x, y, z, qe[i]);
+}
+
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 inline int n64_of(int64_t n) { return (int)((n + 63) & ~int64_t(63)); }
@@ -1286,7 +1508,7 @@ hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps,
 hipError_t launch_drift(const DevState& s, hipStream_t st) {
     k_drift<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                   s.az, s.qe, s.mass, s.species, s.traps, s.cool,
-                                                  s.counter, s.n);
+                                                  s.counter, s.rb, s.n);
     return hipGetLastError();
 }
 
@@ -1341,21 +1563,50 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
             k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                     s.az, s.qm, s.qe, s.mass, s.species, s.part,
                                                     ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                    s.cool, ctr, s.vacc, s.vavg);
+                                                    s.cool, ctr, s.vacc, s.vavg, s.rb);
             break;
         case kModeEnd:
             k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                   s.az, s.qm, s.qe, s.mass, s.species, s.part,
                                                   ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                  s.cool, ctr, s.vacc, s.vavg);
+                                                  s.cool, ctr, s.vacc, s.vavg, s.rb);
             break;
         default:
             k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
                                                        s.ay, s.az, s.qm, s.qe, s.mass, s.species,
                                                        s.part, ls.j_split, s.n, s.n_pad, scale,
-                                                       s.traps, s.cool, ctr, s.vacc, s.vavg);
+                                                       s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_rigid_wrench(const DevState& s, bool end_kick, hipStream_t st) {
+    if (s.nbodies <= 0) return hipSuccess;
+    if (end_kick)
+        k_rigid_wrench<true><<<s.nbodies, 256, 0, st>>>(s.rigid, s.rstart, s.rmembers, s.dbody,
+                                                        s.ax, s.ay, s.az, s.mass, s.vx, s.vy,
+                                                        s.vz, s.traps, s.cool, s.counter, s.vacc,
+                                                        s.vavg, s.n_pad);
+    else
+        k_rigid_wrench<false><<<s.nbodies, 256, 0, st>>>(s.rigid, s.rstart, s.rmembers, s.dbody,
+                                                         s.ax, s.ay, s.az, s.mass, s.vx, s.vy,
+                                                         s.vz, s.traps, s.cool, s.counter,
+                                                         s.vacc, s.vavg, s.n_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_rigid_drift(const DevState& s, hipStream_t st) {
+    if (s.nbodies <= 0) return hipSuccess;
+    k_rigid_drift<<<blocks_for(s.nbodies, 64), 64, 0, st>>>(s.rigid, s.nbodies, s.traps);
+    return hipGetLastError();
+}
+
+hipError_t launch_rigid_place(const DevState& s, int precision, hipStream_t st) {
+    if (s.nbodies <= 0) return hipSuccess;
+    MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
+    k_rigid_place<<<blocks_for(s.n, 256), 256, 0, st>>>(s.rigid, s.rb, s.dbody, s.src, srcm, s.qe,
+                                                        s.n, s.n_pad);
     return hipGetLastError();
 }
 

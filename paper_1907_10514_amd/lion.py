@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.lion_set_damping.argtypes = [vp, i32, d]
     lib.lion_set_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_set_species.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lion_set_rigid_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lion_get_rigid_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), dp, dp, dp, dp]
     lib.lion_set_beam.argtypes = [vp, i32, i32, d, d, d, d]
     lib.lion_set_bath.argtypes = [vp, i32, i32, d, d, ctypes.c_uint64]
     lib.lion_set_step_index.argtypes = [vp, i64]
@@ -97,7 +99,8 @@ def load(path: str = LIB_PATH):
     lib.lion_constants.argtypes = [dp, dp, dp]
     lib.lion_constants.restype = None
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
-                 "lion_set_damping", "lion_set_bodies", "lion_set_species", "lion_set_beam",
+                 "lion_set_damping", "lion_set_bodies", "lion_set_rigid_bodies",
+                 "lion_get_rigid_state", "lion_set_species", "lion_set_beam",
                  "lion_set_bath", "lion_set_step_index", "lion_set_time_average",
                  "lion_get_time_average", "lion_step", "lion_step_batch", "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite",
@@ -169,6 +172,25 @@ def lion_set_bodies(h, body_id):
         return
     b = np.ascontiguousarray(body_id, dtype=np.int32)
     _check(load().lion_set_bodies(h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), h)
+
+
+def lion_set_rigid_bodies(h, body):
+    if body is None:
+        _check(load().lion_set_rigid_bodies(h, None), h)
+        return
+    b = np.ascontiguousarray(body, dtype=np.int32)
+    _check(load().lion_set_rigid_bodies(h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), h)
+
+
+def lion_get_rigid_state(h, max_bodies):
+    nb = ctypes.c_int32(0)
+    m = max(1, int(max_bodies))
+    com, vel, ang, quat = np.empty(3 * m), np.empty(3 * m), np.empty(3 * m), np.empty(4 * m)
+    _check(load().lion_get_rigid_state(h, ctypes.byref(nb), _dp(com), _dp(vel), _dp(ang),
+                                       _dp(quat)), h)
+    k = nb.value
+    return dict(com=com[:3 * k].reshape(k, 3), com_velocity=vel[:3 * k].reshape(k, 3),
+                angular_momentum=ang[:3 * k].reshape(k, 3), quaternion=quat[:4 * k].reshape(k, 4))
 
 
 def lion_set_species(h, species):
@@ -354,6 +376,14 @@ class Simulation:
 
     def set_bodies(self, body_id):
         lion_set_bodies(self.h, body_id)
+
+    def set_rigid_bodies(self, body):
+        """Integrate ions with equal body id >= 0 as rigid bodies (None: off)."""
+        lion_set_rigid_bodies(self.h, body)
+
+    def rigid_state(self):
+        """dict of com, com_velocity, angular_momentum [nb, 3] and quaternion [nb, 4]."""
+        return lion_get_rigid_state(self.h, self.n)
 
     def set_species(self, species):
         lion_set_species(self.h, species)
