@@ -59,22 +59,27 @@ class _Bath(ctypes.Structure):
 
 class _Trap(ctypes.Structure):
     _fields_ = [("V0", ctypes.c_double), ("Omega", ctypes.c_double), ("U0", ctypes.c_double),
-                ("R0", ctypes.c_double), ("Z0", ctypes.c_double), ("kappa", ctypes.c_double)]
+                ("R0", ctypes.c_double), ("Z0", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("pseudo", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
 class Trap:
     """Linear Paul trap of eq. (field): rf amplitude V0 (V) at angular frequency
-    Omega (rad/s), end-cap voltage U0 (V), lengths R0, Z0 (m), geometry factor kappa."""
+    Omega (rad/s), end-cap voltage U0 (V), lengths R0, Z0 (m), geometry factor kappa.
+    pseudo=True replaces the rf by its pseudopotential (eq. (pseudopot)): a static
+    radial field -(Q/M) (V0/R0^2)^2 / (2 Omega^2) (x, y, 0) on each ion."""
     V0: float = 0.0
     Omega: float = 1.0
     U0: float = 0.0
     R0: float = 1.0
     Z0: float = 1.0
     kappa: float = 0.0
+    pseudo: bool = False
 
     def _c(self) -> _Trap:
-        return _Trap(self.V0, self.Omega, self.U0, self.R0, self.Z0, self.kappa)
+        return _Trap(self.V0, self.Omega, self.U0, self.R0, self.Z0, self.kappa,
+                     1 if self.pseudo else 0, 0)
 
 
 _lib = None
@@ -118,6 +123,10 @@ def bind(path: str):
                                        ctypes.POINTER(_Bath), i64, i64, ctypes.c_double,
                                        ctypes.c_double, i64, dp]
     lib.oracle_step_cooled.restype = i64
+    lib.oracle_minimize.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, i64, dp]
+    lib.oracle_minimize.restype = i64
     ip = ctypes.POINTER(ctypes.c_int32)
     lib.oracle_step_rigid.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip, dp,
                                       ctypes.c_int32, dp, dp, dp, dp, dp, dp, tp, ctypes.c_double,
@@ -413,6 +422,26 @@ def step_rigid(state: dict, charge, mass, body, trap: Trap, gamma: float, t_star
                               int(nsteps), ctypes.byref(t_end))
     s.update(ax=ax, ay=ay, az=az, t=t_end.value)
     return s, rg
+
+
+def minimize(state: dict, charge, mass, trap: Trap, dt: float, dmax: float, ftol: float,
+             max_iter: int, t: float = 0.0) -> dict:
+    """Energy minimisation (see lion_oracle.c): damped dynamics keeping only the
+    velocity component along the force, a per-ion step cap dmax (m), until
+    max_i |F_i| <= ftol (N) or max_iter iterations.  Returns the state with the
+    final accelerations, 'iterations' and 'fmax'."""
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    q, m = _f64(charge), _f64(mass)
+    n = s["x"].size
+    ax, ay, az = np.empty(n), np.empty(n), np.empty(n)
+    fmax = ctypes.c_double(0.0)
+    tr = trap._c()
+    it = _load().oracle_minimize(n, _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]), _d(s["vy"]),
+                                 _d(s["vz"]), _d(ax), _d(ay), _d(az), _d(q), _d(m),
+                                 ctypes.byref(tr), float(t), float(dt), float(dmax), float(ftol),
+                                 int(max_iter), ctypes.byref(fmax))
+    s.update(ax=ax, ay=ay, az=az, iterations=int(it), fmax=fmax.value)
+    return s
 
 
 def time_average(samples, first_step: int, origin: int, window: int):

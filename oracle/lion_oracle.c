@@ -47,6 +47,8 @@ typedef struct {
     double R0;     /* radial length scale (m) */
     double Z0;     /* axial length scale (m) */
     double kappa;  /* geometric factor */
+    int32_t pseudo; /* 1: pseudopotential approximation of the rf (eq. (pseudopot)) */
+    int32_t pad;
 } oracle_trap;
 
 double oracle_coulomb_constant(void) { return 1.0 / (4.0 * OR_PI * OR_EPS0); }
@@ -85,14 +87,43 @@ static void nsum_add(nsum *a, double t) {
 static double nsum_get(const nsum *a) { return a->s + a->c; }
 
 /* External field of eq. (field) at one point, dc sign read as confining. */
-static void trap_field(const oracle_trap *tp, double t, double x, double y, double z,
+/* Strength A_rf^2 / (2 Omega^2) of the pseudopotential's radial term (0 for
+ * the full rf field).  With eq. (Mathieuaq) in eq. (pseudopot),
+ * omega_x^2 = (Omega^2/4)(a_x + q_x^2/2) = (Q/M)^2 A_rf^2/(2 Omega^2) - (Q/M) A_dc and
+ * omega_z^2 = 2 (Q/M) A_dc: the dc field stays as it is and the rf becomes the
+ * static radial field -(Q/M) A_rf^2/(2 Omega^2) (x, y, 0), whose strength
+ * depends on the ion's own Q/M. */
+static double pseudo_strength(const oracle_trap *tp) {
+    if (!tp->pseudo) return 0.0;
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    return (a_rf * a_rf) / (2.0 * tp->Omega * tp->Omega);
+}
+
+/* External field E_ext on an ion of charge-to-mass ratio qm at (x, y, z). */
+static void trap_field(const oracle_trap *tp, double t, double qm, double x, double y, double z,
                        double *ex, double *ey, double *ez) {
     double a_rf = tp->V0 / (tp->R0 * tp->R0);
     double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    if (tp->pseudo) {
+        double k = qm * pseudo_strength(tp);
+        *ex = a_dc * x - k * x;
+        *ey = a_dc * y - k * y;
+        *ez = -2.0 * a_dc * z;
+        return;
+    }
     double c = cos(tp->Omega * t);
     *ex = a_rf * c * x + a_dc * x;
     *ey = -a_rf * c * y + a_dc * y;
     *ez = -2.0 * a_dc * z;
+}
+
+/* Magnitude of the radial (rf or pseudopotential) field on an ion, for the
+ * force scale. */
+static double radial_scale(const oracle_trap *tp, double t, double qm, double x, double y) {
+    double rho = sqrt(x * x + y * y);
+    if (tp->pseudo) return fabs(qm * pseudo_strength(tp)) * rho;
+    double a_rf = tp->V0 / (tp->R0 * tp->R0);
+    return fabs(a_rf * cos(tp->Omega * t)) * rho;
 }
 
 /* Coulomb field E_c,i (V/m) on every ion of one cloud.  Returns the number of
@@ -131,8 +162,8 @@ int64_t oracle_accel(int64_t n, const double *x, const double *y, const double *
     int64_t coincident = oracle_coulomb_field(n, x, y, z, charge, ax, ay, az);
     for (int64_t i = 0; i < n; ++i) {
         double ex, ey, ez;
-        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
         double qm = charge[i] / mass[i];
+        trap_field(tp, t, qm, x[i], y[i], z[i], &ex, &ey, &ez);
         ax[i] = qm * (ax[i] + ex);
         ay[i] = qm * (ay[i] + ey);
         az[i] = qm * (az[i] + ez);
@@ -147,9 +178,7 @@ void oracle_accel_at(int64_t n, const double *x, const double *y, const double *
                      int64_t m, const int64_t *idx, double *ax, double *ay, double *az,
                      double *scale) {
     const double ke = oracle_coulomb_constant();
-    double a_rf = tp->V0 / (tp->R0 * tp->R0);
     double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
-    double c = cos(tp->Omega * t);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < m; ++k) {
         int64_t i = idx[k];
@@ -166,12 +195,12 @@ void oracle_accel_at(int64_t n, const double *x, const double *y, const double *
             nsum_add(&sm, fabs(charge[j]) / r2);
         }
         double ex, ey, ez;
-        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
         double qm = charge[i] / mass[i];
+        trap_field(tp, t, qm, x[i], y[i], z[i], &ex, &ey, &ez);
         ax[k] = qm * (ke * nsum_get(&sx) + ex);
         ay[k] = qm * (ke * nsum_get(&sy) + ey);
         az[k] = qm * (ke * nsum_get(&sz) + ez);
-        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double erf = radial_scale(tp, t, charge[i] / mass[i], x[i], y[i]);
         double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
         scale[k] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&sm) + erf + edc);
     }
@@ -187,9 +216,7 @@ int64_t oracle_accel_bodies(int64_t n, const double *x, const double *y, const d
                             const oracle_trap *tp, double t, double *ax, double *ay, double *az,
                             double *scale) {
     const double ke = oracle_coulomb_constant();
-    double a_rf = tp->V0 / (tp->R0 * tp->R0);
     double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
-    double c = cos(tp->Omega * t);
     int64_t coincident = 0;
 #pragma omp parallel for schedule(static) reduction(+ : coincident) if (n >= 256)
     for (int64_t i = 0; i < n; ++i) {
@@ -210,12 +237,12 @@ int64_t oracle_accel_bodies(int64_t n, const double *x, const double *y, const d
             nsum_add(&sm, fabs(charge[j]) / r2);
         }
         double ex, ey, ez;
-        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
         double qm = charge[i] / mass[i];
+        trap_field(tp, t, qm, x[i], y[i], z[i], &ex, &ey, &ez);
         ax[i] = qm * (ke * nsum_get(&sx) + ex);
         ay[i] = qm * (ke * nsum_get(&sy) + ey);
         az[i] = qm * (ke * nsum_get(&sz) + ez);
-        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double erf = radial_scale(tp, t, charge[i] / mass[i], x[i], y[i]);
         double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
         scale[i] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&sm) + erf + edc);
     }
@@ -229,9 +256,7 @@ void oracle_accel_bodies_at(int64_t n, const double *x, const double *y, const d
                             const oracle_trap *tp, double t, int64_t m, const int64_t *idx,
                             double *ax, double *ay, double *az, double *scale) {
     const double ke = oracle_coulomb_constant();
-    double a_rf = tp->V0 / (tp->R0 * tp->R0);
     double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
-    double c = cos(tp->Omega * t);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < m; ++k) {
         int64_t i = idx[k];
@@ -249,12 +274,12 @@ void oracle_accel_bodies_at(int64_t n, const double *x, const double *y, const d
             nsum_add(&sm, fabs(charge[j]) / r2);
         }
         double ex, ey, ez;
-        trap_field(tp, t, x[i], y[i], z[i], &ex, &ey, &ez);
         double qm = charge[i] / mass[i];
+        trap_field(tp, t, qm, x[i], y[i], z[i], &ex, &ey, &ez);
         ax[k] = qm * (ke * nsum_get(&sx) + ex);
         ay[k] = qm * (ke * nsum_get(&sy) + ey);
         az[k] = qm * (ke * nsum_get(&sz) + ez);
-        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double erf = radial_scale(tp, t, charge[i] / mass[i], x[i], y[i]);
         double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
         scale[k] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&sm) + erf + edc);
     }
@@ -266,9 +291,7 @@ void oracle_accel_scale(int64_t n, const double *x, const double *y, const doubl
                         const double *charge, const double *mass, const oracle_trap *tp,
                         double t, double *scale) {
     const double ke = oracle_coulomb_constant();
-    double a_rf = tp->V0 / (tp->R0 * tp->R0);
     double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
-    double c = cos(tp->Omega * t);
 #pragma omp parallel for schedule(static) if (n >= 256)
     for (int64_t i = 0; i < n; ++i) {
         nsum s = {0, 0};
@@ -279,7 +302,7 @@ void oracle_accel_scale(int64_t n, const double *x, const double *y, const doubl
             if (r2 == 0.0) continue;
             nsum_add(&s, fabs(charge[j]) / r2);
         }
-        double erf = fabs(a_rf * c) * sqrt(x[i] * x[i] + y[i] * y[i]);
+        double erf = radial_scale(tp, t, charge[i] / mass[i], x[i], y[i]);
         double edc = fabs(a_dc) * sqrt(x[i] * x[i] + y[i] * y[i] + 4.0 * z[i] * z[i]);
         scale[i] = fabs(charge[i]) / mass[i] * (ke * nsum_get(&s) + erf + edc);
     }
@@ -335,6 +358,9 @@ void oracle_energy(int64_t n, const double *x, const double *y, const double *z,
     for (int64_t i = 0; i < n; ++i) {
         nsum_add(&k, 0.5 * mass[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]));
         nsum_add(&d, charge[i] * a_dc * (z[i] * z[i] - 0.5 * (x[i] * x[i] + y[i] * y[i])));
+        if (tp->pseudo) /* potential of the radial pseudopotential field */
+            nsum_add(&d, 0.5 * charge[i] * (charge[i] / mass[i]) * pseudo_strength(tp) *
+                             (x[i] * x[i] + y[i] * y[i]));
         for (int64_t j = i + 1; j < n; ++j) {
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
             double r = sqrt(dx * dx + dy * dy + dz * dz);
@@ -743,4 +769,64 @@ int64_t oracle_step_rigid(int64_t n, double *x, double *y, double *z, double *vx
     free(sc);
     *t_end = t_start + (double)nsteps * dt;
     return coincident;
+}
+
+/* ------------------------------------------------------------ minimisation
+ *
+ * Energy minimisation (section "Minimisation": damped dynamics that extract
+ * energy and cap how far each ion moves in one step; meaningful only in a
+ * time-independent trap, i.e. the pseudopotential trap or no rf).  Each
+ * iteration, with F_i = M_i a_i at the current positions (trap field at the
+ * fixed time t):
+ *   stop if max_i |F_i| <= ftol;
+ *   P = sum_i v_i . F_i;  v <- (P / sum_i F_i . F_i) F  if P > 0, else v <- 0
+ *     (the 3N-velocity keeps only its component along the 3N-force);
+ *   v <- v + dt a;
+ *   for every ion with dt |v_i| > dmax: v_i <- v_i dmax / (dt |v_i|);
+ *   x <- x + dt v;  forces at the new positions.
+ * Velocities start from the values passed in.  Returns the number of
+ * iterations that moved the ions; *fmax gets max_i |F_i| at the final
+ * positions and (ax, ay, az) the final accelerations. */
+int64_t oracle_minimize(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                        double *vz, double *ax, double *ay, double *az, const double *charge,
+                        const double *mass, const oracle_trap *tp, double t, double dt,
+                        double dmax, double ftol, int64_t max_iter, double *fmax) {
+    int64_t it = 0;
+    oracle_accel(n, x, y, z, charge, mass, tp, t, ax, ay, az);
+    for (;;) {
+        double P = 0.0, FF = 0.0, fm = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double fx = mass[i] * ax[i], fy = mass[i] * ay[i], fz = mass[i] * az[i];
+            P += vx[i] * fx + vy[i] * fy + vz[i] * fz;
+            const double f2 = fx * fx + fy * fy + fz * fz;
+            FF += f2;
+            if (sqrt(f2) > fm) fm = sqrt(f2);
+        }
+        *fmax = fm;
+        if (fm <= ftol || it >= max_iter) break;
+        const double coef = (P > 0.0 && FF > 0.0) ? P / FF : 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double u = coef * (mass[i] * ax[i]), v = coef * (mass[i] * ay[i]),
+                   w = coef * (mass[i] * az[i]);
+            u = u + dt * ax[i];
+            v = v + dt * ay[i];
+            w = w + dt * az[i];
+            const double s = dt * sqrt(u * u + v * v + w * w);
+            if (s > dmax) {
+                const double r = dmax / s;
+                u = u * r;
+                v = v * r;
+                w = w * r;
+            }
+            vx[i] = u;
+            vy[i] = v;
+            vz[i] = w;
+            x[i] = x[i] + dt * u;
+            y[i] = y[i] + dt * v;
+            z[i] = z[i] + dt * w;
+        }
+        ++it;
+        oracle_accel(n, x, y, z, charge, mass, tp, t, ax, ay, az);
+    }
+    return it;
 }

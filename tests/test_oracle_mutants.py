@@ -127,6 +127,47 @@ RIGID_PINS = [
 ]
 
 
+PSEUDO_MUTANTS = {
+    "pseudo_strength_without_half": ("return (a_rf * a_rf) / (2.0 * tp->Omega * tp->Omega);",
+                                     "return (a_rf * a_rf) / (tp->Omega * tp->Omega);"),
+    "pseudo_dc_dropped": ("*ex = a_dc * x - k * x;", "*ex = -k * x;"),
+    "pseudo_energy_sign": ("nsum_add(&d, 0.5 * charge[i] * (charge[i] / mass[i])",
+                           "nsum_add(&d, -0.5 * charge[i] * (charge[i] / mass[i])"),
+}
+
+PSEUDO_PINS = [
+    lambda o: pins.test_pseudo_trap_single_ion_is_harmonic(o, 40.0),
+    lambda o: pins.test_pseudo_trap_single_ion_is_harmonic(o, 17.0),
+    lambda o: pins.test_pseudo_energy_gradient_is_minus_force(o),
+]
+
+
+MINIMISER_MUTANTS = {
+    "fmax_from_accelerations": ("if (sqrt(f2) > fm) fm = sqrt(f2);",
+                                "if (sqrt(f2) / mass[i] > fm) fm = sqrt(f2) / mass[i];"),
+    "step_cap_ignored": ("if (s > dmax) {", "if (s > 1e300 * dmax) {"),
+    "velocity_against_force_kept": ("const double coef = (P > 0.0 && FF > 0.0) ? P / FF : 0.0;",
+                                    "const double coef = (FF > 0.0) ? P / FF : 0.0;"),
+}
+
+MINIMISER_PINS = [
+    lambda o: pins.test_minimised_chains_match_newton_roots(o, 3),
+    lambda o: pins.test_minimiser_step_cap_and_projection(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MINIMISER_MUTANTS))
+def test_minimiser_pins_reject_mutant(tmp_path, name, oracle_mod):
+    so = _build_mutant(tmp_path, *MINIMISER_MUTANTS[name])
+    assert _count_failures(so, MINIMISER_PINS) >= 1, f"no pin caught mutant {name}"
+
+
+@pytest.mark.parametrize("name", sorted(PSEUDO_MUTANTS))
+def test_pseudo_pins_reject_mutant(tmp_path, name, oracle_mod):
+    so = _build_mutant(tmp_path, *PSEUDO_MUTANTS[name])
+    assert _count_failures(so, PSEUDO_PINS) >= 1, f"no pin caught mutant {name}"
+
+
 @pytest.mark.parametrize("name", sorted(RIGID_MUTANTS))
 def test_rigid_pins_reject_mutant(tmp_path, name, oracle_mod):
     so = _build_mutant(tmp_path, *RIGID_MUTANTS[name])

@@ -891,3 +891,158 @@ def test_rigid_members_keep_their_distances(oracle_mod):
     d0 = np.linalg.norm(r0[:, None] - r0[None], axis=2)
     d1 = np.linalg.norm(r1[:, None] - r1[None], axis=2)
     assert np.max(np.abs(d1 - d0)) < 1e-12 * np.max(d0)
+
+
+# ------------------------------------------------------------ pseudopotential trap
+
+def _pseudo_trap(oracle, q_x=0.3, a_x=-0.001):
+    V0, U0 = oracle.voltages_for(q_x, a_x, CA, E, li.OMEGA, li.R0, li.Z0, li.KAPPA)
+    return oracle.Trap(V0=V0, Omega=li.OMEGA, U0=U0, R0=li.R0, Z0=li.Z0, kappa=li.KAPPA,
+                       pseudo=True)
+
+
+@pytest.mark.parametrize("mass_u", [40.0, 17.0])
+def test_pseudo_trap_single_ion_is_harmonic(oracle_mod, mass_u):
+    """In the pseudopotential trap ("Electric fields and confinement":
+    linearPseudoPT) one ion is a harmonic oscillator on each axis with the
+    frequency of eq. (pseudopot), using that ion's own Mathieu coefficients
+    (eq. (Mathieuaq) scales with Q/M).  The oracle's run equals the exact
+    velocity-Verlet transfer matrix of that oscillator."""
+    tr = _pseudo_trap(oracle_mod)
+    m = mass_u * li.AMU
+    q_x, a_x = oracle_mod.mathieu_coefficients(tr.V0, tr.U0, m, E, tr.Omega, tr.R0, tr.Z0,
+                                               tr.kappa)
+    w_r = oracle_mod.pseudopotential_frequency(q_x, a_x, tr.Omega)
+    w_z = oracle_mod.pseudopotential_frequency(0.0, -2 * a_x, tr.Omega)
+    dt, n = li.DT, 3000
+    st = {"x": np.array([3e-6]), "y": np.array([-2e-6]), "z": np.array([5e-6]),
+          "vx": np.array([0.4]), "vy": np.array([0.7]), "vz": np.array([-0.3])}
+    out = oracle_mod.step(st, [E], [m], tr, 0.0, 0.0, dt, n)
+    for p, v, w in (("x", "vx", w_r), ("y", "vy", w_r), ("z", "vz", w_z)):
+        c = 1 - (w * dt) ** 2 / 2
+        T = np.array([[c, dt], [-w * w * dt * (1 - (w * dt) ** 2 / 4), c]])
+        ref = np.linalg.matrix_power(T, n) @ np.array([st[p][0], st[v][0]])
+        amp = math.hypot(st[p][0], st[v][0] / w)
+        assert abs(out[p][0] - ref[0]) < 1e-11 * amp, p
+        assert abs(out[v][0] - ref[1]) < 1e-11 * amp * w, v
+
+
+def test_pseudo_energy_gradient_is_minus_force(oracle_mod):
+    """The pseudopotential trap's static energy (dc + radial pseudopotential)
+    plus the Coulomb energy is the potential of the oracle's force, for two
+    species."""
+    w = li.random_cloud(6, seed=14, light_fraction=0.5)
+    tr = _pseudo_trap(oracle_mod)
+    st = w.state()
+    ax, ay, az = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    h = 1e-10
+    for i in range(6):
+        for p, a in (("x", ax), ("y", ay), ("z", az)):
+            sp, sm = dict(st), dict(st)
+            sp[p] = st[p].copy()
+            sm[p] = st[p].copy()
+            sp[p][i] += h
+            sm[p][i] -= h
+            ep = sum(oracle_mod.energy(sp, w.charge, w.mass, tr)[1:])
+            em = sum(oracle_mod.energy(sm, w.charge, w.mass, tr)[1:])
+            force = -(ep - em) / (2 * h)
+            assert force == pytest.approx(w.mass[i] * a[i], rel=1e-5, abs=0)
+
+
+def test_pseudo_trap_is_time_independent(oracle_mod):
+    """The pseudopotential field does not depend on t."""
+    w = li.random_cloud(10, seed=15, light_fraction=0.3)
+    tr = _pseudo_trap(oracle_mod)
+    a0 = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    a1 = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 3.3e-8)
+    for c0, c1 in zip(a0, a1):
+        assert np.array_equal(c0, c1)
+
+
+# ------------------------------------------------------------------ minimisation
+
+def _force_unit(tr):
+    """M omega_z^2 l: the natural force scale of a chain (N)."""
+    wz2 = 2 * E * tr.kappa * tr.U0 / (CA * tr.Z0 ** 2)
+    return CA * wz2 * _length_scale(tr)
+
+
+def _min_start(n, seed, spread=1.0):
+    """Ions roughly along the axis with off-axis scatter, at rest."""
+    rng = np.random.default_rng(seed)
+    st = {k: np.zeros(n) for k in ("vx", "vy", "vz")}
+    st["z"] = np.linspace(-1.0, 1.0, n) * 12e-6 * max(n - 1, 1) ** 0.7 + rng.normal(0, 1e-6, n)
+    st["x"] = rng.normal(0, spread * 1e-6, n)
+    st["y"] = rng.normal(0, spread * 1e-6, n)
+    return st
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 10])
+def test_minimised_chains_match_newton_roots(oracle_mod, n):
+    """Section 'Equilibrium separation': minimising eq. (fullPotential) in the
+    pseudopotential trap from a scattered start gives the linear chain; its
+    positions equal the independent Newton roots of the axial force balance,
+    and for 3 <= N <= 10 the minimum spacing is within 3 % of the printed
+    z_min fit (golden file)."""
+    tr = _pseudo_trap(oracle_mod)
+    l, fu = _length_scale(tr), _force_unit(tr)
+    out = oracle_mod.minimize(_min_start(n, seed=n), np.full(n, E), np.full(n, CA), tr,
+                              dt=2e-8, dmax=1e-6, ftol=1e-10 * fu, max_iter=200000)
+    assert out["fmax"] <= 1e-10 * fu
+    assert np.max(np.abs(out["x"])) < 1e-9 * l and np.max(np.abs(out["y"])) < 1e-9 * l
+    u = np.sort(out["z"]) / l
+    assert np.max(np.abs(u - analytic.chain_equilibrium(n))) < 1e-8
+    if n >= 3:
+        coef, expo, tol, _, _ = map(float, _golden("zmin_fit.txt")[0])
+        fit = coef / n ** expo
+        assert abs(np.min(np.diff(u)) - fit) / fit < tol
+
+
+def test_minimised_crystal_is_a_local_minimum(oracle_mod):
+    """A 30-ion, two-species cloud minimised in the pseudopotential trap: the
+    force is below tolerance, the energy fell, and the energy rises along 20
+    random small displacements (second-order test of a minimum)."""
+    w = li.random_cloud(30, seed=17, sigma=20e-6, light_fraction=0.3)
+    tr = _pseudo_trap(oracle_mod)
+    fu = _force_unit(tr)
+    st = w.state()
+    for k in ("vx", "vy", "vz"):
+        st[k] = np.zeros(30)
+    out = oracle_mod.minimize(st, w.charge, w.mass, tr, dt=2e-8, dmax=1e-6, ftol=1e-9 * fu,
+                              max_iter=200000)
+    assert out["fmax"] <= 1e-9 * fu
+
+    def pot(s):
+        return sum(oracle_mod.energy(s, w.charge, w.mass, tr)[1:])
+
+    e_min = pot(out)
+    assert e_min < pot(st)
+    rng = np.random.default_rng(3)
+    l = _length_scale(tr)
+    for _ in range(20):
+        d = rng.normal(size=(3, 30)) * 1e-3 * l
+        s2 = dict(out, x=out["x"] + d[0], y=out["y"] + d[1], z=out["z"] + d[2])
+        assert pot(s2) > e_min
+
+
+def test_minimiser_step_cap_and_projection(oracle_mod):
+    """One iteration from a far-off start: every ion moves at most dmax; a
+    velocity pointing against the force is dropped (only dt a remains)."""
+    w = li.random_cloud(8, seed=18, sigma=200e-6)
+    tr = _pseudo_trap(oracle_mod)
+    st = w.state()
+    ax, ay, az = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    st.update(vx=-ax * 1e-7, vy=-ay * 1e-7, vz=-az * 1e-7)  # v . F < 0
+    dmax = 1e-7
+    out = oracle_mod.minimize(st, w.charge, w.mass, tr, dt=1e-8, dmax=dmax, ftol=0.0,
+                              max_iter=1)
+    assert out["iterations"] == 1
+    step = np.sqrt((out["x"] - w.x) ** 2 + (out["y"] - w.y) ** 2 + (out["z"] - w.z) ** 2)
+    assert np.all(step <= dmax * (1 + 1e-12))
+    v = np.stack([out["vx"], out["vy"], out["vz"]])
+    a = np.stack([ax, ay, az])
+    small = 1e-16 * np.linalg.norm(a, axis=0) <= dmax  # moves dt^2 |a| below the cap
+    assert np.any(small) and not np.all(small)
+    assert np.allclose(v[:, small], 1e-8 * a[:, small], rtol=1e-15, atol=0)
+    capped = ~small
+    assert np.allclose(step[capped], dmax, rtol=1e-12, atol=0)
