@@ -14,7 +14,8 @@ from tests import test_oracle_pins as pins
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lion_oracle.c")
 
 MUTANTS = {
-    "dc_sign_flipped": ("*ez = -2.0 * a_dc * z;", "*ez = 2.0 * a_dc * z;"),
+    "dc_sign_flipped": ("*ey = -a_rf * c * y + a_dc * y;\n    *ez = -2.0 * a_dc * z;",
+                        "*ey = -a_rf * c * y + a_dc * y;\n    *ez = 2.0 * a_dc * z;"),
     "rf_y_sign_flipped": ("*ey = -a_rf * c * y + a_dc * y;", "*ey = a_rf * c * y + a_dc * y;"),
     "rf_term_dropped": ("*ex = a_rf * c * x + a_dc * x;", "*ex = a_dc * x;"),
     "pair_index_swapped": ("double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n            double r2 = dx * dx + dy * dy + dz * dz;\n            if (r2 == 0.0) {",
@@ -64,7 +65,7 @@ def _build_mutant(tmp_path, old, new):
     assert src.count(old) >= 1, "mutation anchor not found"
     c = tmp_path / "mut.c"
     so = tmp_path / "libmut.so"
-    c.write_text(src.replace(old, new, 1))
+    c.write_text(src.replace(old, new))  # the slip made wherever the text appears
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c99", "-shared", "-fPIC",
                     str(c), "-o", str(so), "-lm"], check=True)
     return str(so)
@@ -191,7 +192,7 @@ def test_pins_reject_mutant(tmp_path, name, oracle_mod):
     old, new = MUTANTS[name]
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor not found: {name}"
-    mutated = src.replace(old, new, 1)
+    mutated = src.replace(old, new)  # the slip made wherever the text appears
     c = tmp_path / "mut.c"
     so = tmp_path / "libmut.so"
     c.write_text(mutated)
