@@ -189,6 +189,33 @@ int lion_set_time_average(lion_sim *sim, int32_t window_steps);
 int lion_get_time_average(lion_sim *sim, double *vx, double *vy, double *vz,
                           int64_t *window_end_step);
 
+/* Pseudopotential trap (section "Electric fields and confinement": the
+ * linearPseudoPT trap; eq. (pseudopot) with the Mathieu coefficients of
+ * eq. (Mathieuaq)).  Same parameters as lion_set_trap; the rf is replaced by
+ * the static radial field -(Q/M) (V_rf/r0^2)^2 / (2 Omega^2) (x, y, 0), so each
+ * ion feels the secular frequency of its own Q/M (one trap serves every
+ * species).  The dc field is unchanged.  lion_get_energy's trap energy then
+ * includes the radial potential (1/2) Q (Q/M) (V_rf/r0^2)^2/(2 Omega^2)(x^2+y^2).
+ * lion_set_trap switches back to the full field.  Errors as lion_set_trap. */
+int lion_set_pseudo_trap(lion_sim *sim, int32_t trap, double V_rf, double Omega_rad_s,
+                         double U_dc, double r0, double z0, double kappa);
+
+/* Energy minimisation (section "Minimisation": damped dynamics that extract
+ * energy and cap each ion's move per step).  With F_i = M_i a_i at the current
+ * positions, each iteration: stop if max_i |F_i| <= ftol_N (or max_iter
+ * iterations were done); keep only the component of the 3N velocity along the
+ * 3N force (v <- (v.F / F.F) F if v.F > 0, else 0); v <- v + dt a; scale any
+ * ion's velocity so that dt |v_i| <= dmax_m; x <- x + dt v; forces at the new
+ * positions.  Starts from the current velocities and leaves the minimiser's
+ * velocities in the state; the trap clock does not advance.  The trap must be
+ * time independent (pseudopotential trap, or V_rf = 0) -> else
+ * LION_ERR_UNSUPPORTED, as are batched handles and rigid bodies.  State not
+ * set -> LION_ERR_STATE; dt, dmax <= 0, ftol < 0, max_iter < 0 or non-finite
+ * -> LION_ERR_ARG.  *iterations (optional) gets the iterations that moved the
+ * ions, *fmax_N (optional) the largest |F_i| at the final positions. */
+int lion_minimize(lion_sim *sim, double dt, double dmax_m, double ftol_N, int64_t max_iter,
+                  int64_t *iterations, double *fmax_N);
+
 /* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite).
  * nsteps = 0 is a no-op.  Time afterwards: t + nsteps dt.  Requires
  * lion_set_state first (else LION_ERR_STATE). */

@@ -83,7 +83,7 @@ int slices_for(int64_t n) {
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
         flags, body_code, body_gmin, body_gmax, cool, species, vacc, vavg, rigid, rb, dbody,
-        rmembers, rstart, total;
+        rmembers, rstart, minst, minpart, total;
 };
 
 Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
@@ -123,6 +123,8 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.dbody = batched ? SIZE_MAX : take(3 * np * sizeof(double));
     L.rmembers = batched ? SIZE_MAX : take(np * sizeof(int32_t));
     L.rstart = batched ? SIZE_MAX : take((np + 1) * sizeof(int32_t));
+    L.minst = take(sizeof(lion::MinDev));
+    L.minpart = take((size_t)3 * ((np + 255) / 256) * sizeof(double));
     L.total = o;
     return L;
 }
@@ -300,6 +302,47 @@ int run_chunk(lion_sim* s, int64_t L) {
     return LION_OK;
 }
 
+// K minimisation iterations: reduce + stopping test, move, forces at the new
+// positions (a graph per K, parameters read from device memory).
+hipError_t enqueue_min_chunk(lion_sim* s, int64_t K, hipStream_t st) {
+    for (int64_t k = 0; k < K; ++k) {
+        hipError_t e = lion::launch_min_reduce(s->d, st);
+        if (e == hipSuccess) e = lion::launch_min_move(s->d, s->precision, st);
+        if (e == hipSuccess) e = lion::launch_pair(s->d, s->precision, s->ls, false, st);
+        if (e == hipSuccess)
+            e = lion::launch_update(s->d, s->precision, s->ls, lion::kModeAccel, false, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int run_min_chunk(lion_sim* s, int64_t K) {
+    if (s->cfg.use_graph == 2) {
+        LION_HIP(s, enqueue_min_chunk(s, K, s->stream));
+        return LION_OK;
+    }
+    auto key = std::make_pair(K, 1);
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+        hipGraph_t g = nullptr;
+        LION_HIP(s, hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_min_chunk(s, K, s->capture);
+        hipError_t e2 = hipStreamEndCapture(s->capture, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(s, e, "capture minimisation chunk");
+        }
+        if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+        it = s->graphs.emplace(key, ex).first;
+    }
+    LION_HIP(s, hipGraphLaunch(it->second, s->stream));
+    return LION_OK;
+}
+
 int check_ws(lion_sim* s, void* ws, size_t bytes, size_t need) {
     if (!ws) return fail(s, LION_ERR_WORKSPACE, "workspace pointer is NULL");
     if (((uintptr_t)ws) % kAlign) return fail(s, LION_ERR_WORKSPACE, "workspace not 256-byte aligned");
@@ -377,6 +420,8 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     d.species = (int32_t*)(base + L.species);
     d.vacc = (double*)(base + L.vacc);
     d.vavg = (double*)(base + L.vavg);
+    d.minst = (lion::MinDev*)(base + L.minst);
+    d.minpart = (double*)(base + L.minpart);
     d.nbodies = 0;  // set by lion_set_rigid_bodies
     d.rigid = nullptr;
     d.rb = nullptr;
@@ -597,9 +642,25 @@ int lion_set_trap(lion_sim* s, int32_t trap, double V_rf, double Omega, double U
         s->traps[k].a_rf = V_rf / (r0 * r0);
         s->traps[k].omega = Omega;
         s->traps[k].a_dc = kappa * U_dc / (z0 * z0);
+        s->traps[k].ps = 0.0;
     }
     LION_HIP(s, hipSetDevice(s->device));
     int rc = upload_traps(s);
+    if (rc) return rc;
+    if (s->state_set) return refresh_accel(s);
+    return LION_OK;
+}
+
+int lion_set_pseudo_trap(lion_sim* s, int32_t trap, double V_rf, double Omega, double U_dc,
+                         double r0, double z0, double kappa) {
+    int rc = lion_set_trap(s, trap, V_rf, Omega, U_dc, r0, z0, kappa);
+    if (rc) return rc;
+    const int lo = trap < 0 ? 0 : trap, hi = trap < 0 ? s->n_traps : trap + 1;
+    for (int k = lo; k < hi; ++k) {
+        const double a_rf = s->traps[k].a_rf;
+        s->traps[k].ps = a_rf != 0.0 ? (a_rf * a_rf) / (2.0 * Omega * Omega) : 0.0;
+    }
+    rc = upload_traps(s);
     if (rc) return rc;
     if (s->state_set) return refresh_accel(s);
     return LION_OK;
@@ -875,6 +936,42 @@ int lion_compute_accel(lion_sim* s, double* ax, double* ay, double* az) {
     return LION_OK;
 }
 
+int lion_minimize(lion_sim* s, double dt, double dmax, double ftol, int64_t max_iter,
+                  int64_t* iterations, double* fmax) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (s->batched) return fail(s, LION_ERR_UNSUPPORTED, "minimisation is for single traps");
+    if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
+    if (s->d.nbodies > 0) return fail(s, LION_ERR_UNSUPPORTED, "minimisation with rigid bodies");
+    if (!is_fin(dt) || dt <= 0.0 || !is_fin(dmax) || dmax <= 0.0 || !is_fin(ftol) || ftol < 0.0 ||
+        max_iter < 0)
+        return fail(s, LION_ERR_ARG, "need dt > 0, dmax > 0, ftol >= 0, max_iter >= 0 (all finite)");
+    const TrapDev& T = s->traps[0];
+    if (T.ps == 0.0 && T.a_rf != 0.0)
+        return fail(s, LION_ERR_UNSUPPORTED,
+                    "minimisation needs a time-independent trap (pseudopotential trap or no rf)");
+    LION_HIP(s, hipSetDevice(s->device));
+    int rc = refresh_accel(s);  // forces at the current positions, trap clock fixed
+    if (rc) return rc;
+    lion::MinDev m{};
+    m.dt = dt;
+    m.dmax = dmax;
+    m.ftol = ftol;
+    m.max_iter = max_iter;
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipMemcpyAsync(s->d.minst, &m, sizeof(m), hipMemcpyHostToDevice, st));
+    const int64_t K = 50;
+    for (;;) {
+        rc = run_min_chunk(s, K);
+        if (rc) return rc;
+        LION_HIP(s, hipMemcpyAsync(&m, s->d.minst, sizeof(m), hipMemcpyDeviceToHost, st));
+        LION_HIP(s, hipStreamSynchronize(st));
+        if (m.done) break;
+    }
+    if (iterations) *iterations = m.iterations;
+    if (fmax) *fmax = m.fmax;
+    return LION_OK;
+}
+
 int lion_get_energy(lion_sim* s, double* kinetic, double* coulomb, double* dc_trap) {
     if (check_handle(s)) return LION_ERR_ARG;
     if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
@@ -899,13 +996,14 @@ int lion_get_energy(lion_sim* s, double* kinetic, double* coulomb, double* dc_tr
     const double ke_e2 = lion::kElementaryCharge * lion::kElementaryCharge / (4.0 * lion::kPi * lion::kEps0);
     double K = 0, Kc = 0, C = 0, Cc = 0, D = 0, Dc = 0;
     for (int k = 0; k < s->n_traps; ++k) {
-        const double a_dc = s->traps[k].a_dc;
+        const double a_dc = s->traps[k].a_dc, ps = s->traps[k].ps;
         for (int64_t i = s->offsets[k]; i < s->offsets[k + 1]; ++i) {
             const double m = s->mass[i], q = s->charge[i];
             add(K, Kc, 0.5 * m * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]));
             add(C, Cc, 0.5 * ke_e2 * (q / lion::kElementaryCharge) * pe[i]);
             const double4 p = src[i];
             add(D, Dc, q * a_dc * (p.z * p.z - 0.5 * (p.x * p.x + p.y * p.y)));
+            if (ps != 0.0) add(D, Dc, 0.5 * q * (q / m) * ps * (p.x * p.x + p.y * p.y));
         }
     }
     if (kinetic) *kinetic = K + Kc;

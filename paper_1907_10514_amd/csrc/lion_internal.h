@@ -38,6 +38,7 @@ struct TrapDev {
     double h;        // dt / 2
     double t_start;  // s
     double gamma;    // 1/s (kept for reference)
+    double ps;       // pseudopotential trap: A_rf^2 / (2 Omega^2); 0 for the full rf field
 };
 
 // Cooling in the velocity half-steps (applied after the isotropic damping):
@@ -75,6 +76,18 @@ struct CoolDev {
     int32_t avg_window;
     int32_t avg_pad;
     int64_t avg_origin;
+};
+
+// Minimisation state in device memory: parameters, the last reduction and
+// the iteration count (kernels read the parameters here, so one captured
+// graph serves every call).
+struct MinDev {
+    double dt, dmax, ftol;
+    double P, FF, fmax;   // v.F, F.F, max |F| at the current positions
+    int64_t iterations;   // iterations that moved the ions
+    int64_t max_iter;
+    int32_t done;         // fmax <= ftol or iterations >= max_iter
+    int32_t pad;
 };
 
 // Rigid body: a group of ions that keeps its shape.  Member i sits at
@@ -149,6 +162,8 @@ struct DevState {
     int32_t* species; // [n_pad] species label per ion (default 0)
     double* vacc;     // [3][n_pad] velocity sums of the open averaging window
     double* vavg;     // [3][n_pad] average of the last completed window
+    MinDev* minst;       // minimisation state
+    double* minpart;     // [3 * blocks of 256 ions] partial reductions
     // rigid-body integration (NULL / 0 when off)
     int32_t nbodies;
     RigidDev* rigid;     // [nbodies]
@@ -191,6 +206,8 @@ hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int
 hipError_t launch_rigid_wrench(const DevState& s, bool end_kick, hipStream_t st);
 hipError_t launch_rigid_drift(const DevState& s, hipStream_t st);
 hipError_t launch_rigid_place(const DevState& s, int precision, hipStream_t st);
+hipError_t launch_min_reduce(const DevState& s, hipStream_t st);
+hipError_t launch_min_move(const DevState& s, int precision, hipStream_t st);
 hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
 hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
 hipError_t launch_check_finite(const DevState& s, hipStream_t st);

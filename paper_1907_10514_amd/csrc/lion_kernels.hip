@@ -169,6 +169,17 @@ __device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm
                                            double y, double z, double Sx, double Sy, double Sz,
                                            double& ax, double& ay, double& az) {
 #pragma clang fp contract(off)
+    if (T.ps != 0.0) {
+        // pseudopotential trap: static radial field -(Q/M) A_rf^2/(2 Omega^2) (x, y, 0)
+        const double k = qm * T.ps;
+        const double ex = T.a_dc * x - k * x;
+        const double ey = T.a_dc * y - k * y;
+        const double ez = -2.0 * T.a_dc * z;
+        ax = qm * (kKeE * Sx + ex);
+        ay = qm * (kKeE * Sy + ey);
+        az = qm * (kKeE * Sz + ez);
+        return;
+    }
     const double c = cos(T.omega * t);
     const double ex = T.a_rf * c * x + T.a_dc * x;
     const double ey = -T.a_rf * c * y + T.a_dc * y;
@@ -1439,6 +1450,123 @@ __global__ __launch_bounds__(256) void k_rigid_place(const RigidDev* __restrict_
     if (srcm) srcm[i] = make_src(x, y, z, qe[i]);
 }
 
+// ------------------------------------------------------------ minimisation
+
+// Per block of 256 ions: sums of v.F and F.F and the largest |F| (F = M a),
+// reduced over the block in a fixed tree order.
+__global__ __launch_bounds__(256) void k_min_partial(const double* __restrict__ vx,
+                                                     const double* __restrict__ vy,
+                                                     const double* __restrict__ vz,
+                                                     const double* __restrict__ ax,
+                                                     const double* __restrict__ ay,
+                                                     const double* __restrict__ az,
+                                                     const double* __restrict__ mass, int64_t n,
+                                                     double* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ double r[3][256];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    double P = 0.0, FF = 0.0, fm = 0.0;
+    if (i < n) {
+        const double fx = mass[i] * ax[i], fy = mass[i] * ay[i], fz = mass[i] * az[i];
+        P = vx[i] * fx + vy[i] * fy + vz[i] * fz;
+        FF = fx * fx + fy * fy + fz * fz;
+        fm = sqrt(FF);
+    }
+    r[0][tid] = P;
+    r[1][tid] = FF;
+    r[2][tid] = fm;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            r[0][tid] += r[0][tid + w];
+            r[1][tid] += r[1][tid + w];
+            r[2][tid] = fmax(r[2][tid], r[2][tid + w]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[3 * blockIdx.x] = r[0][0];
+        part[3 * blockIdx.x + 1] = r[1][0];
+        part[3 * blockIdx.x + 2] = r[2][0];
+    }
+}
+
+// One block: the partials in a fixed order, then the stopping test.
+__global__ __launch_bounds__(256) void k_min_final(const double* __restrict__ part, int nblocks,
+                                                   MinDev* __restrict__ ms) {
+#pragma clang fp contract(off)
+    __shared__ double r[3][256];
+    const int tid = threadIdx.x;
+    double P = 0.0, FF = 0.0, fm = 0.0;
+    for (int b = tid; b < nblocks; b += 256) {
+        P += part[3 * b];
+        FF += part[3 * b + 1];
+        fm = fmax(fm, part[3 * b + 2]);
+    }
+    r[0][tid] = P;
+    r[1][tid] = FF;
+    r[2][tid] = fm;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            r[0][tid] += r[0][tid + w];
+            r[1][tid] += r[1][tid + w];
+            r[2][tid] = fmax(r[2][tid], r[2][tid + w]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ms->P = r[0][0];
+        ms->FF = r[1][0];
+        ms->fmax = r[2][0];
+        ms->done = (r[2][0] <= ms->ftol || ms->iterations >= ms->max_iter) ? 1 : 0;
+    }
+}
+
+// One iteration's move: keep the velocity's component along the 3N force (or
+// drop it), kick by dt a, cap each ion's move at dmax, drift.  Does nothing
+// once the stopping test has passed.
+__global__ __launch_bounds__(256) void k_min_move(double4* __restrict__ src,
+                                                  MixedSrc* __restrict__ srcm,
+                                                  double* __restrict__ vx,
+                                                  double* __restrict__ vy,
+                                                  double* __restrict__ vz,
+                                                  const double* __restrict__ ax,
+                                                  const double* __restrict__ ay,
+                                                  const double* __restrict__ az,
+                                                  const double* __restrict__ mass,
+                                                  const double* __restrict__ qe, int64_t n,
+                                                  MinDev* __restrict__ ms) {
+#pragma clang fp contract(off)
+    if (ms->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double dt = ms->dt, dmax = ms->dmax, P = ms->P, FF = ms->FF;
+    if (i == 0) ms->iterations += 1;  // one thread; nobody else reads it in this launch
+    if (i >= n) return;
+    const double coef = (P > 0.0 && FF > 0.0) ? P / FF : 0.0;
+    double u = coef * (mass[i] * ax[i]), v = coef * (mass[i] * ay[i]), w = coef * (mass[i] * az[i]);
+    u = u + dt * ax[i];
+    v = v + dt * ay[i];
+    w = w + dt * az[i];
+    const double step = dt * sqrt(u * u + v * v + w * w);
+    if (step > dmax) {
+        const double r = dmax / step;
+        u = u * r;
+        v = v * r;
+        w = w * r;
+    }
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+    double4 p = src[i];
+    p.x = p.x + dt * u;
+    p.y = p.y + dt * v;
+    p.z = p.z + dt * w;
+    src[i] = p;
+    if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
+}
+
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 inline int n64_of(int64_t n) { return (int)((n + 63) & ~int64_t(63)); }
@@ -1607,6 +1735,22 @@ hipError_t launch_rigid_place(const DevState& s, int precision, hipStream_t st) 
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
     k_rigid_place<<<blocks_for(s.n, 256), 256, 0, st>>>(s.rigid, s.rb, s.dbody, s.src, srcm, s.qe,
                                                         s.n, s.n_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_reduce(const DevState& s, hipStream_t st) {
+    const unsigned nb = blocks_for(s.n, 256);
+    k_min_partial<<<nb, 256, 0, st>>>(s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.mass, s.n, s.minpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_min_final<<<1, 256, 0, st>>>(s.minpart, (int)nb, s.minst);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_move(const DevState& s, int precision, hipStream_t st) {
+    MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
+    k_min_move<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
+                                                     s.az, s.mass, s.qe, s.n, s.minst);
     return hipGetLastError();
 }
 

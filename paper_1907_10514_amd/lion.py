@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.lion_set_damping.argtypes = [vp, i32, d]
     lib.lion_set_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_set_species.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lion_set_pseudo_trap.argtypes = [vp, i32, d, d, d, d, d, d]
+    lib.lion_minimize.argtypes = [vp, d, d, d, i64, ctypes.POINTER(ctypes.c_int64), dp]
     lib.lion_set_rigid_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_get_rigid_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), dp, dp, dp, dp]
     lib.lion_set_beam.argtypes = [vp, i32, i32, d, d, d, d]
@@ -100,7 +102,8 @@ def load(path: str = LIB_PATH):
     lib.lion_constants.restype = None
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
                  "lion_set_damping", "lion_set_bodies", "lion_set_rigid_bodies",
-                 "lion_get_rigid_state", "lion_set_species", "lion_set_beam",
+                 "lion_get_rigid_state", "lion_set_pseudo_trap", "lion_minimize",
+                 "lion_set_species", "lion_set_beam",
                  "lion_set_bath", "lion_set_step_index", "lion_set_time_average",
                  "lion_get_time_average", "lion_step", "lion_step_batch", "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite",
@@ -191,6 +194,19 @@ def lion_get_rigid_state(h, max_bodies):
     k = nb.value
     return dict(com=com[:3 * k].reshape(k, 3), com_velocity=vel[:3 * k].reshape(k, 3),
                 angular_momentum=ang[:3 * k].reshape(k, 3), quaternion=quat[:4 * k].reshape(k, 4))
+
+
+def lion_set_pseudo_trap(h, trap, V_rf, Omega, U_dc, r0, z0, kappa):
+    _check(load().lion_set_pseudo_trap(h, int(trap), float(V_rf), float(Omega), float(U_dc),
+                                       float(r0), float(z0), float(kappa)), h)
+
+
+def lion_minimize(h, dt, dmax, ftol, max_iter):
+    it = ctypes.c_int64(0)
+    fm = ctypes.c_double(0.0)
+    _check(load().lion_minimize(h, float(dt), float(dmax), float(ftol), int(max_iter),
+                                ctypes.byref(it), ctypes.byref(fm)), h)
+    return int(it.value), float(fm.value)
 
 
 def lion_set_species(h, species):
@@ -376,6 +392,14 @@ class Simulation:
 
     def set_bodies(self, body_id):
         lion_set_bodies(self.h, body_id)
+
+    def set_pseudo_trap(self, V_rf, Omega, U_dc, r0, z0, kappa, trap=-1):
+        """Pseudopotential trap: the rf replaced by its static radial field."""
+        lion_set_pseudo_trap(self.h, trap, V_rf, Omega, U_dc, r0, z0, kappa)
+
+    def minimize(self, dt, dmax, ftol, max_iter=100000):
+        """Damped minimisation; returns (iterations, largest |F| in N)."""
+        return lion_minimize(self.h, dt, dmax, ftol, max_iter)
 
     def set_rigid_bodies(self, body):
         """Integrate ions with equal body id >= 0 as rigid bodies (None: off)."""
