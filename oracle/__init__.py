@@ -123,6 +123,8 @@ def bind(path: str):
                                        ctypes.POINTER(_Bath), i64, i64, ctypes.c_double,
                                        ctypes.c_double, i64, dp]
     lib.oracle_step_cooled.restype = i64
+    lib.oracle_hessian.argtypes = [i64, dp, dp, dp, dp, dp, tp, dp]
+    lib.oracle_hessian.restype = None
     lib.oracle_minimize.argtypes = [i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, tp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, i64, dp]
@@ -422,6 +424,23 @@ def step_rigid(state: dict, charge, mass, body, trap: Trap, gamma: float, t_star
                               int(nsteps), ctypes.byref(t_end))
     s.update(ax=ax, ay=ay, az=az, t=t_end.value)
     return s, rg
+
+
+def hessian(x, y, z, charge, mass, trap: Trap) -> np.ndarray:
+    """Mass-weighted Hessian (3n x 3n) of the static potential (see lion_oracle.c)."""
+    x, y, z, q, m = map(_f64, (x, y, z, charge, mass))
+    n = x.size
+    D = np.empty((3 * n, 3 * n))
+    tr = trap._c()
+    _load().oracle_hessian(n, _d(x), _d(y), _d(z), _d(q), _d(m), ctypes.byref(tr), _d(D))
+    return D
+
+
+def normal_modes(x, y, z, charge, mass, trap: Trap):
+    """Squared angular frequencies (ascending) and modes (columns, index 3i+axis)
+    of the mass-weighted Hessian, by numpy's symmetric eigen-solver."""
+    w2, v = np.linalg.eigh(hessian(x, y, z, charge, mass, trap))
+    return w2, v
 
 
 def minimize(state: dict, charge, mass, trap: Trap, dt: float, dmax: float, ftol: float,

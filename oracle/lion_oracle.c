@@ -830,3 +830,50 @@ int64_t oracle_minimize(int64_t n, double *x, double *y, double *z, double *vx, 
     }
     return it;
 }
+
+/* ------------------------------------------------------------ normal modes
+ *
+ * Mass-weighted Hessian of the static potential (section "Normal modes of
+ * motion": mode frequencies are eigenvalues of the Hessian of
+ * eq. (fullPotential); the trap part is the pseudopotential's, or the dc alone
+ * when there is no rf).  D[3i+a][3j+b] = d^2 V / dx_ia dx_jb / sqrt(M_i M_j):
+ *   i != j: k_e Q_i Q_j (delta_ab / r^3 - 3 r_a r_b / r^5),  r = x_i - x_j;
+ *   i == j: minus the sum of those blocks over j, plus the trap curvature
+ *           Q_i (Q_i/M_i) A_rf^2/(2 Omega^2) - Q_i A_dc on x and y (the first
+ *           term only for the pseudopotential trap) and 2 Q_i A_dc on z.
+ * D is written row-major, (3n)^2 doubles.  The eigenvalues of D are the
+ * squared angular frequencies of the normal modes. */
+void oracle_hessian(int64_t n, const double *x, const double *y, const double *z,
+                    const double *charge, const double *mass, const oracle_trap *tp, double *D) {
+    const double ke = oracle_coulomb_constant();
+    const double a_dc = tp->kappa * tp->U0 / (tp->Z0 * tp->Z0);
+    const double ps = pseudo_strength(tp);
+    const int64_t m = 3 * n;
+    for (int64_t k = 0; k < m * m; ++k) D[k] = 0.0;
+#pragma omp parallel for schedule(static) if (n >= 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double diag[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double r[3] = {x[i] - x[j], y[i] - y[j], z[i] - z[j]};
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            if (r2 == 0.0) continue;
+            const double inv_r = 1.0 / sqrt(r2);
+            const double inv_r3 = inv_r * inv_r * inv_r, inv_r5 = inv_r3 * inv_r * inv_r;
+            const double c = ke * charge[i] * charge[j];
+            const double w = 1.0 / sqrt(mass[i] * mass[j]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double h = c * ((a == b ? inv_r3 : 0.0) - 3.0 * r[a] * r[b] * inv_r5);
+                    D[(3 * i + a) * m + 3 * j + b] = h * w;
+                    diag[a][b] -= h;
+                }
+        }
+        const double qm = charge[i] / mass[i];
+        diag[0][0] += charge[i] * qm * ps - charge[i] * a_dc;
+        diag[1][1] += charge[i] * qm * ps - charge[i] * a_dc;
+        diag[2][2] += 2.0 * charge[i] * a_dc;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) D[(3 * i + a) * m + 3 * i + b] = diag[a][b] / mass[i];
+    }
+}

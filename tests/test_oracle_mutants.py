@@ -157,6 +157,31 @@ MINIMISER_PINS = [
 ]
 
 
+HESSIAN_MUTANTS = {
+    "hessian_dipole_sign": ("((a == b ? inv_r3 : 0.0) - 3.0 * r[a] * r[b] * inv_r5)",
+                            "((a == b ? inv_r3 : 0.0) + 3.0 * r[a] * r[b] * inv_r5)"),
+    "hessian_off_blocks_not_mass_weighted": ("D[(3 * i + a) * m + 3 * j + b] = h * w;",
+                                             "D[(3 * i + a) * m + 3 * j + b] = h;"),
+    "hessian_axial_trap_halved": ("diag[2][2] += 2.0 * charge[i] * a_dc;",
+                                  "diag[2][2] += charge[i] * a_dc;"),
+    "hessian_pseudo_not_species_scaled": ("diag[0][0] += charge[i] * qm * ps - charge[i] * a_dc;",
+                                          "diag[0][0] += charge[i] * ps - charge[i] * a_dc;"),
+}
+
+HESSIAN_PINS = [
+    lambda o: pins.test_normal_modes_of_one_ion(o, 40.0),
+    lambda o: pins.test_normal_modes_of_one_ion(o, 17.0),
+    lambda o: pins.test_normal_modes_of_minimised_chains(o, 3),
+    lambda o: pins.test_hessian_is_minus_force_derivative(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(HESSIAN_MUTANTS))
+def test_hessian_pins_reject_mutant(tmp_path, name, oracle_mod):
+    so = _build_mutant(tmp_path, *HESSIAN_MUTANTS[name])
+    assert _count_failures(so, HESSIAN_PINS) >= 1, f"no pin caught mutant {name}"
+
+
 @pytest.mark.parametrize("name", sorted(MINIMISER_MUTANTS))
 def test_minimiser_pins_reject_mutant(tmp_path, name, oracle_mod):
     so = _build_mutant(tmp_path, *MINIMISER_MUTANTS[name])

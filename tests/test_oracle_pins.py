@@ -1046,3 +1046,107 @@ def test_minimiser_step_cap_and_projection(oracle_mod):
     assert np.allclose(v[:, small], 1e-8 * a[:, small], rtol=1e-15, atol=0)
     capped = ~small
     assert np.allclose(step[capped], dmax, rtol=1e-12, atol=0)
+
+
+# ------------------------------------------------------------------ normal modes
+
+def _pseudo_freqs(oracle_mod, tr, mass):
+    q_x, a_x = oracle_mod.mathieu_coefficients(tr.V0, tr.U0, mass, E, tr.Omega, tr.R0, tr.Z0,
+                                               tr.kappa)
+    return (oracle_mod.pseudopotential_frequency(q_x, a_x, tr.Omega),
+            oracle_mod.pseudopotential_frequency(0.0, -2 * a_x, tr.Omega))
+
+
+@pytest.mark.parametrize("mass_u", [40.0, 17.0])
+def test_normal_modes_of_one_ion(oracle_mod, mass_u):
+    """One ion: the three modes are the trap's eq. (pseudopot) frequencies."""
+    tr = _pseudo_trap(oracle_mod)
+    m = mass_u * li.AMU
+    w_r, w_z = _pseudo_freqs(oracle_mod, tr, m)
+    w2, _ = oracle_mod.normal_modes([1e-6], [-2e-6], [3e-6], [E], [m], tr)
+    assert np.allclose(np.sort(w2), np.sort([w_r ** 2, w_r ** 2, w_z ** 2]), rtol=1e-12, atol=0)
+
+
+def _james_chain_modes(n, alpha):
+    """Axial and radial mode eigenvalues (units of omega_z^2) of an n-ion chain
+    from the dimensionless equilibrium u (independent 1-D computation):
+    axial A_ii = 1 + sum_p 2/|u_i-u_p|^3, A_ij = -2/|u_i-u_j|^3;
+    radial B_ii = alpha - sum_p 1/|u_i-u_p|^3, B_ij = 1/|u_i-u_j|^3."""
+    u = analytic.chain_equilibrium(n)
+    d = np.abs(u[:, None] - u[None, :])
+    np.fill_diagonal(d, np.inf)
+    c = 1.0 / d ** 3
+    A = -2 * c
+    np.fill_diagonal(A, 1 + 2 * c.sum(1))
+    B = c.copy()
+    np.fill_diagonal(B, alpha - c.sum(1))
+    return np.linalg.eigvalsh(A), np.linalg.eigvalsh(B)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6])
+def test_normal_modes_of_minimised_chains(oracle_mod, n):
+    """Section 'Normal modes of motion': the modes of an n-ion chain minimised
+    in 3D equal the axial and radial spectra computed from the 1-D equilibrium;
+    the COM mode is omega_z, the breathing mode sqrt(3) omega_z, the two-ion
+    rocking mode sqrt(omega_r^2 - omega_z^2), and the 3-ion third axial mode
+    sqrt(29/5) omega_z."""
+    tr = _pseudo_trap(oracle_mod)
+    w_r, w_z = _pseudo_freqs(oracle_mod, tr, CA)
+    fu = _force_unit(tr)
+    out = oracle_mod.minimize(_min_start(n, seed=30 + n), np.full(n, E), np.full(n, CA), tr,
+                              dt=2e-8, dmax=1e-6, ftol=1e-12 * fu, max_iter=400000)
+    w2, _ = oracle_mod.normal_modes(out["x"], out["y"], out["z"], np.full(n, E),
+                                    np.full(n, CA), tr)
+    ax, rad = _james_chain_modes(n, (w_r / w_z) ** 2)
+    ref = np.sort(np.concatenate([ax, rad, rad])) * w_z ** 2
+    assert np.allclose(np.sort(w2), ref, rtol=1e-8, atol=0)
+    got = np.sqrt(np.sort(w2)) / w_z
+    assert np.min(np.abs(got - 1.0)) < 1e-8
+    if n >= 2:
+        assert np.min(np.abs(got - math.sqrt(3))) < 1e-8
+    if n == 2:
+        assert np.min(np.abs(got - math.sqrt((w_r / w_z) ** 2 - 1))) < 1e-8
+    if n == 3:
+        assert np.min(np.abs(got - math.sqrt(29 / 5))) < 1e-8
+
+
+def test_normal_modes_kohn_and_trace(oracle_mod):
+    """Any one-species configuration: the trace of the mass-weighted Hessian is
+    n (2 omega_r^2 + omega_z^2) (the Coulomb blocks are traceless, the Laplacian
+    of 1/r vanishing); at a minimised 3D crystal the spectrum contains the
+    three centre-of-mass frequencies exactly."""
+    tr = _pseudo_trap(oracle_mod)
+    w_r, w_z = _pseudo_freqs(oracle_mod, tr, CA)
+    w = li.random_cloud(25, seed=31, sigma=20e-6)
+    D = oracle_mod.hessian(w.x, w.y, w.z, w.charge, w.mass, tr)
+    assert np.trace(D) == pytest.approx(25 * (2 * w_r ** 2 + w_z ** 2), rel=1e-10, abs=0)
+    st = w.state()
+    for k in ("vx", "vy", "vz"):
+        st[k] = np.zeros(25)
+    out = oracle_mod.minimize(st, w.charge, w.mass, tr, dt=2e-8, dmax=1e-6,
+                              ftol=1e-11 * _force_unit(tr), max_iter=400000)
+    w2, _ = oracle_mod.normal_modes(out["x"], out["y"], out["z"], w.charge, w.mass, tr)
+    for target in (w_r ** 2, w_z ** 2):
+        assert np.min(np.abs(w2 - target)) < 1e-8 * target
+    assert np.sum(np.abs(w2 - w_r ** 2) < 1e-8 * w_r ** 2) >= 2  # x and y COM modes
+
+
+def test_hessian_is_minus_force_derivative(oracle_mod):
+    """D = -sqrt(M_i/M_j) d a_i / d x_j, by central differences of the
+    oracle's acceleration (two species, 5 ions)."""
+    w = li.random_cloud(5, seed=32, sigma=20e-6, light_fraction=0.4)
+    tr = _pseudo_trap(oracle_mod)
+    D = oracle_mod.hessian(w.x, w.y, w.z, w.charge, w.mass, tr)
+    pos = np.stack([w.x, w.y, w.z], 1)
+    h = 1e-10
+    for j in range(5):
+        for b in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[j, b] += h
+            pm[j, b] -= h
+            ap = np.stack(oracle_mod.accel(pp[:, 0], pp[:, 1], pp[:, 2], w.charge, w.mass, tr, 0.0), 1)
+            am = np.stack(oracle_mod.accel(pm[:, 0], pm[:, 1], pm[:, 2], w.charge, w.mass, tr, 0.0), 1)
+            da = (ap - am) / (2 * h)
+            col = -(da * np.sqrt(w.mass / w.mass[j])[:, None]).ravel()
+            scale = np.max(np.abs(D))
+            assert np.max(np.abs(D[:, 3 * j + b] - col)) < 1e-5 * scale, (j, b)
