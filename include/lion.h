@@ -216,6 +216,26 @@ int lion_set_pseudo_trap(lion_sim *sim, int32_t trap, double V_rf, double Omega_
 int lion_minimize(lion_sim *sim, double dt, double dmax_m, double ftol_N, int64_t max_iter,
                   int64_t *iterations, double *fmax_N);
 
+/* Device bytes lion_normal_modes needs for n ions (the (3n)^2 Hessian and
+ * two vectors of 3n); 0 for n < 1.  Host-only. */
+size_t lion_normal_modes_workspace_bytes(int64_t n);
+
+/* Normal modes at the current positions (section "Normal modes of motion":
+ * mode frequencies are the eigenvalues of the Hessian of eq. (fullPotential)).
+ * A HIP kernel builds the mass-weighted Hessian D = H / sqrt(M_i M_j) of the
+ * Coulomb pairs plus the static trap (pseudopotential and dc curvatures) in
+ * FP64, in dev_work (caller-owned device memory, 256-byte aligned, at least
+ * lion_normal_modes_workspace_bytes(n)); rocSOLVER's dsyevd diagonalises it on
+ * the GPU (rocBLAS manages that solver's own scratch memory).  Outputs (host):
+ * omega2 [3n] squared angular frequencies, ascending (rad^2/s^2); modes
+ * [3n * 3n] or NULL: column k (stride 3n, column-major) is the mass-weighted
+ * eigenvector of omega2[k], component 3i + axis.  A minimum of the potential
+ * (lion_minimize) gives omega2 >= 0.  Time-dependent trap, batched handle or
+ * rigid bodies -> LION_ERR_UNSUPPORTED; workspace too small or misaligned ->
+ * LION_ERR_WORKSPACE; solver failure -> LION_ERR_HIP. */
+int lion_normal_modes(lion_sim *sim, void *dev_work, size_t bytes, double *omega2,
+                      double *modes);
+
 /* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite).
  * nsteps = 0 is a no-op.  Time afterwards: t + nsteps dt.  Requires
  * lion_set_state first (else LION_ERR_STATE). */

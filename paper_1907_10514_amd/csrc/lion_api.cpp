@@ -936,6 +936,47 @@ int lion_compute_accel(lion_sim* s, double* ax, double* ay, double* az) {
     return LION_OK;
 }
 
+size_t lion_normal_modes_workspace_bytes(int64_t n) {
+    if (n < 1) return 0;
+    const size_t m = (size_t)(3 * n);
+    return align_up(m * m * 8) + 2 * align_up(m * 8) + align_up(sizeof(int));
+}
+
+int lion_normal_modes(lion_sim* s, void* dev_work, size_t bytes, double* omega2, double* modes) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (!omega2) return fail(s, LION_ERR_ARG, "omega2 output is NULL");
+    if (s->batched) return fail(s, LION_ERR_UNSUPPORTED, "normal modes are for single traps");
+    if (!s->state_set) return fail(s, LION_ERR_STATE, "lion_set_state has not been called");
+    if (s->has_bodies) return fail(s, LION_ERR_UNSUPPORTED, "normal modes with rigid bodies");
+    const TrapDev& T = s->traps[0];
+    if (T.ps == 0.0 && T.a_rf != 0.0)
+        return fail(s, LION_ERR_UNSUPPORTED,
+                    "normal modes need a static trap (pseudopotential trap or no rf)");
+    if (3 * s->n > 2147483647 / (3 * s->n))
+        return fail(s, LION_ERR_UNSUPPORTED, "too many ions for one dense eigen-problem");
+    int rc = check_ws(s, dev_work, bytes, lion_normal_modes_workspace_bytes(s->n));
+    if (rc) return rc;
+    const int m = (int)(3 * s->n);
+    char* base = (char*)dev_work;
+    double* A = (double*)base;
+    double* W = (double*)(base + align_up((size_t)m * m * 8));
+    double* E = (double*)(base + align_up((size_t)m * m * 8) + align_up((size_t)m * 8));
+    int* info = (int*)(base + align_up((size_t)m * m * 8) + 2 * align_up((size_t)m * 8));
+    hipStream_t st = s->stream;
+    LION_HIP(s, hipSetDevice(s->device));
+    LION_HIP(s, lion::launch_hessian(s->d, T, A, st));
+    std::string err;
+    if (lion::eigh_device(A, m, W, E, info, modes != nullptr, st, err) != 0)
+        return fail(s, LION_ERR_HIP, err);
+    int info_h = 0;
+    LION_HIP(s, hipMemcpyAsync(omega2, W, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipMemcpyAsync(&info_h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (modes) LION_HIP(s, hipMemcpyAsync(modes, A, (size_t)m * m * 8, hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    if (info_h != 0) return fail(s, LION_ERR_HIP, "eigen-solver did not converge");
+    return LION_OK;
+}
+
 int lion_minimize(lion_sim* s, double dt, double dmax, double ftol, int64_t max_iter,
                   int64_t* iterations, double* fmax) {
     if (check_handle(s)) return LION_ERR_ARG;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 namespace lion {
@@ -208,6 +209,12 @@ hipError_t launch_rigid_drift(const DevState& s, hipStream_t st);
 hipError_t launch_rigid_place(const DevState& s, int precision, hipStream_t st);
 hipError_t launch_min_reduce(const DevState& s, hipStream_t st);
 hipError_t launch_min_move(const DevState& s, int precision, hipStream_t st);
+hipError_t launch_hessian(const DevState& s, const TrapDev& T, double* D, hipStream_t st);
+// Eigenvalues (ascending, into W) and optionally eigenvectors (into A's
+// columns) of the symmetric m x m matrix A (upper triangle read) with
+// rocSOLVER; E is m doubles of scratch.  Returns 0 or -1 with err set.
+int eigh_device(double* A, int m, double* W, double* E, int* info, bool vectors, hipStream_t st,
+                std::string& err);
 hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
 hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
 hipError_t launch_check_finite(const DevState& s, hipStream_t st);

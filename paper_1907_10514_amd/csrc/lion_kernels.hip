@@ -1567,6 +1567,65 @@ __global__ __launch_bounds__(256) void k_min_move(double4* __restrict__ src,
     if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
 }
 
+// ------------------------------------------------------------ normal modes
+
+// Mass-weighted Hessian of the static potential, one 3x3 block (i, j) per
+// thread, written row-major into D (3n x 3n).  Off-diagonal blocks:
+// k_e Q_i Q_j (delta/r^3 - 3 r r^T / r^5) / sqrt(M_i M_j), r = x_i - x_j.
+// Diagonal blocks: minus the sum of those over j (ascending j), plus the trap
+// curvature (pseudopotential and dc), divided by M_i.
+__global__ __launch_bounds__(256) void k_hessian(const double4* __restrict__ src,
+                                                 const double* __restrict__ qe,
+                                                 const double* __restrict__ mass, int64_t n,
+                                                 TrapDev T, double* __restrict__ D) {
+#pragma clang fp contract(off)
+    const int64_t j = (int64_t)blockIdx.x * 16 + threadIdx.x % 16;
+    const int64_t i = (int64_t)blockIdx.y * 16 + threadIdx.x / 16;
+    if (i >= n || j >= n) return;
+    const int64_t m = 3 * n;
+    const double ke = 1.0 / (4.0 * kPi * kEps0);
+    const double4 pi = src[i];
+    const double Qi = qe[i] * kElementaryCharge;
+    if (i != j) {
+        const double4 pj = src[j];
+        const double r[3] = {pi.x - pj.x, pi.y - pj.y, pi.z - pj.z};
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double w = 1.0 / sqrt(mass[i] * mass[j]);
+        double inv_r3 = 0.0, inv_r5 = 0.0, c = 0.0;
+        if (r2 != 0.0) {
+            const double inv_r = 1.0 / sqrt(r2);
+            inv_r3 = inv_r * inv_r * inv_r;
+            inv_r5 = inv_r3 * inv_r * inv_r;
+            c = ke * Qi * (qe[j] * kElementaryCharge);
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                D[(3 * i + a) * m + 3 * j + b] =
+                    c * ((a == b ? inv_r3 : 0.0) - 3.0 * r[a] * r[b] * inv_r5) * w;
+        return;
+    }
+    double diag[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int64_t k = 0; k < n; ++k) {
+        if (k == i) continue;
+        const double4 pk = src[k];
+        const double r[3] = {pi.x - pk.x, pi.y - pk.y, pi.z - pk.z};
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 == 0.0) continue;
+        const double inv_r = 1.0 / sqrt(r2);
+        const double inv_r3 = inv_r * inv_r * inv_r, inv_r5 = inv_r3 * inv_r * inv_r;
+        const double c = ke * Qi * (qe[k] * kElementaryCharge);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                diag[a][b] -= c * ((a == b ? inv_r3 : 0.0) - 3.0 * r[a] * r[b] * inv_r5);
+    }
+    const double qm = Qi / mass[i];
+    diag[0][0] += Qi * qm * T.ps - Qi * T.a_dc;
+    diag[1][1] += Qi * qm * T.ps - Qi * T.a_dc;
+    diag[2][2] += 2.0 * Qi * T.a_dc;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) D[(3 * i + a) * m + 3 * i + b] = diag[a][b] / mass[i];
+}
+
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 inline int n64_of(int64_t n) { return (int)((n + 63) & ~int64_t(63)); }
@@ -1751,6 +1810,12 @@ hipError_t launch_min_move(const DevState& s, int precision, hipStream_t st) {
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
     k_min_move<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                      s.az, s.mass, s.qe, s.n, s.minst);
+    return hipGetLastError();
+}
+
+hipError_t launch_hessian(const DevState& s, const TrapDev& T, double* D, hipStream_t st) {
+    const unsigned g = blocks_for(s.n, 16);
+    k_hessian<<<dim3(g, g), 256, 0, st>>>(s.src, s.qe, s.mass, s.n, T, D);
     return hipGetLastError();
 }
 

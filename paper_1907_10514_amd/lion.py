@@ -74,6 +74,9 @@ def load(path: str = LIB_PATH):
     lib.lion_set_species.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_set_pseudo_trap.argtypes = [vp, i32, d, d, d, d, d, d]
     lib.lion_minimize.argtypes = [vp, d, d, d, i64, ctypes.POINTER(ctypes.c_int64), dp]
+    lib.lion_normal_modes_workspace_bytes.argtypes = [i64]
+    lib.lion_normal_modes_workspace_bytes.restype = sz
+    lib.lion_normal_modes.argtypes = [vp, vp, sz, dp, dp]
     lib.lion_set_rigid_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_get_rigid_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), dp, dp, dp, dp]
     lib.lion_set_beam.argtypes = [vp, i32, i32, d, d, d, d]
@@ -103,6 +106,7 @@ def load(path: str = LIB_PATH):
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
                  "lion_set_damping", "lion_set_bodies", "lion_set_rigid_bodies",
                  "lion_get_rigid_state", "lion_set_pseudo_trap", "lion_minimize",
+                 "lion_normal_modes_workspace_bytes", "lion_normal_modes",
                  "lion_set_species", "lion_set_beam",
                  "lion_set_bath", "lion_set_step_index", "lion_set_time_average",
                  "lion_get_time_average", "lion_step", "lion_step_batch", "lion_get_state",
@@ -207,6 +211,19 @@ def lion_minimize(h, dt, dmax, ftol, max_iter):
     _check(load().lion_minimize(h, float(dt), float(dmax), float(ftol), int(max_iter),
                                 ctypes.byref(it), ctypes.byref(fm)), h)
     return int(it.value), float(fm.value)
+
+
+def lion_normal_modes_workspace_bytes(n):
+    return int(load().lion_normal_modes_workspace_bytes(int(n)))
+
+
+def lion_normal_modes(h, n, ws_ptr, ws_bytes, vectors=False):
+    m = 3 * int(n)
+    w2 = np.empty(m)
+    modes = np.empty((m, m), order="F") if vectors else None
+    _check(load().lion_normal_modes(h, ctypes.c_void_p(ws_ptr), int(ws_bytes), _dp(w2),
+                                    _dp(modes) if vectors else None), h)
+    return w2, modes
 
 
 def lion_set_species(h, species):
@@ -400,6 +417,20 @@ class Simulation:
     def minimize(self, dt, dmax, ftol, max_iter=100000):
         """Damped minimisation; returns (iterations, largest |F| in N)."""
         return lion_minimize(self.h, dt, dmax, ftol, max_iter)
+
+    def normal_modes(self, vectors=False):
+        """(omega^2 ascending [3n], modes [3n, 3n] column k = mode k, or None) at
+        the current positions; device scratch is a temporary torch tensor."""
+        import torch
+
+        nb = lion_normal_modes_workspace_bytes(self.n)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        ptr = (ws.data_ptr() + 255) // 256 * 256
+        try:
+            return lion_normal_modes(self.h, self.n, ptr, nb, vectors)
+        finally:
+            torch.cuda.current_stream(self.device).synchronize()
+            del ws
 
     def set_rigid_bodies(self, body):
         """Integrate ions with equal body id >= 0 as rigid bodies (None: off)."""

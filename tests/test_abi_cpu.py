@@ -137,3 +137,15 @@ def test_binding_fails_loudly_without_library(tmp_path):
             lion.load(str(tmp_path / "missing.so"))
     finally:
         lion._lib = saved
+
+
+def test_normal_modes_workspace_size():
+    from paper_1907_10514_amd import lion as L
+
+    def up(b):
+        return (b + 255) // 256 * 256
+
+    assert L.lion_normal_modes_workspace_bytes(0) == 0
+    for n in (1, 7, 1000):
+        m = 3 * n
+        assert L.lion_normal_modes_workspace_bytes(n) == up(m * m * 8) + 2 * up(m * 8) + up(4)

@@ -215,3 +215,79 @@ def test_minimize_rejections(torch_gpu, oracle_mod):
         bat.minimize(1e-8, 1e-6, 0.0)
     assert ei.value.code == L.LION_ERR_UNSUPPORTED
     bat.close()
+
+
+# ------------------------------------------------------------------ normal modes
+
+def _modes_case(oracle_mod, kind):
+    tr = _pseudo(oracle_mod)
+    l, k = _length_scale(tr)
+    fu = k * l
+    if kind == "chain6":
+        st = _chain_start(6, seed=6)
+        m, q = np.full(6, CA), np.full(6, E)
+        st = oracle_mod.minimize(st, q, m, tr, dt=2e-8, dmax=1e-6, ftol=1e-11 * fu,
+                                 max_iter=400000)
+    elif kind == "crystal60":
+        w = li.random_cloud(60, seed=61, sigma=20e-6, light_fraction=0.3)
+        m, q = w.mass, w.charge
+        st = w.state()
+        for c in ("vx", "vy", "vz"):
+            st[c] = np.zeros(60)
+        st = oracle_mod.minimize(st, q, m, tr, dt=2e-8, dmax=1e-6, ftol=1e-10 * fu,
+                                 max_iter=800000)
+    else:  # an unrelaxed 512-ion two-species cloud (modes of a saddle: some omega^2 < 0)
+        w = li.random_cloud(512, seed=62, sigma=40e-6, light_fraction=0.3)
+        m, q, st = w.mass, w.charge, w.state()
+    return tr, m, q, st
+
+
+@pytest.mark.parametrize("kind", ["chain6", "crystal60", "cloud512"])
+def test_normal_modes_match_oracle(torch_gpu, oracle_mod, kind):
+    """Eigenvalues of the GPU's mass-weighted Hessian (HIP kernel + rocSOLVER)
+    against the oracle's (plain loops + numpy eigh) at the same positions;
+    eigenvectors satisfy D v = omega^2 v with the oracle's D and are
+    orthonormal."""
+    tr, m, q, st = _modes_case(oracle_mod, kind)
+    sim = _sim(m, q, "fp64", tr, st)
+    w2, V = sim.normal_modes(vectors=True)
+    ref, _ = oracle_mod.normal_modes(st["x"], st["y"], st["z"], q, m, tr)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(w2 - ref))
+    print(f"{kind}: max |omega^2 - oracle| / max|omega^2| = {err / scale:.2e}")
+    assert err < 1e-12 * scale
+    D = oracle_mod.hessian(st["x"], st["y"], st["z"], q, m, tr)
+    assert np.max(np.abs(D @ V - V * w2)) < 1e-11 * scale
+    assert np.max(np.abs(V.T @ V - np.eye(V.shape[0]))) < 1e-11
+    if kind != "cloud512":
+        assert np.min(w2) > 0
+    sim.close()
+
+
+def test_normal_modes_single_ion_and_rejections(torch_gpu, oracle_mod):
+    from paper_1907_10514_amd import LionError
+    from paper_1907_10514_amd import lion as L
+
+    tr = _pseudo(oracle_mod)
+    st = {"x": np.array([1e-6]), "y": np.array([2e-6]), "z": np.array([-1e-6]),
+          "vx": np.zeros(1), "vy": np.zeros(1), "vz": np.zeros(1)}
+    m = 17 * li.AMU
+    sim = _sim(np.array([m]), np.array([E]), "fp64", tr, st)
+    w2, _ = sim.normal_modes()
+    q_x, a_x = oracle_mod.mathieu_coefficients(tr.V0, tr.U0, m, E, tr.Omega, tr.R0, tr.Z0,
+                                               tr.kappa)
+    wr = oracle_mod.pseudopotential_frequency(q_x, a_x, tr.Omega)
+    wz = oracle_mod.pseudopotential_frequency(0.0, -2 * a_x, tr.Omega)
+    assert np.allclose(w2, np.sort([wz ** 2, wr ** 2, wr ** 2]), rtol=1e-12, atol=0)
+    sim.set_trap(tr.V0, tr.Omega, tr.U0, tr.R0, tr.Z0, tr.kappa)  # full rf: no static modes
+    with pytest.raises(LionError) as ei:
+        sim.normal_modes()
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    sim.set_pseudo_trap(tr.V0, tr.Omega, tr.U0, tr.R0, tr.Z0, tr.kappa)
+    import torch
+
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(LionError) as ei:
+        L.lion_normal_modes(sim.h, 1, small.data_ptr(), 256)
+    assert ei.value.code == L.LION_ERR_WORKSPACE
+    sim.close()
