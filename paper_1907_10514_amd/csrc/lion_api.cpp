@@ -158,6 +158,8 @@ void default_shape(lion_sim* s) {
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
     const int nb = lion::sym_tiles(n);
     ls.symmetric = (s->cfg.symmetric == 2 && nb <= lion::kMaxSymTiles && !s->has_bodies) ? 1 : 0;
+    // built-in pair-once variant: the fastest measured (4 for FP32 pairs, 2 for FP64)
+    ls.sym_variant = s->cfg.sym_variant > 0 ? s->cfg.sym_variant - 1 : (mixed ? 3 : 1);
     const int64_t n64 = round_up(n, 64);
     const int64_t blocks_x = (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane);
     int j;
@@ -1095,6 +1097,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->use_graph, {1, 2})) return fail(s, LION_ERR_ARG, "use_graph must be 1 or 2");
     if (!in(c->lds_sources, {1, 2})) return fail(s, LION_ERR_ARG, "lds_sources must be 1 or 2");
     if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");
+    if (!in(c->sym_variant, {1, 2, 3, 4, 5})) return fail(s, LION_ERR_ARG, "sym_variant must be 1..5");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 32768");
     if (c->symmetric == 2 && s->has_bodies)
@@ -1112,6 +1115,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.use_graph = c->use_graph > 0 ? c->use_graph : 1;
     s->cfg.lds_sources = c->lds_sources;
     s->cfg.symmetric = c->symmetric;
+    s->cfg.sym_variant = c->sym_variant;
     default_shape(s);
     return LION_OK;
 }
@@ -1126,6 +1130,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->use_graph = s->cfg.use_graph;
     c->lds_sources = s->ls.lds_sources ? 2 : 1;
     c->symmetric = s->ls.symmetric ? 2 : 1;
+    c->sym_variant = s->ls.sym_variant + 1;
     return LION_OK;
 }
 

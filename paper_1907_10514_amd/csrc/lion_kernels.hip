@@ -706,16 +706,60 @@ __device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int la
     return acc;
 }
 
-template <int L>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+// Target-side sums of the 4 targets per lane, added over the 4 waves in wave
+// order through LDS in two halves (targets 0-1, then 2-3) and stored to the
+// partial slot s.  red holds at least (kWaves - 1) * 3 * 64 * 2 doubles.
+__device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy)[4],
+                                                    double (&sz)[4], double* __restrict__ part,
+                                                    int s, int64_t n, int64_t n_pad,
+                                                    int64_t base, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* px = part + (int64_t)(3 * s) * n_pad;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (wave > 0) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                red[((wave - 1) * 3 + 0) * 128 + lane + 64 * k] = sx[2 * h + k];
+                red[((wave - 1) * 3 + 1) * 128 + lane + 64 * k] = sy[2 * h + k];
+                red[((wave - 1) * 3 + 2) * 128 + lane + 64 * k] = sz[2 * h + k];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                double x = sx[2 * h + k], y = sy[2 * h + k], z = sz[2 * h + k];
+#pragma unroll
+                for (int w = 0; w < kWaves - 1; ++w) {
+                    x += red[(w * 3 + 0) * 128 + lane + 64 * k];
+                    y += red[(w * 3 + 1) * 128 + lane + 64 * k];
+                    z += red[(w * 3 + 2) * 128 + lane + 64 * k];
+                }
+                const int64_t i = base + 64 * (2 * h + k);
+                if (i < n) {
+                    px[i] = x;
+                    px[n_pad + i] = y;
+                    px[2 * n_pad + i] = z;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// CH: sources per reaction-sum chunk (LDS per block grows with it); WPE: the
+// occupancy the register allocation aims at.
+template <int L, int CH, int WPE, int UNR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
                       double* __restrict__ part, int64_t* __restrict__ counter) {
-    constexpr int CH = 8;  // sources per reaction-sum chunk
     __shared__ float4 tile[2 * kSymTile];
     // per-wave reaction buffers, reused for the final target-side reduction
     constexpr int S = CH * 3 + 1;  // row stride of the lane-major reaction buffer
-    __shared__ __align__(16) double smem[(kWaves * 64 * S + 1) / 2];
-    static_assert((kWaves * 64 * S + 1) / 2 >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
+    constexpr int kRed = (kWaves - 1) * 3 * 64 * 2;
+    constexpr int kBuf = (kWaves * 64 * S + 1) / 2;
+    __shared__ __align__(16) double smem[kBuf > kRed ? kBuf : kRed];
     int a, b;
     sym_unit(nb, a, b);
     const bool diag = (a == b);
@@ -748,7 +792,7 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
         float fx[4], fy[4], fz[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
-#pragma unroll 2
+#pragma unroll UNR
         for (int uu = 0; uu < CH; ++uu) {
             const MixedSrc m = mine[s0 + uu];
             float tx = 0.0f, ty = 0.0f, tz = 0.0f;
@@ -788,9 +832,10 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const double tot = column_sum64<CH * 3, 2>(jb, lane);
-            const int col = lane >> 1;
-            if ((lane & 1) == 0 && col < CH * 3) {
+            const double tot = column_sum64<CH * 3, (CH * 3 * 4 <= 64 ? 4 : 2)>(jb, lane);
+            constexpr int P = CH * 3 * 4 <= 64 ? 4 : 2;
+            const int col = lane / P;
+            if ((lane % P) == 0 && col < CH * 3) {
                 const int uu = col / 3, c = col - 3 * uu;
                 const int64_t j = (int64_t)b * kSymTile + wave * 64 + s0 + uu;
                 part[((int64_t)a * 3 + c) * n_pad + j] = tot;
@@ -801,12 +846,13 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
         }
     }
     __syncthreads();  // every wave is done with its reaction buffer
-    reduce_store_in<4>(sx, sy, sz, part, b, n, n_pad, base, smem);
+    reduce_store_halves(sx, sy, sz, part, b, n, n_pad, base, smem);
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
-template <int DUMMY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// WPE: the occupancy the register allocation aims at; UNR: sources unrolled.
+template <int WPE, int UNR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
                     int nb, int64_t n_pad, double* __restrict__ part,
                     int64_t* __restrict__ counter) {
@@ -833,7 +879,7 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
     double* jb = smem + wave * 64 * S;
     const int64_t j0 = (int64_t)b * kSymTile + wave * 64;
     for (int s0 = 0; s0 < 64; s0 += CH) {
-#pragma unroll 2
+#pragma unroll UNR
         for (int uu = 0; uu < CH; ++uu) {
             const double4 p = src[j0 + s0 + uu];
             double tx = 0.0, ty = 0.0, tz = 0.0;
@@ -1712,9 +1758,41 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
         const int nb = sym_tiles(s.n);
         const unsigned units = (unsigned)(nb * (nb + 1) / 2);
         if (precision == 0) {
-            k_pair_f64_sym<0><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+            switch (ls.sym_variant) {
+                case 1:
+                    k_pair_f64_sym<4, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 2:
+                    k_pair_f64_sym<3, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 3:
+                    k_pair_f64_sym<4, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 4:
+                    k_pair_f64_sym<2, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                default:
+                    k_pair_f64_sym<3, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+            }
         } else {
-            k_pair_mixed_sym<8><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+            switch (ls.sym_variant) {
+                case 1:
+                    k_pair_mixed_sym<8, 4, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 2:
+                    k_pair_mixed_sym<8, 4, 6, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 3:
+                    k_pair_mixed_sym<8, 8, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 4:
+                    k_pair_mixed_sym<8, 4, 4, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                default:
+                    k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+            }
         }
         return hipGetLastError();
     }

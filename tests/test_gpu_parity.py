@@ -176,6 +176,23 @@ def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+def test_pair_once_variants(torch_gpu, oracle_mod, prec, variant):
+    """Every pair-once kernel variant the tuner may pick meets the bar, on full
+    and ragged tiles."""
+    for n in (255, 1000, 4097):
+        w = li.random_cloud(n, seed=500 + n, sigma=60e-6, light_fraction=0.2)
+        sim = _sim(w, prec, oracle_mod, symmetric=2, sym_variant=variant)
+        assert sim.config()["sym_variant"] == variant
+        tr = _oracle_trap(oracle_mod, w.traps[0])
+        r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+        sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+        err = _m1(sim.compute_accel(), r, sc)
+        assert err <= TOL[prec], (n, err)
+        sim.close()
+
+
 def test_pair_once_rejected_where_unsupported(torch_gpu, oracle_mod):
     from paper_1907_10514_amd import LionError
     from paper_1907_10514_amd import lion as L
