@@ -285,13 +285,15 @@ typedef struct {
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
                              LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 32768
                              (else LION_ERR_UNSUPPORTED)                                     */
-    int32_t sym_variant;  /* pair-once kernel variant, 1..5 (built-in: 4 for
-                             LION_MIXED_F64ACC, 2 for LION_FP64).  FP32 pairs: reaction sums
-                             per chunk of 8 or 4 sources, sources in flight, register budget:
-                             1: 8, two, 4 waves/SIMD; 2: 4, one, 5 waves; 3: 4, one,
-                             6 waves; 4: 8, one, 5-wave budget; 5: 4, one, 4 waves.
-                             FP64: 1: two sources in flight, 3 waves/SIMD; 2: one, 4 waves;
-                             3: one, 3 waves; 4: two, 4 waves (spills); 5: two, 2 waves    */
+    int32_t sym_variant;  /* pair-once kernel variant, 1..7 (built-in: 7 for
+                             LION_MIXED_F64ACC, 6 for LION_FP64).  FP32 pairs: reaction sums
+                             per chunk of 8 or 4 sources, sources unrolled, register budget,
+                             next source prefetched: 1: 8, two, 4 waves/SIMD; 2: 4, one,
+                             5 waves; 3: 4, one, 6 waves; 4: 8, one, 5-wave budget; 5: 4, one,
+                             4 waves; 6: 8, one, 5-wave budget, prefetch; 7: 8, two, 4 waves,
+                             prefetch.  FP64: 1: two sources unrolled, 3 waves/SIMD; 2: one,
+                             4 waves; 3: one, 3 waves; 4: two, 4 waves (spills); 5: two,
+                             2 waves; 6: one, 4 waves, prefetch; 7: two, 3 waves, prefetch   */
 } lion_kernel_config;
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);

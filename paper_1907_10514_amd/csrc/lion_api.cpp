@@ -158,8 +158,8 @@ void default_shape(lion_sim* s) {
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
     const int nb = lion::sym_tiles(n);
     ls.symmetric = (s->cfg.symmetric == 2 && nb <= lion::kMaxSymTiles && !s->has_bodies) ? 1 : 0;
-    // built-in pair-once variant: the fastest measured (4 for FP32 pairs, 2 for FP64)
-    ls.sym_variant = s->cfg.sym_variant > 0 ? s->cfg.sym_variant - 1 : (mixed ? 3 : 1);
+    // built-in pair-once variant: the fastest measured (7 for FP32 pairs, 6 for FP64)
+    ls.sym_variant = s->cfg.sym_variant > 0 ? s->cfg.sym_variant - 1 : (mixed ? 6 : 5);
     const int64_t n64 = round_up(n, 64);
     const int64_t blocks_x = (n + 64 * ls.i_per_lane - 1) / (64 * ls.i_per_lane);
     int j;
@@ -1097,7 +1097,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->use_graph, {1, 2})) return fail(s, LION_ERR_ARG, "use_graph must be 1 or 2");
     if (!in(c->lds_sources, {1, 2})) return fail(s, LION_ERR_ARG, "lds_sources must be 1 or 2");
     if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");
-    if (!in(c->sym_variant, {1, 2, 3, 4, 5})) return fail(s, LION_ERR_ARG, "sym_variant must be 1..5");
+    if (!in(c->sym_variant, {1, 2, 3, 4, 5, 6, 7})) return fail(s, LION_ERR_ARG, "sym_variant must be 1..7");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 32768");
     if (c->symmetric == 2 && s->has_bodies)

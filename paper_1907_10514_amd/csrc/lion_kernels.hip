@@ -750,7 +750,7 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
 
 // CH: sources per reaction-sum chunk (LDS per block grows with it); WPE: the
 // occupancy the register allocation aims at.
-template <int L, int CH, int WPE, int UNR>
+template <int L, int CH, int WPE, int UNR, bool PF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
                       double* __restrict__ part, int64_t* __restrict__ counter) {
@@ -788,13 +788,21 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
 #pragma unroll
     for (int k = 0; k < 4; ++k) sx[k] = sy[k] = sz[k] = 0.0;
     float* jb = reinterpret_cast<float*>(smem) + wave * 64 * S;
+    // with PF the next source is read from LDS while the current one is used
+    MixedSrc m_next = mine[0];
     for (int s0 = 0; s0 < 64; s0 += CH) {
         float fx[4], fy[4], fz[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
 #pragma unroll UNR
         for (int uu = 0; uu < CH; ++uu) {
-            const MixedSrc m = mine[s0 + uu];
+            MixedSrc m;
+            if constexpr (PF) {
+                m = m_next;
+                m_next = mine[min(s0 + uu + 1, 63)];
+            } else {
+                m = mine[s0 + uu];
+            }
             float tx = 0.0f, ty = 0.0f, tz = 0.0f;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -851,7 +859,7 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
 }
 
 // WPE: the occupancy the register allocation aims at; UNR: sources unrolled.
-template <int WPE, int UNR>
+template <int WPE, int UNR, bool PF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
                     int nb, int64_t n_pad, double* __restrict__ part,
@@ -878,10 +886,18 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
     }
     double* jb = smem + wave * 64 * S;
     const int64_t j0 = (int64_t)b * kSymTile + wave * 64;
+    // with PF the next source is loaded while the current one is used
+    double4 p_next = src[j0];
     for (int s0 = 0; s0 < 64; s0 += CH) {
 #pragma unroll UNR
         for (int uu = 0; uu < CH; ++uu) {
-            const double4 p = src[j0 + s0 + uu];
+            double4 p;
+            if constexpr (PF) {
+                p = p_next;
+                p_next = src[j0 + min(s0 + uu + 1, 63)];
+            } else {
+                p = src[j0 + s0 + uu];
+            }
             double tx = 0.0, ty = 0.0, tz = 0.0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -1771,6 +1787,12 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
                 case 4:
                     k_pair_f64_sym<2, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
                     break;
+                case 5:
+                    k_pair_f64_sym<4, 1, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 6:
+                    k_pair_f64_sym<3, 2, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
                 default:
                     k_pair_f64_sym<3, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
                     break;
@@ -1788,6 +1810,12 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
                     break;
                 case 4:
                     k_pair_mixed_sym<8, 4, 4, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 5:
+                    k_pair_mixed_sym<8, 8, 5, 1, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    break;
+                case 6:
+                    k_pair_mixed_sym<8, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
                     break;
                 default:
                     k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
