@@ -294,6 +294,8 @@ typedef struct {
                              prefetch.  FP64: 1: two sources unrolled, 3 waves/SIMD; 2: one,
                              4 waves; 3: one, 3 waves; 4: two, 4 waves (spills); 5: two,
                              2 waves; 6: one, 4 waves, prefetch; 7: two, 3 waves, prefetch   */
+    int32_t update_waves; /* waves that share the slice sums of 64 ions in the step
+                             epilogue: 4, 8 or 16 (built-in: 4)                               */
 } lion_kernel_config;
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);

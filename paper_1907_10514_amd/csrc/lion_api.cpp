@@ -173,6 +173,8 @@ void default_shape(lion_sim* s) {
     ls.jps = (int)round_up((n64 + j - 1) / j, 64);
     ls.j_split = (int)((n64 + ls.jps - 1) / ls.jps);  // slices that hold sources
     if (ls.symmetric) ls.j_split = nb;               // one partial per tile
+    // epilogue: 4 waves per 64 ions unless set (8 and 16 measured no faster)
+    ls.update_waves = s->cfg.update_waves > 0 ? s->cfg.update_waves : 4;
 }
 
 void clear_graphs(lion_sim* s) {
@@ -1098,6 +1100,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->lds_sources, {1, 2})) return fail(s, LION_ERR_ARG, "lds_sources must be 1 or 2");
     if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");
     if (!in(c->sym_variant, {1, 2, 3, 4, 5, 6, 7})) return fail(s, LION_ERR_ARG, "sym_variant must be 1..7");
+    if (!in(c->update_waves, {4, 8, 16})) return fail(s, LION_ERR_ARG, "update_waves must be 4, 8 or 16");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 32768");
     if (c->symmetric == 2 && s->has_bodies)
@@ -1116,6 +1119,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.lds_sources = c->lds_sources;
     s->cfg.symmetric = c->symmetric;
     s->cfg.sym_variant = c->sym_variant;
+    s->cfg.update_waves = c->update_waves;
     default_shape(s);
     return LION_OK;
 }
@@ -1131,6 +1135,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->lds_sources = s->ls.lds_sources ? 2 : 1;
     c->symmetric = s->ls.symmetric ? 2 : 1;
     c->sym_variant = s->ls.sym_variant + 1;
+    c->update_waves = s->ls.update_waves;
     return LION_OK;
 }
 

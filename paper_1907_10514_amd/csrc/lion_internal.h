@@ -186,7 +186,8 @@ struct LaunchShape {
     int batch_block;
     int lds_sources;  // FP32 pair kernels: 1 = sources staged in LDS, 0 = scalar loads
     int symmetric;    // 1 = each unordered pair once (tile pairs), 0 = all ordered pairs
-    int sym_variant;  // pair-once FP32 kernel: 0 = (8-source chunks, 4 waves/SIMD), 1..3 others
+    int sym_variant;  // pair-once kernel variant (0-based)
+    int update_waves; // waves per 64 ions in the step epilogue (4, 8 or 16)
 };
 
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the

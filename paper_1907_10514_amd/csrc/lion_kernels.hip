@@ -950,8 +950,8 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
 // ions with 4 waves: wave g adds the partial slots [g*per, (g+1)*per) in slot
 // order, wave 0 adds the four group sums in group order (deterministic for a
 // given number of slots), then applies the trap field and kick / damp / drift.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
+template <int MODE, int UW>
+__global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
                                                 MixedSrc* __restrict__ srcm,
                                                 double* __restrict__ vx, double* __restrict__ vy,
                                                 double* __restrict__ vz, double* __restrict__ ax,
@@ -968,10 +968,12 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
                                                 double* __restrict__ vacc,
                                                 double* __restrict__ vavg,
                                                 const int32_t* __restrict__ rb) {
-    __shared__ double red[kWaves - 1][3][64];
+    // UW waves per 64 ions: wave g sums a contiguous range of slices, then the
+    // wave sums are added in wave order
+    __shared__ double red[UW - 1][3][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-    const int per = (j_split + kWaves - 1) / kWaves;
+    const int per = (j_split + UW - 1) / UW;
     const int s0 = min(g * per, j_split), s1 = min(s0 + per, j_split);
     double Sx = 0.0, Sy = 0.0, Sz = 0.0;
     if (i < n) {
@@ -991,7 +993,7 @@ __global__ __launch_bounds__(256) void k_update(double4* __restrict__ src,
     __syncthreads();
     if (g > 0 || i >= n) return;
 #pragma unroll
-    for (int w = 0; w < kWaves - 1; ++w) {
+    for (int w = 0; w < UW - 1; ++w) {
         Sx += red[w][0][lane];
         Sy += red[w][1][lane];
         Sz += red[w][2][lane];
@@ -1845,31 +1847,36 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
     }
 }
 
+template <int MODE, int UW>
+void update_launch(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
+                   const int64_t* ctr, hipStream_t st) {
+    const unsigned g = blocks_for(s.n, 64);  // 64 ions per block of UW waves
+    k_update<MODE, UW><<<g, 64 * UW, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
+                                              s.qm, s.qe, s.mass, s.species, s.part, ls.j_split,
+                                              s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc,
+                                              s.vavg, s.rb);
+}
+
+template <int MODE>
+void update_dispatch(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
+                     const int64_t* ctr, hipStream_t st) {
+    if (ls.update_waves == 16)
+        update_launch<MODE, 16>(s, ls, scale, srcm, ctr, st);
+    else if (ls.update_waves == 8)
+        update_launch<MODE, 8>(s, ls, scale, srcm, ctr, st);
+    else
+        update_launch<MODE, 4>(s, ls, scale, srcm, ctr, st);
+}
+
 hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls, int mode,
                          bool use_counter, hipStream_t st) {
     const double scale = precision == 0 ? 1.0 : kMixedFieldScale;
     const int64_t* ctr = use_counter ? s.counter : nullptr;
-    const unsigned g = blocks_for(s.n, 64);  // 64 ions per block of 4 waves
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
     switch (mode) {
-        case kModeAccel:
-            k_update<kModeAccel><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
-                                                    s.az, s.qm, s.qe, s.mass, s.species, s.part,
-                                                    ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                    s.cool, ctr, s.vacc, s.vavg, s.rb);
-            break;
-        case kModeEnd:
-            k_update<kModeEnd><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
-                                                  s.az, s.qm, s.qe, s.mass, s.species, s.part,
-                                                  ls.j_split, s.n, s.n_pad, scale, s.traps,
-                                                  s.cool, ctr, s.vacc, s.vavg, s.rb);
-            break;
-        default:
-            k_update<kModeEndDrift><<<g, 256, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax,
-                                                       s.ay, s.az, s.qm, s.qe, s.mass, s.species,
-                                                       s.part, ls.j_split, s.n, s.n_pad, scale,
-                                                       s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
-            break;
+        case kModeAccel: update_dispatch<kModeAccel>(s, ls, scale, srcm, ctr, st); break;
+        case kModeEnd: update_dispatch<kModeEnd>(s, ls, scale, srcm, ctr, st); break;
+        default: update_dispatch<kModeEndDrift>(s, ls, scale, srcm, ctr, st); break;
     }
     return hipGetLastError();
 }

@@ -95,6 +95,7 @@ def test_accel_parity_multiple_charges(torch_gpu, oracle_mod):
     ("mixed", [dict(i_per_lane=i, j_split=j, flush_len=l) for i in (1, 2, 4) for j in (1, 9, 64)
                for l in (4, 8, 16)]),
     ("mixed_kahan", [dict(i_per_lane=i, j_split=j) for i in (1, 2, 4) for j in (1, 64)]),
+    ("fp64", [dict(j_split=64, update_waves=u) for u in (4, 8, 16)]),
 ])
 def test_accel_parity_launch_shapes(torch_gpu, oracle_mod, prec, cfgs):
     """Every launch shape the tuner may pick gives the same forces within the bar."""
