@@ -225,6 +225,38 @@ def time_clusters(torch, precision, steps, warmup, reps):
                 finite=finite, launch=cfg)
 
 
+def time_small(torch, w, steps, oracle_steps):
+    """The 8-ion and 1024-ion FP64 configurations: GPU steps/s and pairs/s over
+    `steps` steps, beside the oracle on `oracle_steps` steps of the same input
+    (the whole run for 8 ions; a bounded sample for 1024)."""
+    import oracle
+
+    from paper_1907_10514_amd import runner
+
+    spec = w.traps[0]
+    sim = runner.simulation_for(w, precision="fp64")
+    sim.step(min(steps, 200), spec.dt)
+    sync(torch)
+    t0 = time.perf_counter()
+    sim.step(steps, spec.dt)
+    sync(torch)
+    el = time.perf_counter() - t0
+    finite = sim.check_finite() == 0
+    sim.close()
+    V0, U0 = oracle.voltages_for(spec.q_x, spec.a_x, spec.ref_mass, spec.ref_charge, spec.omega,
+                                 spec.r0, spec.z0, spec.kappa)
+    tr = oracle.Trap(V0=V0, Omega=spec.omega, U0=U0, R0=spec.r0, Z0=spec.z0, kappa=spec.kappa)
+    t0 = time.perf_counter()
+    oracle.step(w.state(), w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, oracle_steps)
+    oel = time.perf_counter() - t0
+    pairs = w.n * (w.n - 1)
+    return dict(n_ions=w.n, precision="fp64", steps=steps, steps_per_s=steps / el,
+                pairs_per_s=pairs * steps / el, finite=finite,
+                oracle=dict(steps=oracle_steps, steps_per_s=oracle_steps / oel,
+                            pairs_per_s=pairs * (oracle_steps + 1) / oel,
+                            cores=oracle.num_threads()))
+
+
 def cpu_baseline(w, seconds):
     """The FP64 oracle on the host cores, on a bounded number of steps of the
     same workload."""
@@ -308,6 +340,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-clusters", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 8-ion and 1024-ion configurations")
     ap.add_argument("--cluster-steps", type=int, default=200)
     ap.add_argument("--precisions", default="fp64,mixed,mixed_kahan")
     ap.add_argument("--profile-pass", action="store_true",
@@ -393,9 +427,9 @@ def main():
             out["batch512"][p] = time_batch(torch, p, args.batch_steps, 100, args.seq_steps)
             log(f"[bench] batch512 {p}: {out['batch512'][p]['pairs_per_s']:.4e} pairs/s, "
                 f"x{out['batch512'][p]['speedup_vs_sequential']:.1f} vs one-by-one")
-        if "mixed" in out["batch512"] and "fp64" in res:
-            out["batch512"]["speedup_batched_mixed_over_single_fp64_n16384"] = (
-                out["batch512"]["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"])
+        if "mixed" in out["batch512"] and "fp64" in out["batch512"]:
+            out["batch512"]["speedup_mixed_over_fp64"] = (
+                out["batch512"]["mixed"]["pairs_per_s"] / out["batch512"]["fp64"]["pairs_per_s"])
     if not args.no_clusters:
         out["clusters65536"] = {}
         for p in ("mixed", "fp64"):
@@ -408,6 +442,14 @@ def main():
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if not args.no_small:
+            out["small_configs"] = {}
+            for wk, steps, osteps in ((li.crystal8(), 20000, 20000), (li.crystal1024(), 5000, 2000)):
+                log(f"[bench] {wk.name}: {steps} GPU steps, {osteps} oracle steps")
+                out["small_configs"][wk.name] = time_small(torch, wk, steps, osteps)
+                r = out["small_configs"][wk.name]
+                log(f"[bench] {wk.name}: GPU {r['steps_per_s']:.0f} steps/s, "
+                    f"oracle {r['oracle']['steps_per_s']:.1f} steps/s")
     out["device"] = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
                      "cu": props.multi_processor_count,
                      "clocks_under_load": gpu_clocks(torch, w, head),

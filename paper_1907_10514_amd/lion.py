@@ -383,7 +383,8 @@ class Simulation:
             from . import tune
 
             arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "")
-            cfg = tune.lookup(arch, self.n, self.precision, self.batched)
+            n_traps = len(self.n_per_trap) if self.batched else 1
+            cfg = tune.lookup(arch, self.n, self.precision, self.batched, n_traps)
             if cfg:
                 try:
                     self.set_config(**cfg)
