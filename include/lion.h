@@ -296,7 +296,15 @@ typedef struct {
                              2 waves; 6: one, 4 waves, prefetch; 7: two, 3 waves, prefetch   */
     int32_t update_waves; /* waves that share the slice sums of 64 ions in the step
                              epilogue: 4, 8 or 16 (built-in: 4)                               */
+    int32_t small_trap;   /* single trap: 1: always the multi-workgroup kernels; 2: step the
+                             trap inside one workgroup, many steps per launch (the batched
+                             kernel with one trap; N <= 1024, no body exclusion or rigid
+                             bodies, else the multi-workgroup kernels run).  Built-in: 2
+                             for N <= LION_SMALL_TRAP_IONS, else 1                           */
 } lion_kernel_config;
+
+/* Ion count up to which a single trap is stepped inside one workgroup by default. */
+#define LION_SMALL_TRAP_IONS 128
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);
 int lion_get_kernel_config(const lion_sim *sim, lion_kernel_config *cfg);

@@ -175,6 +175,11 @@ void default_shape(lion_sim* s) {
     if (ls.symmetric) ls.j_split = nb;               // one partial per tile
     // epilogue: 4 waves per 64 ions unless set (8 and 16 measured no faster)
     ls.update_waves = s->cfg.update_waves > 0 ? s->cfg.update_waves : 4;
+    ls.small_path = s->cfg.small_trap > 0 ? (s->cfg.small_trap == 2 ? 1 : 0)
+                                          : (n <= LION_SMALL_TRAP_IONS ? 1 : 0);
+    // one-workgroup stepping of a single trap: 256 threads up to 64 ions, then 1024
+    if (!s->batched && ls.small_path && s->cfg.batch_block <= 0)
+        ls.batch_block = n <= 64 ? 256 : 1024;
 }
 
 void clear_graphs(lion_sim* s) {
@@ -247,6 +252,13 @@ hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
         e = lion::launch_batch(s->d, s->precision, s->n_traps, s->max_trap, s->ls, (int)L, 0, st);
         if (e != hipSuccess) return e;
         return lion::launch_counter_add(s->d, L, st);
+    }
+    if (s->ls.small_path && s->n <= kMaxTrap && !s->has_bodies && s->d.nbodies == 0) {
+        // the whole trap inside one workgroup, L steps per launch
+        e = lion::launch_batch(s->d, s->precision, 1, (int)s->n, s->ls, (int)L, 0, st);
+        if (e == hipSuccess) e = lion::launch_counter_add(s->d, L, st);
+        if (e == hipSuccess && s->d.srcm) e = lion::launch_pack_mixed(s->d, st);
+        return e;
     }
     const bool rigid = s->d.nbodies > 0;
     if (rigid) {
@@ -1101,6 +1113,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");
     if (!in(c->sym_variant, {1, 2, 3, 4, 5, 6, 7})) return fail(s, LION_ERR_ARG, "sym_variant must be 1..7");
     if (!in(c->update_waves, {4, 8, 16})) return fail(s, LION_ERR_ARG, "update_waves must be 4, 8 or 16");
+    if (!in(c->small_trap, {1, 2})) return fail(s, LION_ERR_ARG, "small_trap must be 1 or 2");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 32768");
     if (c->symmetric == 2 && s->has_bodies)
@@ -1120,6 +1133,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.symmetric = c->symmetric;
     s->cfg.sym_variant = c->sym_variant;
     s->cfg.update_waves = c->update_waves;
+    s->cfg.small_trap = c->small_trap;
     default_shape(s);
     return LION_OK;
 }
@@ -1136,6 +1150,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->symmetric = s->ls.symmetric ? 2 : 1;
     c->sym_variant = s->ls.sym_variant + 1;
     c->update_waves = s->ls.update_waves;
+    c->small_trap = s->ls.small_path ? 2 : 1;
     return LION_OK;
 }
 

@@ -188,6 +188,7 @@ struct LaunchShape {
     int symmetric;    // 1 = each unordered pair once (tile pairs), 0 = all ordered pairs
     int sym_variant;  // pair-once kernel variant (0-based)
     int update_waves; // waves per 64 ions in the step epilogue (4, 8 or 16)
+    int small_path;   // single trap stepped by the one-workgroup kernel (k_batch, one trap)
 };
 
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the

@@ -407,6 +407,56 @@ def test_batch_equals_single_trap_path(torch_gpu, oracle_mod):
         assert np.max(np.abs(out[0][k] - out[1][k])) < 1e-10 * ext
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("n", [1, 8, 100, 128, 300])
+def test_small_trap_path_equals_multi_workgroup_path(torch_gpu, oracle_mod, n, prec, tol):
+    """A single trap stepped inside one workgroup (many steps per launch) and by
+    the multi-workgroup kernels gives the same trajectory to rounding, with a
+    beam, a bath and the velocity time average switched on; force evaluations
+    after the run see the updated positions in both paths."""
+    w = li.random_cloud(n, seed=600 + n, sigma=20e-6 * max(1, n / 8) ** (1 / 3),
+                        light_fraction=0.3)
+    sp = (w.mass < 30 * li.AMU).astype(np.int32)
+    out = []
+    for small in (1, 2):
+        sim = _sim(w, prec, oracle_mod, small_trap=small, chunk_steps=40)
+        assert sim.config()["small_trap"] == small
+        sim.set_species(sp)
+        sim.set_beam(0, (0.3, 0.2, 1.0), 2e5, species=0)
+        sim.set_bath(0, 1e-3, 50e-6, 11, species=1)
+        sim.set_time_average(20)
+        sim.step(150, w.traps[0].dt)
+        st, t = sim.get_state()
+        avg, end = sim.time_average()
+        out.append((st, t, avg, end, np.array(sim.compute_accel())))
+        sim.close()
+    (a, ta, va, ea, fa), (b, tb, vb, eb, fb) = out
+    assert ta == tb and ea == eb == 140
+    ext = max(np.max(np.abs(w.x)), 1e-6)
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(a[k] - b[k])) < tol * 1e3 * ext, k
+    vs = max(np.max(np.abs(a["vx"])), 1e-3)
+    for k in ("vx", "vy", "vz"):
+        assert np.max(np.abs(a[k] - b[k])) < tol * 1e3 * vs, k
+    assert np.max(np.abs(fa - fb)) <= tol * 1e3 * np.max(np.abs(fa))
+
+
+def test_crystal8_full_run_matches_oracle_on_both_paths(torch_gpu, oracle_mod):
+    w = li.crystal8()
+    spec = w.traps[0]
+    ref = oracle_mod.step(w.state(), w.charge, w.mass, _oracle_trap(oracle_mod, spec),
+                          spec.gamma, 0.0, spec.dt, w.nsteps)
+    ext = np.max(np.abs(ref["z"]))
+    for small in (1, 2):
+        sim = _sim(w, "fp64", oracle_mod, small_trap=small)
+        sim.step(w.nsteps, spec.dt)
+        st, t = sim.get_state()
+        assert t == ref["t"]
+        for k in ("x", "y", "z"):
+            assert np.max(np.abs(st[k] - ref[k])) < 1e-9 * ext, (small, k)
+        sim.close()
+
+
 def test_error_paths_on_gpu(torch_gpu, oracle_mod):
     from paper_1907_10514_amd import LionError, Simulation
     from paper_1907_10514_amd import lion as L
