@@ -224,6 +224,13 @@ int upload_cooling(lion_sim* s, double dt) {
     C.step_base = s->steps_done;
     C.avg_window = s->avg_window;
     C.avg_origin = s->avg_origin;
+    // captured graphs hold the kernels built with or without these features
+    const bool on = C.nbeams > 0 || C.nbaths > 0 || C.avg_window > 0;
+    if (on != s->ls.cool_on) {
+        LION_HIP(s, hipStreamSynchronize(s->stream));  // no launch of a graph still pending
+        clear_graphs(s);
+        s->ls.cool_on = on;
+    }
     LION_HIP(s, hipMemcpyAsync(s->d.cool, &s->cool, sizeof(lion::CoolDev), hipMemcpyHostToDevice,
                                s->stream));
     return LION_OK;
@@ -266,7 +273,7 @@ hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
         e = lion::launch_rigid_wrench(s->d, false, st);
         if (e != hipSuccess) return e;
     }
-    e = lion::launch_drift(s->d, st);
+    e = lion::launch_drift(s->d, s->ls.cool_on, st);
     if (e != hipSuccess) return e;
     if (rigid) {
         e = lion::launch_rigid_drift(s->d, st);

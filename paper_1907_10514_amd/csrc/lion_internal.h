@@ -189,6 +189,7 @@ struct LaunchShape {
     int sym_variant;  // pair-once kernel variant (0-based)
     int update_waves; // waves per 64 ions in the step epilogue (4, 8 or 16)
     int small_path;   // single trap stepped by the one-workgroup kernel (k_batch, one trap)
+    bool cool_on;     // a beam, bath or time average is on: the kernels built with them run
 };
 
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the
@@ -197,7 +198,7 @@ inline int sym_tiles(int64_t n) { return (int)((n + 255) / 256); }
 constexpr int kMaxSymTiles = 128;
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
-hipError_t launch_drift(const DevState& s, hipStream_t st);
+hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st);
 hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, bool count_step,
                        hipStream_t st);
 hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls, int mode,

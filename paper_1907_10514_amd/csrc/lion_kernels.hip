@@ -225,8 +225,41 @@ __device__ __forceinline__ void bath_normals(uint64_t seed, int64_t ion, int64_t
     z2 = r2 * cos(2.0 * kPi * u4);
 }
 
+// The cooling and averaging switches, read once per launch: they cannot change
+// during one, and re-reading them after every barrier of an in-kernel step
+// loop costs more than the step's arithmetic for small traps.
+struct CoolRef {
+    const CoolDev* C;
+    int nb, nt, W;
+    int64_t origin;
+};
+
+// X = false: a kernel built with beams, baths and time averages compiled out
+// (all switches constant zero), launched while none of them is on.
+template <bool X>
+__device__ __forceinline__ CoolRef cool_switches(const CoolDev* __restrict__ C);
+
+__device__ __forceinline__ CoolRef load_cool(const CoolDev* __restrict__ C) {
+    CoolRef r;
+    r.C = C;
+    r.nb = C ? C->nbeams : 0;
+    r.nt = C ? C->nbaths : 0;
+    r.W = C ? C->avg_window : 0;
+    r.origin = C ? C->avg_origin : 0;
+    return r;
+}
+
+template <bool X>
+__device__ __forceinline__ CoolRef cool_switches(const CoolDev* __restrict__ C) {
+    if constexpr (X) {
+        return load_cool(C);
+    } else {
+        return CoolRef{nullptr, 0, 0, 0, 0};
+    }
+}
+
 // Velocity half-step: isotropic damping f, then beams, then baths (index order).
-__device__ __forceinline__ void velocity_half(const CoolDev* __restrict__ C, int64_t ion,
+__device__ __forceinline__ void velocity_half(const CoolRef& R, int64_t ion,
                                               int32_t species, double mass, double f,
                                               int64_t step, int half, double& u, double& v,
                                               double& w) {
@@ -234,8 +267,9 @@ __device__ __forceinline__ void velocity_half(const CoolDev* __restrict__ C, int
     u = f * u;
     v = f * v;
     w = f * w;
-    if (!C) return;
-    const int nb = C->nbeams, nt = C->nbaths;
+    const int nb = R.nb, nt = R.nt;
+    if (nb == 0 && nt == 0) return;
+    const CoolDev* __restrict__ C = R.C;
     for (int b = 0; b < nb; ++b) {
         const BeamDev B = C->beams[b];
         if (!B.on || (B.species >= 0 && B.species != species)) continue;
@@ -260,15 +294,15 @@ __device__ __forceinline__ void velocity_half(const CoolDev* __restrict__ C, int
 // each step is added to the open window's sums; the step that closes a window
 // publishes sums / W and restarts the sums.  `step` is the run-wide number of
 // the step just completed.
-__device__ __forceinline__ void time_average(const CoolDev* __restrict__ C, int64_t i,
+__device__ __forceinline__ void time_average(const CoolRef& R, int64_t i,
                                              int64_t n_pad, int64_t step, double* __restrict__ acc,
                                              double* __restrict__ avg, double u, double v,
                                              double w) {
 #pragma clang fp contract(off)
-    const int W = C->avg_window;
+    const int W = R.W;
     if (W <= 0) return;
     const double sx = acc[i] + u, sy = acc[n_pad + i] + v, sz = acc[2 * n_pad + i] + w;
-    if ((step - C->avg_origin) % W == 0) {
+    if ((step - R.origin) % W == 0) {
         avg[i] = sx / (double)W;
         avg[n_pad + i] = sy / (double)W;
         avg[2 * n_pad + i] = sz / (double)W;
@@ -284,7 +318,7 @@ __device__ __forceinline__ void time_average(const CoolDev* __restrict__ C, int6
 
 // First half of a step: velocity half-step (damping, beams, baths), half kick,
 // drift.  `step` numbers steps from 1 over the whole run.
-__device__ __forceinline__ void half_step_drift(const TrapDev& T, const CoolDev* __restrict__ C,
+__device__ __forceinline__ void half_step_drift(const TrapDev& T, const CoolRef& C,
                                                 int64_t ion, int32_t species, double mass,
                                                 int64_t step, double& x, double& y, double& z,
                                                 double& vx, double& vy, double& vz, double ax,
@@ -300,7 +334,7 @@ __device__ __forceinline__ void half_step_drift(const TrapDev& T, const CoolDev*
 }
 
 // Second half of a step: half kick with the new acceleration, velocity half-step.
-__device__ __forceinline__ void end_kick(const TrapDev& T, const CoolDev* __restrict__ C,
+__device__ __forceinline__ void end_kick(const TrapDev& T, const CoolRef& C,
                                          int64_t ion, int32_t species, double mass, int64_t step,
                                          double& vx, double& vy, double& vz, double ax, double ay,
                                          double az) {
@@ -313,6 +347,7 @@ __device__ __forceinline__ void end_kick(const TrapDev& T, const CoolDev* __rest
 
 // ------------------------------------------------------------------ kernels
 
+template <bool X>
 __global__ __launch_bounds__(256) void k_drift(double4* __restrict__ src,
                                                MixedSrc* __restrict__ srcm,
                                                double* __restrict__ vx, double* __restrict__ vy,
@@ -334,7 +369,8 @@ __global__ __launch_bounds__(256) void k_drift(double4* __restrict__ src,
     const int64_t step = cool->step_base + *counter + 1;
     double4 p = src[i];
     double u = vx[i], v = vy[i], w = vz[i];
-    half_step_drift(T, cool, i, species[i], mass[i], step, p.x, p.y, p.z, u, v, w, ax[i], ay[i],
+    half_step_drift(T, cool_switches<X>(cool), i, species[i], mass[i], step, p.x, p.y, p.z, u,
+                    v, w, ax[i], ay[i],
                     az[i]);
     src[i] = p;
     vx[i] = u;
@@ -950,7 +986,7 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
 // ions with 4 waves: wave g adds the partial slots [g*per, (g+1)*per) in slot
 // order, wave 0 adds the four group sums in group order (deterministic for a
 // given number of slots), then applies the trap field and kick / damp / drift.
-template <int MODE, int UW>
+template <int MODE, int UW, bool X>
 __global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
                                                 MixedSrc* __restrict__ srcm,
                                                 double* __restrict__ vx, double* __restrict__ vy,
@@ -1015,10 +1051,11 @@ __global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
     const int32_t sp = species[i];
     const double mi = mass[i];
     double u = vx[i], v = vy[i], w = vz[i];
-    end_kick(T, cool, i, sp, mi, step, u, v, w, a_x, a_y, a_z);
-    time_average(cool, i, n_pad, step, vacc, vavg, u, v, w);
+    const CoolRef cr = cool_switches<X>(cool);
+    end_kick(T, cr, i, sp, mi, step, u, v, w, a_x, a_y, a_z);
+    time_average(cr, i, n_pad, step, vacc, vavg, u, v, w);
     if (MODE == kModeEndDrift) {
-        half_step_drift(T, cool, i, sp, mi, step + 1, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
+        half_step_drift(T, cr, i, sp, mi, step + 1, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
         src[i] = p;
         if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
     }
@@ -1092,7 +1129,7 @@ struct BatchSrc<2> {
     using T = MixedSrc;
 };
 
-template <int PREC, int BLOCK>
+template <int PREC, int BLOCK, bool X>
 __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  double* __restrict__ vx,
                                                  double* __restrict__ vy,
@@ -1173,6 +1210,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
 
     const int total = accel_only ? 1 : nsteps;
     const int64_t step0 = cool->step_base + k0 + 1;  // run-wide number of the first step
+    const CoolRef cr = cool_switches<X>(cool);
     for (int step = 0; step < total; ++step) {
         // first half of the step; positions into the LDS source stream
 #pragma unroll
@@ -1180,7 +1218,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             const int il = slot + IS * k;
             if (owner && il < m) {
                 if (!accel_only)
-                    half_step_drift(T, cool, o + il, sp[k], m_i[k], step0 + step, x[k], y[k],
+                    half_step_drift(T, cr, o + il, sp[k], m_i[k], step0 + step, x[k], y[k],
                                     z[k], u[k], v[k], w[k], a0[k], a1[k], a2[k]);
                 if constexpr (PREC == 0) {
                     lds[il] = make_double4(x[k], y[k], z[k], 1.5 * q_e[k]);
@@ -1273,9 +1311,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                 trap_accel(T, t, q_m[k], x[k], y[k], z[k], Sx[k], Sy[k], Sz[k], a0[k], a1[k],
                            a2[k]);
                 if (!accel_only) {
-                    end_kick(T, cool, o + il, sp[k], m_i[k], step0 + step, u[k], v[k], w[k],
+                    end_kick(T, cr, o + il, sp[k], m_i[k], step0 + step, u[k], v[k], w[k],
                              a0[k], a1[k], a2[k]);
-                    time_average(cool, o + il, n_pad, step0 + step, vacc, vavg, u[k], v[k],
+                    time_average(cr, o + il, n_pad, step0 + step, vacc, vavg, u[k], v[k],
                                  w[k]);
                 }
             }
@@ -1451,7 +1489,7 @@ __global__ __launch_bounds__(256) void k_rigid_wrench(RigidDev* __restrict__ bod
         vx[i] = u;
         vy[i] = v;
         vz[i] = w;
-        time_average(cool, i, n_pad, step, vacc, vavg, u, v, w);
+        time_average(load_cool(cool), i, n_pad, step, vacc, vavg, u, v, w);
     }
 }
 
@@ -1734,32 +1772,45 @@ hipError_t pair_mixed_dispatch_l(const DevState& s, const LaunchShape& ls, int64
     }
 }
 
-template <int PREC, int BLOCK>
+template <int PREC, int BLOCK, bool X>
 hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only,
                         hipStream_t st) {
-    k_batch<PREC, BLOCK><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
-                                                    s.qm, s.qe, s.mass, s.species, s.traps,
-                                                    s.cool, s.offsets, s.order, s.counter,
-                                                    s.vacc, s.vavg, s.n_pad, nsteps, accel_only);
+    k_batch<PREC, BLOCK, X><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay,
+                                                       s.az, s.qm, s.qe, s.mass, s.species,
+                                                       s.traps, s.cool, s.offsets, s.order,
+                                                       s.counter, s.vacc, s.vavg, s.n_pad,
+                                                       nsteps, accel_only);
     return hipGetLastError();
+}
+
+template <int PREC, bool X>
+hipError_t batch_dispatch_x(const DevState& s, int n_traps, int block, int nsteps,
+                            int accel_only, hipStream_t st) {
+    switch (block) {
+        case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, st);
+        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, st);
+        default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, st);
+    }
 }
 
 template <int PREC>
 hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps, int accel_only,
-                          hipStream_t st) {
-    switch (block) {
-        case 512: return batch_launch<PREC, 512>(s, n_traps, nsteps, accel_only, st);
-        case 1024: return batch_launch<PREC, 1024>(s, n_traps, nsteps, accel_only, st);
-        default: return batch_launch<PREC, 256>(s, n_traps, nsteps, accel_only, st);
-    }
+                          bool cool_on, hipStream_t st) {
+    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, block, nsteps, accel_only, st)
+                   : batch_dispatch_x<PREC, false>(s, n_traps, block, nsteps, accel_only, st);
 }
 
 }  // namespace
 
-hipError_t launch_drift(const DevState& s, hipStream_t st) {
-    k_drift<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay,
-                                                  s.az, s.qe, s.mass, s.species, s.traps, s.cool,
-                                                  s.counter, s.rb, s.n);
+hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st) {
+    if (cool_on)
+        k_drift<true><<<blocks_for(s.n, 256), 256, 0, st>>>(
+            s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qe, s.mass, s.species, s.traps,
+            s.cool, s.counter, s.rb, s.n);
+    else
+        k_drift<false><<<blocks_for(s.n, 256), 256, 0, st>>>(
+            s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qe, s.mass, s.species, s.traps,
+            s.cool, s.counter, s.rb, s.n);
     return hipGetLastError();
 }
 
@@ -1851,10 +1902,14 @@ template <int MODE, int UW>
 void update_launch(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
                    const int64_t* ctr, hipStream_t st) {
     const unsigned g = blocks_for(s.n, 64);  // 64 ions per block of UW waves
-    k_update<MODE, UW><<<g, 64 * UW, 0, st>>>(s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
-                                              s.qm, s.qe, s.mass, s.species, s.part, ls.j_split,
-                                              s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc,
-                                              s.vavg, s.rb);
+    if (ls.cool_on && MODE != kModeAccel)
+        k_update<MODE, UW, true><<<g, 64 * UW, 0, st>>>(
+            s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm, s.qe, s.mass, s.species,
+            s.part, ls.j_split, s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
+    else
+        k_update<MODE, UW, false><<<g, 64 * UW, 0, st>>>(
+            s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm, s.qe, s.mass, s.species,
+            s.part, ls.j_split, s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
 }
 
 template <int MODE>
@@ -1936,9 +1991,9 @@ hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_t
                         const LaunchShape& ls, int nsteps, int, hipStream_t st) {
     (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, st);
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, st);
     }
 }
 
@@ -1946,9 +2001,9 @@ hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int
                               const LaunchShape& ls, hipStream_t st) {
     (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, st);
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, false, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, false, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, false, st);
     }
 }
 
