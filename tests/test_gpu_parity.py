@@ -573,3 +573,60 @@ def test_bodies_rejected_where_unsupported(torch_gpu, oracle_mod):
         bs.set_bodies(np.zeros(b.n, dtype=np.int32))
     assert ei.value.code == L.LION_ERR_UNSUPPORTED
     bs.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batch512_full_size_sampled(torch_gpu, oracle_mod, prec):
+    """The full 512-trap batch (130408 ions) in the benchmarked launch shape:
+    forces and a 20-step run of 12 sampled traps (including the largest)
+    against the oracle."""
+    from paper_1907_10514_amd import runner
+
+    w = li.batch512(nsteps=0)
+    sim = runner.simulation_for(w, precision=prec)
+    a = sim.compute_accel()
+    sizes = np.diff(w.offsets)
+    rng = np.random.default_rng(7)
+    pick = sorted(set([int(np.argmax(sizes))] + list(rng.choice(w.n_traps, 11, replace=False))))
+    traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
+    for k in pick:
+        o, e = int(w.offsets[k]), int(w.offsets[k + 1])
+        r = oracle_mod.accel(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e], traps[k],
+                             0.0)
+        sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e],
+                                    traps[k], 0.0)
+        assert _m1([c[o:e] for c in a], r, sc) <= TOL[prec], k
+    dts = np.array([s.dt for s in w.traps])
+    sim.step(20, dts)
+    st, _ = sim.get_state()
+    for k in pick:
+        o, e = int(w.offsets[k]), int(w.offsets[k + 1])
+        sub = {c: v[o:e] for c, v in w.state().items()}
+        ref = oracle_mod.step(sub, w.charge[o:e], w.mass[o:e], traps[k], w.traps[k].gamma, 0.0,
+                              dts[k], 20)
+        disp = np.max(np.abs(ref["x"] - sub["x"])) + 1e-12
+        tol = 1e-9 if prec == "fp64" else 1e-4
+        for c in ("x", "y", "z"):
+            assert np.max(np.abs(st[c][o:e] - ref[c])) < tol * disp, (k, c)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_mixed16384_full_size_steps(torch_gpu, oracle_mod, prec, tol):
+    """Ten steps of the full 16384-ion cloud in the benchmarked launch shape
+    against the oracle, every ion compared."""
+    from paper_1907_10514_amd import runner
+
+    w = li.mixed16384()
+    spec = w.traps[0]
+    sim = runner.simulation_for(w, precision=prec)
+    sim.step(10, spec.dt)
+    st, _ = sim.get_state()
+    ref = oracle_mod.step(w.state(), w.charge, w.mass, _oracle_trap(oracle_mod, spec), spec.gamma,
+                          0.0, spec.dt, 10)
+    disp = np.max(np.abs(ref["x"] - w.x))
+    err = max(np.max(np.abs(st[k] - ref[k])) for k in ("x", "y", "z"))
+    print(f"{prec}: max |dx| {err:.2e} after 10 steps (displacement {disp:.2e}), "
+          f"config {sim.config()}")
+    assert err < tol * disp
+    sim.close()
