@@ -38,6 +38,7 @@ struct lion_sim {
     bool state_set = false;
     bool has_bodies = false;
     int64_t steps_done = 0;           // run-wide step count (numbers the bath draws)
+    double uniform_q = 0.0;           // common charge (units of e) of all ions, 0 if they differ
     bool rigid_on = false;            // rigid-body integration of the body groups
     std::vector<int32_t> rigid_ids;   // [n] body id per ion while rigid_on
     size_t rigid_off[5] = {0, 0, 0, 0, 0};  // workspace offsets: bodies, rb, dbody, members, start
@@ -175,6 +176,7 @@ void default_shape(lion_sim* s) {
     if (ls.symmetric) ls.j_split = nb;               // one partial per tile
     // epilogue: 4 waves per 64 ions unless set (8 and 16 measured no faster)
     ls.update_waves = s->cfg.update_waves > 0 ? s->cfg.update_waves : 4;
+    ls.uniform_q = s->uniform_q;
     ls.small_path = s->cfg.small_trap > 0 ? (s->cfg.small_trap == 2 ? 1 : 0)
                                           : (n <= LION_SMALL_TRAP_IONS ? 1 : 0);
     // one-workgroup stepping of a single trap: 256 threads up to 64 ions, then 1024
@@ -481,6 +483,12 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     }
     s->mass.assign(masses, masses + n);
     s->charge.assign(charges, charges + n);
+    {
+        bool same = true;
+        for (int64_t i = 1; i < n && same; ++i) same = qe[i] == qe[0];
+        s->uniform_q = same ? qe[0] : 0.0;
+        s->ls.uniform_q = s->uniform_q;
+    }
     s->traps.assign(n_traps, TrapDev{0, 1.0, 0, 1.0, 0, 0, 0, 0});
     s->t_now.assign(n_traps, 0.0);
     std::vector<int32_t> order(n_traps);

@@ -190,6 +190,7 @@ struct LaunchShape {
     int update_waves; // waves per 64 ions in the step epilogue (4, 8 or 16)
     int small_path;   // single trap stepped by the one-workgroup kernel (k_batch, one trap)
     bool cool_on;     // a beam, bath or time average is on: the kernels built with them run
+    double uniform_q;  // every ion's charge in units of e when all are equal, else 0
 };
 
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the

@@ -786,18 +786,15 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
 
 // CH: sources per reaction-sum chunk (LDS per block grows with it); WPE: the
 // occupancy the register allocation aims at.
-template <int L, int CH, int WPE, int UNR, bool PF = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
-void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
-                      double* __restrict__ part, int64_t* __restrict__ counter) {
-    __shared__ float4 tile[2 * kSymTile];
-    // per-wave reaction buffers, reused for the final target-side reduction
+// FQ: every ion of the tile pair carries the same charge uq (in units of e), so
+// the per-pair charge factors are applied once per sum instead (an exact
+// refactoring; tiles holding zero-charge padding ions take the general path).
+template <int L, int CH, int UNR, bool PF, bool FQ>
+__device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm, int64_t n,
+                                               int nb, int64_t n_pad, double* __restrict__ part,
+                                               int a, int b, float uq, float4* tile,
+                                               double* smem) {
     constexpr int S = CH * 3 + 1;  // row stride of the lane-major reaction buffer
-    constexpr int kRed = (kWaves - 1) * 3 * 64 * 2;
-    constexpr int kBuf = (kWaves * 64 * S + 1) / 2;
-    __shared__ __align__(16) double smem[kBuf > kRed ? kBuf : kRed];
-    int a, b;
-    sym_unit(nb, a, b);
     const bool diag = (a == b);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t base = (int64_t)a * kSymTile + lane;
@@ -848,12 +845,12 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, m.r2floor)));
                 const float y = __builtin_amdgcn_rsqf(r2);
                 const float y3 = (y * y) * y;
-                const float wi = m.nq * y3;  // -q_j r^-3
+                const float wi = FQ ? y3 : m.nq * y3;  // -q_j r^-3 (times -1/uq with FQ)
                 fx[k] = fmaf(wi, dx, fx[k]);
                 fy[k] = fmaf(wi, dy, fy[k]);
                 fz[k] = fmaf(wi, dz, fz[k]);
                 if (!diag) {
-                    const float wj = qi[k] * y3;  // q_i r^-3
+                    const float wj = FQ ? y3 : qi[k] * y3;  // q_i r^-3 (times 1/uq with FQ)
                     tx = fmaf(wj, dx, tx);
                     ty = fmaf(wj, dy, ty);
                     tz = fmaf(wj, dz, tz);
@@ -882,30 +879,57 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
             if ((lane % P) == 0 && col < CH * 3) {
                 const int uu = col / 3, c = col - 3 * uu;
                 const int64_t j = (int64_t)b * kSymTile + wave * 64 + s0 + uu;
-                part[((int64_t)a * 3 + c) * n_pad + j] = tot;
+                part[((int64_t)a * 3 + c) * n_pad + j] = FQ ? tot * (double)uq : tot;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
+    if (FQ) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sx[k] *= -(double)uq;
+            sy[k] *= -(double)uq;
+            sz[k] *= -(double)uq;
+        }
+    }
     __syncthreads();  // every wave is done with its reaction buffer
     reduce_store_halves(sx, sy, sz, part, b, n, n_pad, base, smem);
+}
+
+// uq != 0: every ion carries the charge uq (units of e) and tiles below
+// full_tiles hold no padding; those tile pairs take the charge-free loop.
+template <int L, int CH, int WPE, int UNR, bool PF = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
+                      double* __restrict__ part, int64_t* __restrict__ counter, float uq,
+                      int full_tiles) {
+    __shared__ float4 tile[2 * kSymTile];
+    // per-wave reaction buffers, reused for the final target-side reduction
+    constexpr int S = CH * 3 + 1;
+    constexpr int kRed = (kWaves - 1) * 3 * 64 * 2;
+    constexpr int kBuf = (kWaves * 64 * S + 1) / 2;
+    __shared__ __align__(16) double smem[kBuf > kRed ? kBuf : kRed];
+    int a, b;
+    sym_unit(nb, a, b);
+    if (uq != 0.0f && b < full_tiles)
+        mixed_sym_body<L, CH, UNR, PF, true>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
+    else
+        mixed_sym_body<L, CH, UNR, PF, false>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
-// WPE: the occupancy the register allocation aims at; UNR: sources unrolled.
-template <int WPE, int UNR, bool PF = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
-void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
-                    int nb, int64_t n_pad, double* __restrict__ part,
-                    int64_t* __restrict__ counter) {
+// One tile pair (a, b) of the FP64 pair-once kernel.  With FQ every ion in
+// both tiles carries the charge uq: the sums run over c d alone and are scaled
+// by the charge once, at the end.
+template <int UNR, bool PF, bool FQ>
+__device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
+                                             const double* __restrict__ qe, int64_t n,
+                                             int64_t n_pad, double* __restrict__ part, int a,
+                                             int b, double uq, double* smem) {
     constexpr int CH = 4;
     constexpr int S = CH * 3 + 1;
-    __shared__ double smem[kWaves * 64 * S];
-    static_assert(kWaves * 64 * S >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
-    int a, b;
-    sym_unit(nb, a, b);
     const bool diag = (a == b);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -917,7 +941,7 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
         xi[k] = p.x;
         yi[k] = p.y;
         zi[k] = p.z;
-        nqi[k] = -1.5 * qe[base + 64 * k];
+        nqi[k] = FQ ? 0.0 : -1.5 * qe[base + 64 * k];
         sx[k] = sy[k] = sz[k] = 0.0;
     }
     double* jb = smem + wave * 64 * S;
@@ -942,13 +966,13 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
                 const double y = __builtin_amdgcn_rsq(r2);
                 const double a2 = y * y;
                 const double g = fma(r2, a2, -5.0 / 3.0);
-                const double c = (a2 * y) * g;   // -(2/3) r^-3 (one Newton correction)
-                const double wi = c * p.w;       // 1.5 q_j c = -q_j r^-3
+                const double c = (a2 * y) * g;        // -(2/3) r^-3 (one Newton correction)
+                const double wi = FQ ? c : c * p.w;  // 1.5 q_j c = -q_j r^-3
                 sx[k] = fma(wi, dx, sx[k]);
                 sy[k] = fma(wi, dy, sy[k]);
                 sz[k] = fma(wi, dz, sz[k]);
                 if (!diag) {
-                    const double wj = c * nqi[k];  // -1.5 q_i c = q_i r^-3
+                    const double wj = FQ ? c : c * nqi[k];  // -1.5 q_i c = q_i r^-3
                     tx = fma(wj, dx, tx);
                     ty = fma(wj, dy, ty);
                     tz = fma(wj, dz, tz);
@@ -968,15 +992,42 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
             const int col = lane >> 2;
             if ((lane & 3) == 0 && col < CH * 3) {
                 const int uu = col / 3, c = col - 3 * uu;
-                part[((int64_t)a * 3 + c) * n_pad + j0 + s0 + uu] = tot;
+                part[((int64_t)a * 3 + c) * n_pad + j0 + s0 + uu] = FQ ? tot * (-1.5 * uq) : tot;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
+    if (FQ) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sx[k] *= 1.5 * uq;
+            sy[k] *= 1.5 * uq;
+            sz[k] *= 1.5 * uq;
+        }
+    }
     __syncthreads();  // every wave is done with its reaction buffer
     reduce_store_in<4>(sx, sy, sz, part, b, n, n_pad, base, smem);
+}
+
+// WPE: the occupancy the register allocation aims at; UNR: sources unrolled.
+// uq != 0: every ion carries the charge uq (units of e) and tiles below
+// full_tiles hold no padding; those tile pairs take the charge-free loop.
+template <int WPE, int UNR, bool PF = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
+                    int nb, int64_t n_pad, double* __restrict__ part,
+                    int64_t* __restrict__ counter, double uq, int full_tiles) {
+    constexpr int S = 4 * 3 + 1;
+    __shared__ double smem[kWaves * 64 * S];
+    static_assert(kWaves * 64 * S >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
+    int a, b;
+    sym_unit(nb, a, b);
+    if (uq != 0.0 && b < full_tiles)
+        f64_sym_body<UNR, PF, true>(src, qe, n, n_pad, part, a, b, uq, smem);
+    else
+        f64_sym_body<UNR, PF, false>(src, qe, n, n_pad, part, a, b, uq, smem);
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
@@ -1826,52 +1877,54 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
     if (ls.symmetric) {
         const int nb = sym_tiles(s.n);
         const unsigned units = (unsigned)(nb * (nb + 1) / 2);
+        const double uq = ls.uniform_q;                // 0: charges differ
+        const int full = (int)(s.n / kSymTile);        // tiles without padding
         if (precision == 0) {
             switch (ls.sym_variant) {
                 case 1:
-                    k_pair_f64_sym<4, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<4, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
                 case 2:
-                    k_pair_f64_sym<3, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<3, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
                 case 3:
-                    k_pair_f64_sym<4, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<4, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
                 case 4:
-                    k_pair_f64_sym<2, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<2, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
                 case 5:
-                    k_pair_f64_sym<4, 1, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<4, 1, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
                 case 6:
-                    k_pair_f64_sym<3, 2, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<3, 2, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
                 default:
-                    k_pair_f64_sym<3, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_f64_sym<3, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
                     break;
             }
         } else {
             switch (ls.sym_variant) {
                 case 1:
-                    k_pair_mixed_sym<8, 4, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 4, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
                 case 2:
-                    k_pair_mixed_sym<8, 4, 6, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 4, 6, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
                 case 3:
-                    k_pair_mixed_sym<8, 8, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 8, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
                 case 4:
-                    k_pair_mixed_sym<8, 4, 4, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 4, 4, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
                 case 5:
-                    k_pair_mixed_sym<8, 8, 5, 1, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 8, 5, 1, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
                 case 6:
-                    k_pair_mixed_sym<8, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
                 default:
-                    k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr);
+                    k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
                     break;
             }
         }

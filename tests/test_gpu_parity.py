@@ -194,6 +194,24 @@ def test_pair_once_variants(torch_gpu, oracle_mod, prec, variant):
         sim.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("q", [-1, 3])
+def test_pair_once_uniform_charge(torch_gpu, oracle_mod, prec, q):
+    """All ions of one charge other than +1 e: tile pairs without padding take
+    the loop with the charge factored out of the sums, the last ragged tile the
+    general loop; both meet the bar with the right sign and scale."""
+    for n in (1000, 4096):
+        w = li.random_cloud(n, seed=700 + n, sigma=60e-6, light_fraction=0.2,
+                            charge_e=np.full(n, q))
+        sim = _sim(w, prec, oracle_mod, symmetric=2)
+        tr = _oracle_trap(oracle_mod, w.traps[0])
+        r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+        sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+        err = _m1(sim.compute_accel(), r, sc)
+        assert err <= TOL[prec], (n, q, err)
+        sim.close()
+
+
 def test_pair_once_rejected_where_unsupported(torch_gpu, oracle_mod):
     from paper_1907_10514_amd import LionError
     from paper_1907_10514_amd import lion as L
