@@ -691,8 +691,9 @@ __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict
 // Pair field with Newton's third law: every unordered pair is evaluated once.
 //
 // Ions are cut into tiles of 256.  Block u handles the tile pair (a, b), a <= b
-// (upper triangle, row-major).  Its 4 waves each hold all 256 targets of tile a
-// (4 per lane) and take 64 of the 256 sources of tile b.  For a source j and
+// (the strict upper triangle row-major, then the diagonal tiles).  Its 4 waves
+// each hold all 256 targets of tile a (4 per lane) and take 64 of the 256
+// sources of tile b.  For a source j and
 // target i the block adds q_j (r_i - r_j)/r^3 to target i (registers) and
 // q_i (r_j - r_i)/r^3 to source j; the latter is summed over the wave's 64
 // lanes through a per-wave LDS transpose (fixed order).  Diagonal tiles
@@ -704,14 +705,20 @@ __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict
 constexpr int kSymTile = 256;
 
 __device__ __forceinline__ void sym_unit(int nb, int& a, int& b) {
-    int u = blockIdx.x, row = 0, len = nb;
+    const int off = nb * (nb - 1) / 2;
+    int u = blockIdx.x;
+    if (u >= off) {  // diagonal tiles, which skip the reaction sums, go last
+        a = b = u - off;
+        return;
+    }
+    int row = 0, len = nb - 1;
     while (u >= len) {
         u -= len;
         ++row;
         --len;
     }
     a = row;
-    b = row + u;
+    b = row + 1 + u;
 }
 
 // Sum over the 64 lanes of a wave of C columns held lane-major in buf[64][S]
