@@ -174,6 +174,7 @@ struct DevState {
     int32_t* rstart;     // [nbodies + 1]
     // rigid-body exclusion (all NULL when no bodies are set)
     int32_t* body_code;  // [n_pad] body id >= 0, or -1 - i for a free ion i
+    int32_t* tile_body;  // [n_pad / 256] body of every ion of a 256-ion tile, or -1 (no body ions)
     int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions
     int32_t* body_gmax;  // [n_pad / 16] largest body id (-1 if none)
 };
@@ -196,7 +197,7 @@ struct LaunchShape {
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the
 // epilogue then adds one partial per tile.
 inline int sym_tiles(int64_t n) { return (int)((n + 255) / 256); }
-constexpr int kMaxSymTiles = 128;
+constexpr int kMaxSymTiles = 256;
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st);

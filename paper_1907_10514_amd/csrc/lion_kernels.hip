@@ -721,6 +721,32 @@ __device__ __forceinline__ void sym_unit(int nb, int& a, int& b) {
     b = row + 1 + u;
 }
 
+// Rigid-body exclusion for the pair-once kernels.  tile_body[t] is the body of
+// every ion of tile t (>= 0) or -1 when the tile holds no body ions (bodies
+// that share a tile with other ions take the all-pairs kernels instead).  A
+// tile pair inside one body contributes nothing: its two partial slots get
+// zeros, so the epilogue still adds one partial per tile.
+__device__ __forceinline__ bool sym_unit_excluded(const int32_t* __restrict__ tile_body, int a,
+                                                  int b) {
+    return tile_body && tile_body[a] >= 0 && tile_body[a] == tile_body[b];
+}
+
+__device__ __forceinline__ void sym_unit_zero(double* __restrict__ part, int64_t n,
+                                              int64_t n_pad, int a, int b) {
+    const int64_t i = (int64_t)a * kSymTile + threadIdx.x;  // target side, slot b
+    if (i < n) {
+        part[((int64_t)b * 3 + 0) * n_pad + i] = 0.0;
+        part[((int64_t)b * 3 + 1) * n_pad + i] = 0.0;
+        part[((int64_t)b * 3 + 2) * n_pad + i] = 0.0;
+    }
+    if (a != b) {  // reaction side, slot a
+        const int64_t j = (int64_t)b * kSymTile + threadIdx.x;
+        part[((int64_t)a * 3 + 0) * n_pad + j] = 0.0;
+        part[((int64_t)a * 3 + 1) * n_pad + j] = 0.0;
+        part[((int64_t)a * 3 + 2) * n_pad + j] = 0.0;
+    }
+}
+
 // Sum over the 64 lanes of a wave of C columns held lane-major in buf[64][S]
 // (S = C + 1: consecutive lanes write consecutive rows, and a column read by
 // consecutive lanes touches consecutive banks).  P lanes per column each add
@@ -911,7 +937,7 @@ template <int L, int CH, int WPE, int UNR, bool PF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
                       double* __restrict__ part, int64_t* __restrict__ counter, float uq,
-                      int full_tiles) {
+                      int full_tiles, const int32_t* __restrict__ tile_body) {
     __shared__ float4 tile[2 * kSymTile];
     // per-wave reaction buffers, reused for the final target-side reduction
     constexpr int S = CH * 3 + 1;
@@ -920,7 +946,9 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
     __shared__ __align__(16) double smem[kBuf > kRed ? kBuf : kRed];
     int a, b;
     sym_unit(nb, a, b);
-    if (uq != 0.0f && b < full_tiles)
+    if (sym_unit_excluded(tile_body, a, b))
+        sym_unit_zero(part, n, n_pad, a, b);
+    else if (uq != 0.0f && b < full_tiles)
         mixed_sym_body<L, CH, UNR, PF, true>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
     else
         mixed_sym_body<L, CH, UNR, PF, false>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
@@ -1025,13 +1053,16 @@ template <int WPE, int UNR, bool PF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
                     int nb, int64_t n_pad, double* __restrict__ part,
-                    int64_t* __restrict__ counter, double uq, int full_tiles) {
+                    int64_t* __restrict__ counter, double uq, int full_tiles,
+                    const int32_t* __restrict__ tile_body) {
     constexpr int S = 4 * 3 + 1;
     __shared__ double smem[kWaves * 64 * S];
     static_assert(kWaves * 64 * S >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
     int a, b;
     sym_unit(nb, a, b);
-    if (uq != 0.0 && b < full_tiles)
+    if (sym_unit_excluded(tile_body, a, b))
+        sym_unit_zero(part, n, n_pad, a, b);
+    else if (uq != 0.0 && b < full_tiles)
         f64_sym_body<UNR, PF, true>(src, qe, n, n_pad, part, a, b, uq, smem);
     else
         f64_sym_body<UNR, PF, false>(src, qe, n, n_pad, part, a, b, uq, smem);
@@ -1886,52 +1917,53 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
         const unsigned units = (unsigned)(nb * (nb + 1) / 2);
         const double uq = ls.uniform_q;                // 0: charges differ
         const int full = (int)(s.n / kSymTile);        // tiles without padding
+        const int32_t* tb = s.body_code ? s.tile_body : nullptr;  // exclusion by whole tiles
         if (precision == 0) {
             switch (ls.sym_variant) {
                 case 1:
-                    k_pair_f64_sym<4, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<4, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
                 case 2:
-                    k_pair_f64_sym<3, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<3, 1><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
                 case 3:
-                    k_pair_f64_sym<4, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<4, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
                 case 4:
-                    k_pair_f64_sym<2, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<2, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
                 case 5:
-                    k_pair_f64_sym<4, 1, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<4, 1, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
                 case 6:
-                    k_pair_f64_sym<3, 2, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<3, 2, true><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
                 default:
-                    k_pair_f64_sym<3, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full);
+                    k_pair_f64_sym<3, 2><<<units, 256, 0, st>>>(s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb);
                     break;
             }
         } else {
             switch (ls.sym_variant) {
                 case 1:
-                    k_pair_mixed_sym<8, 4, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 4, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 case 2:
-                    k_pair_mixed_sym<8, 4, 6, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 4, 6, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 case 3:
-                    k_pair_mixed_sym<8, 8, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 8, 5, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 case 4:
-                    k_pair_mixed_sym<8, 4, 4, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 4, 4, 1><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 case 5:
-                    k_pair_mixed_sym<8, 8, 5, 1, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 8, 5, 1, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 case 6:
-                    k_pair_mixed_sym<8, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 default:
-                    k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full);
+                    k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
             }
         }

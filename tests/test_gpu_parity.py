@@ -544,15 +544,97 @@ def test_body_exclusion_parity(torch_gpu, oracle_mod, prec, contiguous):
     sim.close()
 
 
+def _tile_body_cloud(n, seed, charge_e=None):
+    """Cloud whose bodies fill whole 256-ion tiles: body 0 = tile 0, body 1 =
+    tiles 1-2, body 2 = tile 3; the rest free (last tile ragged)."""
+    w = li.random_cloud(n, seed=seed, sigma=40e-6, light_fraction=0.2, charge_e=charge_e)
+    body = np.full(n, -1, dtype=np.int32)
+    body[:256] = 0
+    body[256:768] = 1
+    body[768:1024] = 2
+    return w, body
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("charges", ["uniform", "mixed"])
+def test_pair_once_tile_aligned_bodies(torch_gpu, oracle_mod, prec, charges):
+    """Bodies that fill whole 256-ion tiles on the pair-once kernels: tile pairs
+    inside one body are skipped, everything else is evaluated once; the field
+    meets the bar against the oracle and the all-pairs kernels with the mask."""
+    q = None if charges == "uniform" else np.random.default_rng(3).choice([1, 2, -1], 3000)
+    w, body = _tile_body_cloud(3000, 51, q)
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    rx, ry, rz, sc = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0)
+    sym = _sim(w, prec, oracle_mod, symmetric=2)
+    sym.set_bodies(body)
+    assert sym.config()["symmetric"] == 2
+    a = sym.compute_accel()
+    err = _m1(a, (rx, ry, rz), sc)
+    allp = _sim(w, prec, oracle_mod, symmetric=1)
+    allp.set_bodies(body)
+    err_all = _m1(a, allp.compute_accel(), sc)
+    print(f"tile bodies {prec} {charges}: M1={err:.3e} vs masked all-pairs {err_all:.3e}")
+    assert err <= TOL[prec]
+    assert err_all <= 2 * TOL[prec]
+    sym.close()
+    allp.close()
+
+
+def test_pair_once_rigid_steps(torch_gpu, oracle_mod):
+    """Rigid integration over the pair-once kernels (tile-aligned bodies)
+    follows the masked all-pairs run to round-off over 30 FP64 steps."""
+    w, body = _tile_body_cloud(1600, 53)
+    dt = w.traps[0].dt
+    outs = []
+    for sym in (2, 1):
+        sim = _sim(w, "fp64", oracle_mod, symmetric=sym)
+        sim.set_rigid_bodies(body)
+        sim.step(30, dt)
+        outs.append(sim.get_state()[0])
+        sim.close()
+    ext = np.max(np.abs(w.x))
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(outs[0][k] - outs[1][k])) < 1e-11 * ext, k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pair_once_above_32768(torch_gpu, oracle_mod, prec):
+    """Pair-once kernels at 40000 ions (157 tiles, one partial per tile):
+    sampled targets against the oracle, and 5 steps against all-pairs."""
+    w = li.random_cloud(40000, seed=55, sigma=200e-6, light_fraction=0.2)
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    sim = _sim(w, prec, oracle_mod, symmetric=2)
+    assert sim.config()["symmetric"] == 2
+    a = sim.compute_accel()
+    idx = np.random.default_rng(6).choice(w.n, 256, replace=False)
+    rx, ry, rz, sc = oracle_mod.accel_at(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0, idx)
+    err = _m1((a[0][idx], a[1][idx], a[2][idx]), (rx, ry, rz), sc)
+    print(f"pair-once N=40000 {prec} sampled M1={err:.3e}")
+    assert err <= TOL[prec]
+    outs = []
+    for s2 in (sim, _sim(w, prec, oracle_mod, symmetric=1)):
+        s2.step(5, w.traps[0].dt)
+        outs.append(s2.get_state()[0])
+        s2.close()
+    ext = np.max(np.abs(w.x))
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(outs[0][k] - outs[1][k])) < tol * ext
+
+
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_clusters65536_sampled(torch_gpu, oracle_mod, prec):
+@pytest.mark.parametrize("sym", [1, 2])
+def test_clusters65536_sampled(torch_gpu, oracle_mod, prec, sym):
     """64 rigid clusters of 512 + 32768 free ions (65536): sampled targets in
-    clusters and free, every source counted, intra-cluster pairs left out."""
+    clusters and free, every source counted, intra-cluster pairs left out, on
+    the all-pairs kernels (mask) and on the pair-once kernels (whole tile
+    pairs skipped)."""
     w = li.clusters65536()
     body = w.notes["body"]
     tr = _oracle_trap(oracle_mod, w.traps[0])
-    sim = _sim(w, prec, oracle_mod)
+    sim = _sim(w, prec, oracle_mod, symmetric=sym)
     sim.set_bodies(body)
+    assert sim.config()["symmetric"] == sym
     a = sim.compute_accel()
     rng = np.random.default_rng(5)
     idx = np.concatenate([rng.choice(32768, 96, replace=False),
@@ -572,15 +654,19 @@ def test_bodies_rejected_where_unsupported(torch_gpu, oracle_mod):
     from paper_1907_10514_amd import lion as L
 
     w = li.random_cloud(300, seed=2)
+    shared = np.full(300, -1, dtype=np.int32)
+    shared[:100] = 0  # body 0 shares the first 256-ion tile with free ions
     sim = _sim(w, "mixed", oracle_mod, symmetric=2)
     with pytest.raises(LionError) as ei:
-        sim.set_bodies(np.zeros(300, dtype=np.int32))
+        sim.set_bodies(shared)
     assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    sim.set_bodies(np.zeros(300, dtype=np.int32))  # whole tiles: accepted
+    assert sim.config()["symmetric"] == 2
     sim.set_config(symmetric=1)
     with pytest.raises(LionError) as ei:
         sim.set_bodies(np.full(300, -2, dtype=np.int32))
     assert ei.value.code == L.LION_ERR_ARG
-    sim.set_bodies(np.zeros(300, dtype=np.int32))
+    sim.set_bodies(shared)
     with pytest.raises(LionError) as ei:
         sim.set_config(symmetric=2)
     assert ei.value.code == L.LION_ERR_UNSUPPORTED
