@@ -750,9 +750,12 @@ __device__ __forceinline__ void sym_unit_zero(double* __restrict__ part, int64_t
 // Sum over the 64 lanes of a wave of C columns held lane-major in buf[64][S]
 // (S = C + 1: consecutive lanes write consecutive rows, and a column read by
 // consecutive lanes touches consecutive banks).  P lanes per column each add
-// 64/P rows in FP64 with four independent partial sums, then the P part sums
-// are combined by lane exchanges (P = 2 or 4).  The column total ends up in
-// lanes with (lane % P) == 0, column = lane / P.
+// 64/P rows, then the P part sums are combined by lane exchanges (P = 2 or 4).
+// FP64 rows are added in FP64 with four independent partial sums.  FP32 rows
+// are added in FP32 runs of 8 (pairwise, so each run carries at most 3
+// roundings) and the run totals in FP64, the same FP32-run / FP64-flush rule
+// as the target sums.  The column total ends up in lanes with
+// (lane % P) == 0, column = lane / P.
 template <int C, int P, typename T>
 __device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int lane) {
     static_assert(C * P <= 64 && (P == 2 || P == 4), "bad column split");
@@ -761,12 +764,28 @@ __device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int la
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     if (col < C) {
         const T* p = buf + (E * q) * S + col;
+        if constexpr (sizeof(T) == sizeof(float)) {
+            static_assert(E % 8 == 0 && E / 8 <= 4, "FP32 runs of 8 rows");
+            double run[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < E; e += 4) {
-            acc0 += (double)p[(e + 0) * S];
-            acc1 += (double)p[(e + 1) * S];
-            acc2 += (double)p[(e + 2) * S];
-            acc3 += (double)p[(e + 3) * S];
+            for (int g = 0; g < E / 8; ++g) {
+                const T* r = p + 8 * g * S;
+                const float s01 = r[0] + r[S], s23 = r[2 * S] + r[3 * S];
+                const float s45 = r[4 * S] + r[5 * S], s67 = r[6 * S] + r[7 * S];
+                run[g] = (double)((s01 + s23) + (s45 + s67));
+            }
+            acc0 = run[0];
+            acc1 = run[1];
+            acc2 = run[2];
+            acc3 = run[3];
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; e += 4) {
+                acc0 += (double)p[(e + 0) * S];
+                acc1 += (double)p[(e + 1) * S];
+                acc2 += (double)p[(e + 2) * S];
+                acc3 += (double)p[(e + 3) * S];
+            }
         }
     }
     double acc = (acc0 + acc1) + (acc2 + acc3);
