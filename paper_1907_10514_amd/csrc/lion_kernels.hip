@@ -1221,6 +1221,9 @@ __global__ __launch_bounds__(256) void k_check_finite(const double4* __restrict_
 // in registers for the whole launch; the trap's source stream lives in LDS.
 
 constexpr int kMaxTrap = 1024;
+// Traps of at least kBatchTpt4 (kBatchTpt2) ions give each thread 4 (2) targets.
+constexpr int kBatchTpt4 = 256;
+constexpr int kBatchTpt2 = 128;
 
 template <int PREC>
 struct BatchSrc;
@@ -1236,6 +1239,114 @@ template <>
 struct BatchSrc<2> {
     using T = MixedSrc;
 };
+
+// Field sums of TPT targets per thread over the sources [jb, je) of the LDS
+// stream: each source is read once for all TPT targets (il_k = slot + ws k),
+// which cuts the broadcast LDS reads per pair by TPT.  Per target the sums run
+// over the sources in order, as with one target per thread (FP32 runs of 8
+// flushed to FP64, or Kahan).  Targets at or beyond m give unused sums.
+template <int PREC, int TPT>
+__device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>::T* __restrict__ lds,
+                                                  int m, int slot, int ws, int jb, int je,
+                                                  double (&Sx)[4], double (&Sy)[4],
+                                                  double (&Sz)[4]) {
+    int il[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int t = slot + ws * k;
+        il[k] = t < m ? t : 0;
+    }
+    if constexpr (PREC == 0) {
+        double xi[TPT], yi[TPT], zi[TPT], sx[TPT], sy[TPT], sz[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const double4 me = lds[il[k]];
+            xi[k] = me.x;
+            yi[k] = me.y;
+            zi[k] = me.z;
+            sx[k] = sy[k] = sz[k] = 0.0;
+        }
+        for (int j = jb; j < je; ++j) {
+            const double4 p = lds[j];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) pair_f64(p, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            Sx[k] = sx[k];
+            Sy[k] = sy[k];
+            Sz[k] = sz[k];
+        }
+    } else if constexpr (PREC == 1) {
+        FF t[TPT];
+        double sx[TPT], sy[TPT], sz[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const MixedSrc me = lds[il[k]];
+            t[k].xh = me.xh;
+            t[k].yh = me.yh;
+            t[k].zh = me.zh;
+            t[k].xl = me.xl;
+            t[k].yl = me.yl;
+            t[k].zl = me.zl;
+            sx[k] = sy[k] = sz[k] = 0.0;
+        }
+        for (int j = jb; j < je; j += 8) {
+            float fx[TPT], fy[TPT], fz[TPT];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+#pragma unroll
+            for (int uu = 0; uu < 8; ++uu) {
+                const MixedSrc q = lds[j + uu];
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) pair_f32(q, t[k], fx[k], fy[k], fz[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                sx[k] += (double)fx[k];
+                sy[k] += (double)fy[k];
+                sz[k] += (double)fz[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            Sx[k] = sx[k] * kMixedFieldScale;
+            Sy[k] = sy[k] * kMixedFieldScale;
+            Sz[k] = sz[k] * kMixedFieldScale;
+        }
+    } else {
+        FF t[TPT];
+        float sx[TPT], sy[TPT], sz[TPT], cx[TPT], cy[TPT], cz[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const MixedSrc me = lds[il[k]];
+            t[k].xh = me.xh;
+            t[k].yh = me.yh;
+            t[k].zh = me.zh;
+            t[k].xl = me.xl;
+            t[k].yl = me.yl;
+            t[k].zl = me.zl;
+            sx[k] = sy[k] = sz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
+        }
+        for (int j = jb; j < je; ++j) {
+            const MixedSrc q = lds[j];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                float tx, ty, tz;
+                pair_f32_terms(q, t[k], tx, ty, tz);
+                kahan_add(tx, sx[k], cx[k]);
+                kahan_add(ty, sy[k], cy[k]);
+                kahan_add(tz, sz[k], cz[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            Sx[k] = ((double)sx[k] - (double)cx[k]) * kMixedFieldScale;
+            Sy[k] = ((double)sy[k] - (double)cy[k]) * kMixedFieldScale;
+            Sz[k] = ((double)sz[k] - (double)cz[k]) * kMixedFieldScale;
+        }
+    }
+}
 
 template <int PREC, int BLOCK, bool X>
 __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
@@ -1278,6 +1389,19 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const int je = min(jb + jlen, m16);
     const TrapDev T = traps[tr];
     const int64_t k0 = *counter;
+    // pair work of larger traps: TPT targets per thread read each source once
+    // (at most 2 with 1024 threads, whose 128-VGPR budget 4 targets overflow)
+    constexpr int TMAX = BLOCK >= 1024 ? 2 : 4;
+    int TPT = m >= kBatchTpt4 ? TMAX : (m >= kBatchTpt2 ? 2 : 1);
+    if (TPT > 1)
+        while (TPT < TMAX && TPT * BLOCK < m) TPT *= 2;
+    const int WS = ((m + 64 * TPT - 1) / (64 * TPT)) * 64;  // <= BLOCK
+    const int JPW = BLOCK / WS;
+    const int wslot = tid % WS, wpart = tid / WS;
+    const bool wactive = wpart < JPW;
+    const int wlen = ((m16 / JPW) + 15) & ~15;
+    const int wjb = min(wpart * wlen, m16);
+    const int wje = min(wjb + wlen, m16);
 
     double x[KMAX], y[KMAX], z[KMAX], u[KMAX], v[KMAX], w[KMAX], a0[KMAX], a1[KMAX], a2[KMAX];
     double q_m[KMAX], q_e[KMAX], m_i[KMAX];
@@ -1336,13 +1460,51 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             }
         }
         __syncthreads();
-        // pair field of this thread's targets over its source part
         double Sx[KMAX], Sy[KMAX], Sz[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) Sx[k] = Sy[k] = Sz[k] = 0.0;
+        if (TPT > 1) {
+            // TPT targets per thread, partial sums to the owners in part order
+            double Wx[4], Wy[4], Wz[4];
+            if (wactive) {
+                if constexpr (TMAX >= 4) {
+                    if (TPT == 4)
+                        batch_pairs_multi<PREC, 4>(lds, m, wslot, WS, wjb, wje, Wx, Wy, Wz);
+                    else
+                        batch_pairs_multi<PREC, 2>(lds, m, wslot, WS, wjb, wje, Wx, Wy, Wz);
+                } else {
+                    batch_pairs_multi<PREC, 2>(lds, m, wslot, WS, wjb, wje, Wx, Wy, Wz);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= TPT) break;
+                if (wactive) {
+                    red[0][tid] = Wx[k];
+                    red[1][tid] = Wy[k];
+                    red[2][tid] = Wz[k];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < KMAX; ++kk) {
+                    const int il = slot + IS * kk;
+                    if (owner && il < m && il / WS == k) {
+                        const int r = il - WS * k;
+                        for (int pp = 0; pp < JPW; ++pp) {
+                            Sx[kk] += red[0][pp * WS + r];
+                            Sy[kk] += red[1][pp * WS + r];
+                            Sz[kk] += red[2][pp * WS + r];
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // pair field of this thread's targets over its source part (one target per thread)
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const int il = slot + IS * k;
-            Sx[k] = Sy[k] = Sz[k] = 0.0;
-            if (!active || il >= m) continue;
+            if (TPT > 1 || !active || il >= m) continue;
             if constexpr (PREC == 0) {
                 const double4 me = lds[il];
                 double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -1393,7 +1555,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                 }
             }
         }
-        if (JP > 1) {
+        if (JP > 1 && TPT == 1) {
             // deterministic reduction over source parts: owners add parts in order
             // (only KMAX == 1 can have JP > 1, since JP > 1 needs m <= BLOCK / 2)
             if (active && jpart > 0) {
