@@ -54,12 +54,29 @@ __device__ __forceinline__ void pair_f64(const double4 p, double xi, double yi, 
     sz = fma(w, dz, sz);
 }
 
+// As pair_f64 for a source of unit weight: adds y^3 (r2 y^2 - 5/3) d, which
+// times 1.5 q_j is the term of pair_f64 (the caller scales the sums).
+__device__ __forceinline__ void pair_f64_unit(const double4 p, double xi, double yi, double zi,
+                                              double& sx, double& sy, double& sz) {
+    const double dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, kR2FloorF64)));
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double a = y * y;
+    const double g = fma(r2, a, -5.0 / 3.0);
+    const double w = (a * y) * g;
+    sx = fma(w, dx, sx);
+    sy = fma(w, dy, sy);
+    sz = fma(w, dz, sz);
+}
+
 // Target-side float-float position.
 struct FF {
     float xh, yh, zh, xl, yl, zl;
 };
 
 // One FP32 pair term on float-float positions; returns the three products.
+// UNIT: the source weight -q is left out (the caller scales the sums).
+template <bool UNIT = false>
 __device__ __forceinline__ void pair_f32_terms(const MixedSrc& q, const FF& t, float& tx,
                                                float& ty, float& tz) {
     const float dx = (q.xh - t.xh) + (q.xl - t.xl);
@@ -67,10 +84,24 @@ __device__ __forceinline__ void pair_f32_terms(const MixedSrc& q, const FF& t, f
     const float dz = (q.zh - t.zh) + (q.zl - t.zl);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, q.r2floor)));
     const float y = __builtin_amdgcn_rsqf(r2);
-    const float w = (q.nq * y) * (y * y);  // -q r^-3
+    const float w = UNIT ? y * (y * y) : (q.nq * y) * (y * y);  // -q r^-3 (r^-3 with UNIT)
     tx = w * dx;
     ty = w * dy;
     tz = w * dz;
+}
+
+// As pair_f32 for a source of unit weight (r^-3 d; the caller scales by -q).
+__device__ __forceinline__ void pair_f32_unit(const MixedSrc& q, const FF& t, float& sx,
+                                              float& sy, float& sz) {
+    const float dx = (q.xh - t.xh) + (q.xl - t.xl);
+    const float dy = (q.yh - t.yh) + (q.yl - t.yl);
+    const float dz = (q.zh - t.zh) + (q.zl - t.zl);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, q.r2floor)));
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float w = y * (y * y);
+    sx = fmaf(w, dx, sx);
+    sy = fmaf(w, dy, sy);
+    sz = fmaf(w, dz, sz);
 }
 
 __device__ __forceinline__ void pair_f32(const MixedSrc& q, const FF& t, float& sx, float& sy,
@@ -1221,6 +1252,7 @@ __global__ __launch_bounds__(256) void k_check_finite(const double4* __restrict_
 // in registers for the whole launch; the trap's source stream lives in LDS.
 
 constexpr int kMaxTrap = 1024;
+constexpr double kFarPad = 1e6;  // m: position of padding sources on the common-charge path
 // Traps of at least kBatchTpt4 (kBatchTpt2) ions give each thread 4 (2) targets.
 constexpr int kBatchTpt4 = 256;
 constexpr int kBatchTpt2 = 128;
@@ -1245,10 +1277,10 @@ struct BatchSrc<2> {
 // which cuts the broadcast LDS reads per pair by TPT.  Per target the sums run
 // over the sources in order, as with one target per thread (FP32 runs of 8
 // flushed to FP64, or Kahan).  Targets at or beyond m give unused sums.
-template <int PREC, int TPT>
+template <int PREC, int TPT, bool FQ>
 __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>::T* __restrict__ lds,
                                                   int m, int slot, int ws, int jb, int je,
-                                                  double (&Sx)[4], double (&Sy)[4],
+                                                  double uq, double (&Sx)[4], double (&Sy)[4],
                                                   double (&Sz)[4]) {
     int il[TPT];
 #pragma unroll
@@ -1269,13 +1301,19 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
         for (int j = jb; j < je; ++j) {
             const double4 p = lds[j];
 #pragma unroll
-            for (int k = 0; k < TPT; ++k) pair_f64(p, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+            for (int k = 0; k < TPT; ++k) {
+                if constexpr (FQ)
+                    pair_f64_unit(p, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                else
+                    pair_f64(p, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+            }
         }
+        const double cq = FQ ? 1.5 * uq : 1.0;  // pair_f64_unit leaves out the 1.5 q_j factor
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
-            Sx[k] = sx[k];
-            Sy[k] = sy[k];
-            Sz[k] = sz[k];
+            Sx[k] = FQ ? sx[k] * cq : sx[k];
+            Sy[k] = FQ ? sy[k] * cq : sy[k];
+            Sz[k] = FQ ? sz[k] * cq : sz[k];
         }
     } else if constexpr (PREC == 1) {
         FF t[TPT];
@@ -1299,7 +1337,12 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
             for (int uu = 0; uu < 8; ++uu) {
                 const MixedSrc q = lds[j + uu];
 #pragma unroll
-                for (int k = 0; k < TPT; ++k) pair_f32(q, t[k], fx[k], fy[k], fz[k]);
+                for (int k = 0; k < TPT; ++k) {
+                    if constexpr (FQ)
+                        pair_f32_unit(q, t[k], fx[k], fy[k], fz[k]);
+                    else
+                        pair_f32(q, t[k], fx[k], fy[k], fz[k]);
+                }
             }
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
@@ -1308,11 +1351,13 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
                 sz[k] += (double)fz[k];
             }
         }
+        // pair_f32_unit leaves out the -q_j factor
+        const double cs = FQ ? -uq * kMixedFieldScale : kMixedFieldScale;
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
-            Sx[k] = sx[k] * kMixedFieldScale;
-            Sy[k] = sy[k] * kMixedFieldScale;
-            Sz[k] = sz[k] * kMixedFieldScale;
+            Sx[k] = sx[k] * cs;
+            Sy[k] = sy[k] * cs;
+            Sz[k] = sz[k] * cs;
         }
     } else {
         FF t[TPT];
@@ -1333,17 +1378,18 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
                 float tx, ty, tz;
-                pair_f32_terms(q, t[k], tx, ty, tz);
+                pair_f32_terms<FQ>(q, t[k], tx, ty, tz);
                 kahan_add(tx, sx[k], cx[k]);
                 kahan_add(ty, sy[k], cy[k]);
                 kahan_add(tz, sz[k], cz[k]);
             }
         }
+        const double cs = FQ ? -uq * kMixedFieldScale : kMixedFieldScale;
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
-            Sx[k] = ((double)sx[k] - (double)cx[k]) * kMixedFieldScale;
-            Sy[k] = ((double)sy[k] - (double)cy[k]) * kMixedFieldScale;
-            Sz[k] = ((double)sz[k] - (double)cz[k]) * kMixedFieldScale;
+            Sx[k] = ((double)sx[k] - (double)cx[k]) * cs;
+            Sy[k] = ((double)sy[k] - (double)cy[k]) * cs;
+            Sz[k] = ((double)sz[k] - (double)cz[k]) * cs;
         }
     }
 }
@@ -1367,8 +1413,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  const int64_t* __restrict__ counter,
                                                  double* __restrict__ vacc,
                                                  double* __restrict__ vavg, int64_t n_pad,
-                                                 int nsteps, int accel_only) {
+                                                 int nsteps, int accel_only, double uq) {
     constexpr int KMAX = kMaxTrap / BLOCK;  // ions per owner thread at most
+    // uq != 0: every ion carries the charge uq (units of e); the FP64 pair sums
+    // then run over r^-3 d alone and are scaled by the charge once.  (The FP32
+    // loops without the charge multiply measured slower, 34.1 against 32.1 us
+    // per step of the 512-trap batch, so they keep it.)
+    const bool fq = PREC == 0 && uq != 0.0;
     using S = typename BatchSrc<PREC>::T;
     __shared__ S lds[kMaxTrap];
     __shared__ double red[3][BLOCK];
@@ -1431,12 +1482,15 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             sp[k] = 0;
         }
     }
-    // zero-charge padding of the source stream
+    // zero-charge padding of the source stream; with a common charge the sums
+    // weigh every source alike, so padding sits 1e6 m away, where its term is
+    // ~1e-20 of a neighbour's at 1e-4 m (below FP64 rounding)
+    const double pad = fq ? kFarPad : 0.0;
     for (int il = m + tid; il < m16; il += BLOCK) {
         if constexpr (PREC == 0) {
-            lds[il] = make_double4(0.0, 0.0, 0.0, 0.0);
+            lds[il] = make_double4(pad, pad, pad, 0.0);
         } else {
-            lds[il] = make_src(0.0, 0.0, 0.0, 0.0);
+            lds[il] = make_src(pad, pad, pad, 0.0);
         }
     }
 
@@ -1468,12 +1522,20 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             double Wx[4], Wy[4], Wz[4];
             if (wactive) {
                 if constexpr (TMAX >= 4) {
-                    if (TPT == 4)
-                        batch_pairs_multi<PREC, 4>(lds, m, wslot, WS, wjb, wje, Wx, Wy, Wz);
-                    else
-                        batch_pairs_multi<PREC, 2>(lds, m, wslot, WS, wjb, wje, Wx, Wy, Wz);
+                    if (TPT == 4) {
+                        if (fq)
+                            batch_pairs_multi<PREC, 4, true>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                        else
+                            batch_pairs_multi<PREC, 4, false>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                    } else if (fq) {
+                        batch_pairs_multi<PREC, 2, true>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                    } else {
+                        batch_pairs_multi<PREC, 2, false>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                    }
+                } else if (fq) {
+                    batch_pairs_multi<PREC, 2, true>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
                 } else {
-                    batch_pairs_multi<PREC, 2>(lds, m, wslot, WS, wjb, wje, Wx, Wy, Wz);
+                    batch_pairs_multi<PREC, 2, false>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
                 }
             }
 #pragma unroll
@@ -1505,55 +1567,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
         for (int k = 0; k < KMAX; ++k) {
             const int il = slot + IS * k;
             if (TPT > 1 || !active || il >= m) continue;
-            if constexpr (PREC == 0) {
-                const double4 me = lds[il];
-                double sx = 0.0, sy = 0.0, sz = 0.0;
-                for (int j = jb; j < je; j += 4) {
-                    pair_f64(lds[j], me.x, me.y, me.z, sx, sy, sz);
-                    pair_f64(lds[j + 1], me.x, me.y, me.z, sx, sy, sz);
-                    pair_f64(lds[j + 2], me.x, me.y, me.z, sx, sy, sz);
-                    pair_f64(lds[j + 3], me.x, me.y, me.z, sx, sy, sz);
-                }
-                Sx[k] = sx;
-                Sy[k] = sy;
-                Sz[k] = sz;
-            } else {
-                const MixedSrc* LM = lds;
-                const MixedSrc me = LM[il];
-                FF t;
-                t.xh = me.xh;
-                t.yh = me.yh;
-                t.zh = me.zh;
-                t.xl = me.xl;
-                t.yl = me.yl;
-                t.zl = me.zl;
-                if constexpr (PREC == 1) {
-                    double sx = 0.0, sy = 0.0, sz = 0.0;
-                    for (int j = jb; j < je; j += 8) {
-                        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-#pragma unroll
-                        for (int uu = 0; uu < 8; ++uu) pair_f32(LM[j + uu], t, fx, fy, fz);
-                        sx += (double)fx;
-                        sy += (double)fy;
-                        sz += (double)fz;
-                    }
-                    Sx[k] = sx * kMixedFieldScale;
-                    Sy[k] = sy * kMixedFieldScale;
-                    Sz[k] = sz * kMixedFieldScale;
-                } else {
-                    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-                    for (int j = jb; j < je; ++j) {
-                        float tx, ty, tz;
-                        pair_f32_terms(LM[j], t, tx, ty, tz);
-                        kahan_add(tx, sx, cx);
-                        kahan_add(ty, sy, cy);
-                        kahan_add(tz, sz, cz);
-                    }
-                    Sx[k] = ((double)sx - (double)cx) * kMixedFieldScale;
-                    Sy[k] = ((double)sy - (double)cy) * kMixedFieldScale;
-                    Sz[k] = ((double)sz - (double)cz) * kMixedFieldScale;
-                }
-            }
+            double W1x[4], W1y[4], W1z[4];
+            if (fq)
+                batch_pairs_multi<PREC, 1, true>(lds, m, il, IS, jb, je, uq, W1x, W1y, W1z);
+            else
+                batch_pairs_multi<PREC, 1, false>(lds, m, il, IS, jb, je, uq, W1x, W1y, W1z);
+            Sx[k] = W1x[0];
+            Sy[k] = W1y[0];
+            Sz[k] = W1z[0];
         }
         if (JP > 1 && TPT == 1) {
             // deterministic reduction over source parts: owners add parts in order
@@ -2043,31 +2064,31 @@ hipError_t pair_mixed_dispatch_l(const DevState& s, const LaunchShape& ls, int64
 }
 
 template <int PREC, int BLOCK, bool X>
-hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only,
+hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only, double uq,
                         hipStream_t st) {
     k_batch<PREC, BLOCK, X><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                        s.az, s.qm, s.qe, s.mass, s.species,
                                                        s.traps, s.cool, s.offsets, s.order,
                                                        s.counter, s.vacc, s.vavg, s.n_pad,
-                                                       nsteps, accel_only);
+                                                       nsteps, accel_only, uq);
     return hipGetLastError();
 }
 
 template <int PREC, bool X>
 hipError_t batch_dispatch_x(const DevState& s, int n_traps, int block, int nsteps,
-                            int accel_only, hipStream_t st) {
+                            int accel_only, double uq, hipStream_t st) {
     switch (block) {
-        case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, st);
-        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, st);
-        default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, st);
+        case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, uq, st);
+        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, uq, st);
+        default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, uq, st);
     }
 }
 
 template <int PREC>
 hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps, int accel_only,
-                          bool cool_on, hipStream_t st) {
-    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, block, nsteps, accel_only, st)
-                   : batch_dispatch_x<PREC, false>(s, n_traps, block, nsteps, accel_only, st);
+                          bool cool_on, double uq, hipStream_t st) {
+    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, block, nsteps, accel_only, uq, st)
+                   : batch_dispatch_x<PREC, false>(s, n_traps, block, nsteps, accel_only, uq, st);
 }
 
 }  // namespace
@@ -2264,9 +2285,9 @@ hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_t
                         const LaunchShape& ls, int nsteps, int, hipStream_t st) {
     (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, st);
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, st);
     }
 }
 
@@ -2274,9 +2295,9 @@ hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int
                               const LaunchShape& ls, hipStream_t st) {
     (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, false, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, false, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, false, st);
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, st);
     }
 }
 

@@ -369,8 +369,14 @@ def _small_batch(n_traps=24, seed=13, n_max=300):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
-def test_batch_accel_parity(torch_gpu, oracle_mod, prec):
+@pytest.mark.parametrize("charges", ["common", "mixed"])
+def test_batch_accel_parity(torch_gpu, oracle_mod, prec, charges):
+    """Batched field against the oracle for every workgroup size, with one
+    common charge (sums scaled by it once, padding placed far away) and with
+    per-ion charges."""
     w = _small_batch()
+    if charges == "mixed":
+        w.charge = np.random.default_rng(7).choice([1, 2, -1], w.n) * li.E_CHARGE
     traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
     r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
                                np.zeros(w.n_traps))
