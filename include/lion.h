@@ -287,8 +287,9 @@ typedef struct {
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
-                             LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 65536, bodies
-                             only by whole 256-ion tiles (else LION_ERR_UNSUPPORTED)          */
+                             LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 131072, bodies
+                             only by whole 256-ion tiles (else LION_ERR_UNSUPPORTED).  Built-in
+                             (0): each pair once where that is allowed and N >= 12288         */
     int32_t sym_variant;  /* pair-once kernel variant, 1..7 (built-in: 7 for
                              LION_MIXED_F64ACC, 6 for LION_FP64).  FP32 pairs: reaction sums
                              per chunk of 8 or 4 sources, sources unrolled, register budget,

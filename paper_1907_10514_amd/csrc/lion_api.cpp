@@ -76,7 +76,8 @@ int j_max_for(int64_t n) {
 }
 
 // Partial-sum slices the workspace holds: enough for any source split and, up
-// to kMaxSymTiles tiles, for the pair-once kernels (one slice per tile).
+// to kMaxSymTiles tiles, for the pair-once kernels (one slice per tile; at
+// N = 131072 that is 512 slices, 1.6 GB).
 int slices_for(int64_t n) {
     const int nb = lion::sym_tiles(n);
     return std::max(j_max_for(n), nb <= lion::kMaxSymTiles ? nb : 0);
@@ -160,8 +161,12 @@ void default_shape(lion_sim* s) {
     ls.batch_block = s->cfg.batch_block > 0 ? s->cfg.batch_block : 256;
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
     const int nb = lion::sym_tiles(n);
-    ls.symmetric = (s->cfg.symmetric == 2 && nb <= lion::kMaxSymTiles &&
-                    (!s->has_bodies || s->tile_bodies)) ? 1 : 0;
+    // pair-once kernels: when asked for, and by default for one trap of 12288 ions or
+    // more (48+ tiles: more tile pairs than workgroup slots), where they are faster
+    const bool sym_ok = nb <= lion::kMaxSymTiles && (!s->has_bodies || s->tile_bodies) &&
+                        !s->batched && s->precision != LION_MIXED_KAHAN;
+    const bool sym_default = s->cfg.symmetric <= 0 && n >= lion::kSymDefaultIons;
+    ls.symmetric = (sym_ok && (s->cfg.symmetric == 2 || sym_default)) ? 1 : 0;
     // built-in pair-once variant: the fastest measured (7 for FP32 pairs, 6 for FP64)
     ls.sym_variant = s->cfg.sym_variant > 0 ? s->cfg.sym_variant - 1 : (mixed ? 6 : 5);
     const int64_t n64 = round_up(n, 64);
@@ -1151,7 +1156,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->update_waves, {4, 8, 16})) return fail(s, LION_ERR_ARG, "update_waves must be 4, 8 or 16");
     if (!in(c->small_trap, {1, 2})) return fail(s, LION_ERR_ARG, "small_trap must be 1 or 2");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
-        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 65536");
+        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 131072");
     if (c->symmetric == 2 && s->has_bodies && !s->tile_bodies)
         return fail(s, LION_ERR_UNSUPPORTED,
                     "pair-once kernels exclude bodies by whole 256-ion tiles; these bodies share tiles");

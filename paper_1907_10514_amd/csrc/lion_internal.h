@@ -197,7 +197,8 @@ struct LaunchShape {
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the
 // epilogue then adds one partial per tile.
 inline int sym_tiles(int64_t n) { return (int)((n + 255) / 256); }
-constexpr int kMaxSymTiles = 256;
+constexpr int kMaxSymTiles = 512;
+constexpr int64_t kSymDefaultIons = 12288;  // pair-once by default from here (48 tiles)
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st);

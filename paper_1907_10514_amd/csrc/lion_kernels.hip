@@ -735,21 +735,25 @@ __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict
 
 constexpr int kSymTile = 256;
 
+// Row a of off-diagonal unit u: rows r < a hold S(a) = a (nb - 1) - a (a - 1) / 2
+// units, so a is the largest root bound of S(a) <= u, from the quadratic and
+// then corrected by whole steps (in FP32 the estimate is already exact for
+// nb <= 512, checked on the host for every unit).
 __device__ __forceinline__ void sym_unit(int nb, int& a, int& b) {
     const int off = nb * (nb - 1) / 2;
-    int u = blockIdx.x;
+    const int u = blockIdx.x;
     if (u >= off) {  // diagonal tiles, which skip the reaction sums, go last
         a = b = u - off;
         return;
     }
-    int row = 0, len = nb - 1;
-    while (u >= len) {
-        u -= len;
-        ++row;
-        --len;
-    }
-    a = row;
-    b = row + 1 + u;
+    auto rows_before = [nb](int r) { return r * (nb - 1) - r * (r - 1) / 2; };
+    const float c = (float)nb - 0.5f;
+    int r = (int)(c - sqrtf(fmaxf(c * c - 2.0f * (float)u, 0.0f)));
+    r = min(max(r, 0), nb - 2);
+    while (r + 1 <= nb - 2 && rows_before(r + 1) <= u) ++r;
+    while (r > 0 && rows_before(r) > u) --r;
+    a = r;
+    b = r + 1 + (u - rows_before(r));
 }
 
 // Rigid-body exclusion for the pair-once kernels.  tile_body[t] is the body of

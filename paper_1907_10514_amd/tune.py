@@ -93,13 +93,13 @@ def single_candidates(n: int, precision: int):
     if precision == L.LION_FP64:
         for i, j in itertools.product((1, 2, 4), js):
             yield dict(i_per_lane=i, j_split=j, symmetric=1)
-        if (n + 255) // 256 <= 256:
+        if (n + 255) // 256 <= 512:
             for v in (1, 2, 3, 5, 6, 7):
                 yield dict(symmetric=2, sym_variant=v)
     elif precision == L.LION_MIXED_F64ACC:
         for i, j, fl, lds in itertools.product((1, 2, 4), js, (8, 16), (1, 2)):
             yield dict(i_per_lane=i, j_split=j, flush_len=fl, lds_sources=lds, symmetric=1)
-        if (n + 255) // 256 <= 256:
+        if (n + 255) // 256 <= 512:
             for v in (1, 2, 4, 5, 6, 7):
                 yield dict(symmetric=2, sym_variant=v)
     else:

@@ -629,10 +629,12 @@ def test_pair_once_rigid_steps(torch_gpu, oracle_mod):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_pair_once_above_32768(torch_gpu, oracle_mod, prec):
-    """Pair-once kernels at 40000 ions (157 tiles, one partial per tile):
-    sampled targets against the oracle, and 5 steps against all-pairs."""
-    w = li.random_cloud(40000, seed=55, sigma=200e-6, light_fraction=0.2)
+@pytest.mark.parametrize("n", [40000, 100000])
+def test_pair_once_above_32768(torch_gpu, oracle_mod, prec, n):
+    """Pair-once kernels at 40000 and 100000 ions (157 and 391 tiles, one
+    partial per tile): sampled targets against the oracle, and 5 steps against
+    all-pairs."""
+    w = li.random_cloud(n, seed=55, sigma=200e-6, light_fraction=0.2)
     tr = _oracle_trap(oracle_mod, w.traps[0])
     sim = _sim(w, prec, oracle_mod, symmetric=2)
     assert sim.config()["symmetric"] == 2
@@ -640,7 +642,7 @@ def test_pair_once_above_32768(torch_gpu, oracle_mod, prec):
     idx = np.random.default_rng(6).choice(w.n, 256, replace=False)
     rx, ry, rz, sc = oracle_mod.accel_at(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0, idx)
     err = _m1((a[0][idx], a[1][idx], a[2][idx]), (rx, ry, rz), sc)
-    print(f"pair-once N=40000 {prec} sampled M1={err:.3e}")
+    print(f"pair-once N={n} {prec} sampled M1={err:.3e}")
     assert err <= TOL[prec]
     outs = []
     for s2 in (sim, _sim(w, prec, oracle_mod, symmetric=1)):
