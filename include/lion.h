@@ -103,13 +103,12 @@ int lion_set_trap(lion_sim *sim, int32_t trap, double V_rf, double Omega_rad_s, 
  * of ions with the same body id are left out of the pair sum.  NULL (or all
  * -1) clears the mask.  Ions keep per-ion integration (lion_set_rigid_bodies
  * adds rigid integration); energies still count every pair.  Fastest when each
- * body's ions are consecutive in index order.  Single-trap handles only.  The
- * pair-once kernels (lion_kernel_config.symmetric = 2) exclude whole tile pairs,
- * so they need every 256-ion tile (ions 256 t .. 256 t + 255) to hold ions of
- * one body only or no body ions; other layouts use the all-pairs kernels, and
- * asking for pair-once with them gives LION_ERR_UNSUPPORTED.  Batched handles
- * -> LION_ERR_UNSUPPORTED; ids < -1 -> LION_ERR_ARG.  Recomputes the cached
- * accelerations. */
+ * body's ions are consecutive in index order.  Single-trap handles only.  In
+ * the pair-once kernels (lion_kernel_config.symmetric = 2) a pair of 256-ion
+ * tiles (ions 256 t .. 256 t + 255) that both hold ions of one body only is
+ * skipped; tile pairs whose body ids may meet compare body ids per pair.
+ * Batched handles -> LION_ERR_UNSUPPORTED; ids < -1 -> LION_ERR_ARG.
+ * Recomputes the cached accelerations. */
 int lion_set_bodies(lion_sim *sim, const int32_t *body_id);
 
 /* Laser cooling (section "Cooling the motion of ions") as an isotropic viscous
@@ -287,9 +286,9 @@ typedef struct {
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
-                             LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 131072, bodies
-                             only by whole 256-ion tiles (else LION_ERR_UNSUPPORTED).  Built-in
-                             (0): each pair once where that is allowed and N >= 12288         */
+                             LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 131072 (else
+                             LION_ERR_UNSUPPORTED).  Built-in (0): each pair once where that is
+                             allowed and N >= 12288                                           */
     int32_t sym_variant;  /* pair-once kernel variant, 1..7 (built-in: 7 for
                              LION_MIXED_F64ACC, 6 for LION_FP64).  FP32 pairs: reaction sums
                              per chunk of 8 or 4 sources, sources unrolled, register budget,

@@ -50,7 +50,7 @@ struct lion_sim {
     Bath baths[lion::kMaxBaths] = {};
     lion::CoolDev cool{};
     char* ws = nullptr;
-    size_t body_off[4] = {0, 0, 0, 0};
+    size_t body_off[5] = {0, 0, 0, 0, 0};
     bool tile_bodies = false;  // every 256-ion tile holds ions of one body only, or none
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (chunk length, kind)
     std::string err;
@@ -85,7 +85,7 @@ int slices_for(int64_t n) {
 
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
-        flags, body_code, tile_body, body_gmin, body_gmax, cool, species, vacc, vavg, rigid, rb, dbody,
+        flags, body_code, tile_body, tile_brange, body_gmin, body_gmax, cool, species, vacc, vavg, rigid, rb, dbody,
         rmembers, rstart, minst, minpart, total;
 };
 
@@ -115,6 +115,7 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.flags = take(4 * sizeof(int32_t));
     L.body_code = take(np * sizeof(int32_t));
     L.tile_body = take(np / 256 * sizeof(int32_t));
+    L.tile_brange = take(2 * (np / 256) * sizeof(int32_t));
     L.body_gmin = take(np / 16 * sizeof(int32_t));
     L.body_gmax = take(np / 16 * sizeof(int32_t));
     L.cool = take(sizeof(lion::CoolDev));
@@ -163,10 +164,12 @@ void default_shape(lion_sim* s) {
     const int nb = lion::sym_tiles(n);
     // pair-once kernels: when asked for, and by default for one trap of 12288 ions or
     // more (48+ tiles: more tile pairs than workgroup slots), where they are faster
-    const bool sym_ok = nb <= lion::kMaxSymTiles && (!s->has_bodies || s->tile_bodies) &&
-                        !s->batched && s->precision != LION_MIXED_KAHAN;
+    const bool sym_ok = nb <= lion::kMaxSymTiles && !s->batched &&
+                        s->precision != LION_MIXED_KAHAN;
     const bool sym_default = s->cfg.symmetric <= 0 && n >= lion::kSymDefaultIons;
     ls.symmetric = (sym_ok && (s->cfg.symmetric == 2 || sym_default)) ? 1 : 0;
+    // bodies that share tiles with other ions need the per-pair test in those kernels
+    ls.sym_masked = (ls.symmetric && s->has_bodies && !s->tile_bodies) ? 1 : 0;
     // built-in pair-once variant: the fastest measured (7 for FP32 pairs, 6 for FP64)
     ls.sym_variant = s->cfg.sym_variant > 0 ? s->cfg.sym_variant - 1 : (mixed ? 6 : 5);
     const int64_t n64 = round_up(n, 64);
@@ -468,12 +471,15 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     s->rigid_off[4] = L.rstart;
     d.body_code = nullptr;  // set by lion_set_bodies
     d.tile_body = nullptr;
+    d.tile_bmin = nullptr;
+    d.tile_bmax = nullptr;
     d.body_gmin = nullptr;
     d.body_gmax = nullptr;
     s->body_off[0] = L.body_code;
     s->body_off[1] = L.body_gmin;
     s->body_off[2] = L.body_gmax;
     s->body_off[3] = L.tile_body;
+    s->body_off[4] = L.tile_brange;
     s->ws = base;
     s->j_max = batched ? 1 : j_max_for(n);
     s->cfg.chunk_steps = 100;
@@ -718,19 +724,25 @@ int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
             any = any || body_id[i] >= 0;
         }
     }
-    // pair-once kernels exclude whole tile pairs: every 256-ion tile must hold
-    // ions of one body only, or no body ions
+    // pair-once kernels: a tile pair inside one body is skipped whole; tiles of
+    // one body only ("aligned" when every tile is such or free) need no per-pair
+    // test, other tile pairs whose body-id ranges meet take it
     const int nb = lion::sym_tiles(n);
-    std::vector<int32_t> tb(np / 256, -1);
+    std::vector<int32_t> tb(np / 256, -1), tmin(np / 256, INT32_MAX), tmax(np / 256, -1);
     bool aligned = any;
-    for (int t = 0; t < nb && aligned; ++t) {
+    for (int t = 0; t < nb && any; ++t) {
         const int64_t lo = (int64_t)t * 256, hi = std::min<int64_t>(n, lo + 256);
-        tb[t] = body_id[lo];
-        for (int64_t i = lo + 1; i < hi; ++i) aligned = aligned && body_id[i] == tb[t];
+        bool pure = body_id[lo] >= 0;
+        for (int64_t i = lo; i < hi; ++i) {
+            pure = pure && body_id[i] == body_id[lo];
+            if (body_id[i] >= 0) {
+                tmin[t] = std::min(tmin[t], body_id[i]);
+                tmax[t] = std::max(tmax[t], body_id[i]);
+            }
+        }
+        tb[t] = pure ? body_id[lo] : -1;
+        aligned = aligned && (pure || tmax[t] < 0);
     }
-    if (s->cfg.symmetric == 2 && any && !aligned)
-        return fail(s, LION_ERR_UNSUPPORTED,
-                    "pair-once kernels exclude bodies by whole 256-ion tiles; these bodies share tiles");
     LION_HIP(s, hipSetDevice(s->device));
     (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);  // captured launches carry the mask pointers
@@ -739,6 +751,7 @@ int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
         s->has_bodies = false;
         s->tile_bodies = false;
         s->d.body_code = s->d.body_gmin = s->d.body_gmax = s->d.tile_body = nullptr;
+        s->d.tile_bmin = s->d.tile_bmax = nullptr;
         default_shape(s);
         return s->state_set ? refresh_accel(s) : LION_OK;
     }
@@ -759,12 +772,17 @@ int lion_set_bodies(lion_sim* s, const int32_t* body_id) {
     LION_HIP(s, hipMemcpyAsync(dmin, gmin.data(), np / 16 * 4, hipMemcpyHostToDevice, st));
     LION_HIP(s, hipMemcpyAsync(dmax, gmax.data(), np / 16 * 4, hipMemcpyHostToDevice, st));
     int32_t* dtb = (int32_t*)(s->ws + s->body_off[3]);
-    if (aligned) LION_HIP(s, hipMemcpyAsync(dtb, tb.data(), np / 256 * 4, hipMemcpyHostToDevice, st));
+    int32_t* dtr = (int32_t*)(s->ws + s->body_off[4]);
+    LION_HIP(s, hipMemcpyAsync(dtb, tb.data(), np / 256 * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(dtr, tmin.data(), np / 256 * 4, hipMemcpyHostToDevice, st));
+    LION_HIP(s, hipMemcpyAsync(dtr + np / 256, tmax.data(), np / 256 * 4, hipMemcpyHostToDevice, st));
     LION_HIP(s, hipStreamSynchronize(st));
     s->d.body_code = dc;
     s->d.body_gmin = dmin;
     s->d.body_gmax = dmax;
-    s->d.tile_body = aligned ? dtb : nullptr;
+    s->d.tile_body = dtb;
+    s->d.tile_bmin = dtr;
+    s->d.tile_bmax = dtr + np / 256;
     s->tile_bodies = aligned;
     s->has_bodies = true;
     default_shape(s);
@@ -1157,9 +1175,6 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->small_trap, {1, 2})) return fail(s, LION_ERR_ARG, "small_trap must be 1 or 2");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 131072");
-    if (c->symmetric == 2 && s->has_bodies && !s->tile_bodies)
-        return fail(s, LION_ERR_UNSUPPORTED,
-                    "pair-once kernels exclude bodies by whole 256-ion tiles; these bodies share tiles");
     if (c->symmetric == 2 && s->precision == LION_MIXED_KAHAN)
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels exist for FP64 and MIXED_F64ACC");
     (void)hipSetDevice(s->device);

@@ -174,7 +174,9 @@ struct DevState {
     int32_t* rstart;     // [nbodies + 1]
     // rigid-body exclusion (all NULL when no bodies are set)
     int32_t* body_code;  // [n_pad] body id >= 0, or -1 - i for a free ion i
-    int32_t* tile_body;  // [n_pad / 256] body of every ion of a 256-ion tile, or -1 (no body ions)
+    int32_t* tile_body;  // [n_pad / 256] body of every ion of a 256-ion tile, or -1 (none, or several)
+    int32_t* tile_bmin;  // [n_pad / 256] smallest body id >= 0 in a tile (INT32_MAX: none)
+    int32_t* tile_bmax;  // [n_pad / 256] largest body id in a tile (-1: none)
     int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions
     int32_t* body_gmax;  // [n_pad / 16] largest body id (-1 if none)
 };
@@ -192,6 +194,7 @@ struct LaunchShape {
     int small_path;   // single trap stepped by the one-workgroup kernel (k_batch, one trap)
     bool cool_on;     // a beam, bath or time average is on: the kernels built with them run
     double uniform_q;  // every ion's charge in units of e when all are equal, else 0
+    int sym_masked;    // pair-once kernels with the per-pair body test (bodies share tiles)
 };
 
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the

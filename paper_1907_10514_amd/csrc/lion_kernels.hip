@@ -782,6 +782,17 @@ __device__ __forceinline__ void sym_unit_zero(double* __restrict__ part, int64_t
     }
 }
 
+// Body ids per tile for the masked pair-once path: tile pairs whose body-id
+// ranges meet take the per-pair test, the others the plain loop.
+struct BodyTiles {
+    const int32_t* __restrict__ code = nullptr;  // [n_pad] body id, or -1 - i for free ion i
+    const int32_t* __restrict__ tmin = nullptr;  // [tiles] smallest body id >= 0 in the tile
+    const int32_t* __restrict__ tmax = nullptr;  // [tiles] largest (tmin > tmax: none)
+    __device__ bool may_share(int a, int b) const {
+        return tmin[a] <= tmax[b] && tmin[b] <= tmax[a];
+    }
+};
+
 // Sum over the 64 lanes of a wave of C columns held lane-major in buf[64][S]
 // (S = C + 1: consecutive lanes write consecutive rows, and a column read by
 // consecutive lanes touches consecutive banks).  P lanes per column each add
@@ -876,17 +887,22 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
 // FQ: every ion of the tile pair carries the same charge uq (in units of e), so
 // the per-pair charge factors are applied once per sum instead (an exact
 // refactoring; tiles holding zero-charge padding ions take the general path).
-template <int L, int CH, int UNR, bool PF, bool FQ>
+// MK: some pairs of the tile pair belong to one rigid body; code[i] is ion i's
+// body id (or a number unique to a free ion) and a pair of equal codes adds 0.
+template <int L, int CH, int UNR, bool PF, bool FQ, bool MK = false>
 __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm, int64_t n,
                                                int nb, int64_t n_pad, double* __restrict__ part,
                                                int a, int b, float uq, float4* tile,
-                                               double* smem) {
+                                               double* smem,
+                                               const int32_t* __restrict__ code = nullptr,
+                                               int32_t* tcode = nullptr) {
     constexpr int S = CH * 3 + 1;  // row stride of the lane-major reaction buffer
     const bool diag = (a == b);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t base = (int64_t)a * kSymTile + lane;
     FF t[4];
     float qi[4];
+    int32_t ci[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const MixedSrc m = srcm[base + 64 * k];
@@ -897,13 +913,16 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
         t[k].yl = m.yl;
         t[k].zl = m.zl;
         qi[k] = -m.nq;
+        ci[k] = MK ? code[base + 64 * k] : 0;
     }
     {
         const float4* __restrict__ g = reinterpret_cast<const float4*>(srcm) + 2 * (int64_t)b * kSymTile;
         for (int q = threadIdx.x; q < 2 * kSymTile; q += 256) tile[q] = g[q];
+        if constexpr (MK) tcode[threadIdx.x] = code[(int64_t)b * kSymTile + threadIdx.x];
     }
     __syncthreads();
     const MixedSrc* mine = reinterpret_cast<const MixedSrc*>(tile) + wave * 64;
+    const int32_t* mcode = MK ? tcode + wave * 64 : nullptr;
     double sx[4], sy[4], sz[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) sx[k] = sy[k] = sz[k] = 0.0;
@@ -924,6 +943,7 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
                 m = mine[s0 + uu];
             }
             float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+            const int32_t cj = MK ? mcode[s0 + uu] : 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const float dx = (m.xh - t[k].xh) + (m.xl - t[k].xl);
@@ -931,7 +951,7 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
                 const float dz = (m.zh - t[k].zh) + (m.zl - t[k].zl);
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, m.r2floor)));
                 const float y = __builtin_amdgcn_rsqf(r2);
-                const float y3 = (y * y) * y;
+                const float y3 = (MK && ci[k] == cj) ? 0.0f : (y * y) * y;
                 const float wi = FQ ? y3 : m.nq * y3;  // -q_j r^-3 (times -1/uq with FQ)
                 fx[k] = fmaf(wi, dx, fx[k]);
                 fy[k] = fmaf(wi, dy, fy[k]);
@@ -987,11 +1007,13 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
 
 // uq != 0: every ion carries the charge uq (units of e) and tiles below
 // full_tiles hold no padding; those tile pairs take the charge-free loop.
-template <int L, int CH, int WPE, int UNR, bool PF = false>
+template <int L, int CH, int WPE, int UNR, bool PF = false, bool MK = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
                       double* __restrict__ part, int64_t* __restrict__ counter, float uq,
-                      int full_tiles, const int32_t* __restrict__ tile_body) {
+                      int full_tiles, const int32_t* __restrict__ tile_body,
+                      const BodyTiles bt = BodyTiles{}) {
+    __shared__ int32_t tcode[MK ? kSymTile : 1];
     __shared__ float4 tile[2 * kSymTile];
     // per-wave reaction buffers, reused for the final target-side reduction
     constexpr int S = CH * 3 + 1;
@@ -1002,6 +1024,9 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
     sym_unit(nb, a, b);
     if (sym_unit_excluded(tile_body, a, b))
         sym_unit_zero(part, n, n_pad, a, b);
+    else if (MK && bt.may_share(a, b))
+        mixed_sym_body<L, CH, UNR, PF, false, true>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem,
+                                                    bt.code, tcode);
     else if (uq != 0.0f && b < full_tiles)
         mixed_sym_body<L, CH, UNR, PF, true>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
     else
@@ -1012,11 +1037,12 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
 // One tile pair (a, b) of the FP64 pair-once kernel.  With FQ every ion in
 // both tiles carries the charge uq: the sums run over c d alone and are scaled
 // by the charge once, at the end.
-template <int UNR, bool PF, bool FQ>
+template <int UNR, bool PF, bool FQ, bool MK = false>
 __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
                                              const double* __restrict__ qe, int64_t n,
                                              int64_t n_pad, double* __restrict__ part, int a,
-                                             int b, double uq, double* smem) {
+                                             int b, double uq, double* smem,
+                                             const int32_t* __restrict__ code = nullptr) {
     constexpr int CH = 4;
     constexpr int S = CH * 3 + 1;
     const bool diag = (a == b);
@@ -1024,6 +1050,7 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t base = (int64_t)a * kSymTile + lane;
     double xi[4], yi[4], zi[4], nqi[4], sx[4], sy[4], sz[4];
+    int32_t ci[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const double4 p = src[base + 64 * k];
@@ -1031,6 +1058,7 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
         yi[k] = p.y;
         zi[k] = p.z;
         nqi[k] = FQ ? 0.0 : -1.5 * qe[base + 64 * k];
+        ci[k] = MK ? code[base + 64 * k] : 0;
         sx[k] = sy[k] = sz[k] = 0.0;
     }
     double* jb = smem + wave * 64 * S;
@@ -1048,6 +1076,7 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
                 p = src[j0 + s0 + uu];
             }
             double tx = 0.0, ty = 0.0, tz = 0.0;
+            const int32_t cj = MK ? code[j0 + s0 + uu] : 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const double dx = p.x - xi[k], dy = p.y - yi[k], dz = p.z - zi[k];
@@ -1055,7 +1084,8 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
                 const double y = __builtin_amdgcn_rsq(r2);
                 const double a2 = y * y;
                 const double g = fma(r2, a2, -5.0 / 3.0);
-                const double c = (a2 * y) * g;        // -(2/3) r^-3 (one Newton correction)
+                // -(2/3) r^-3 (one Newton correction); 0 for a pair inside one body
+                const double c = (MK && ci[k] == cj) ? 0.0 : (a2 * y) * g;
                 const double wi = FQ ? c : c * p.w;  // 1.5 q_j c = -q_j r^-3
                 sx[k] = fma(wi, dx, sx[k]);
                 sy[k] = fma(wi, dy, sy[k]);
@@ -1103,12 +1133,12 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
 // WPE: the occupancy the register allocation aims at; UNR: sources unrolled.
 // uq != 0: every ion carries the charge uq (units of e) and tiles below
 // full_tiles hold no padding; those tile pairs take the charge-free loop.
-template <int WPE, int UNR, bool PF = false>
+template <int WPE, int UNR, bool PF = false, bool MK = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ qe, int64_t n,
                     int nb, int64_t n_pad, double* __restrict__ part,
                     int64_t* __restrict__ counter, double uq, int full_tiles,
-                    const int32_t* __restrict__ tile_body) {
+                    const int32_t* __restrict__ tile_body, const BodyTiles bt = BodyTiles{}) {
     constexpr int S = 4 * 3 + 1;
     __shared__ double smem[kWaves * 64 * S];
     static_assert(kWaves * 64 * S >= (kWaves - 1) * 3 * 64 * 4, "LDS reuse too small");
@@ -1116,6 +1146,8 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
     sym_unit(nb, a, b);
     if (sym_unit_excluded(tile_body, a, b))
         sym_unit_zero(part, n, n_pad, a, b);
+    else if (MK && bt.may_share(a, b))
+        f64_sym_body<UNR, PF, false, true>(src, qe, n, n_pad, part, a, b, uq, smem, bt.code);
     else if (uq != 0.0 && b < full_tiles)
         f64_sym_body<UNR, PF, true>(src, qe, n, n_pad, part, a, b, uq, smem);
     else
@@ -2124,6 +2156,17 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
         const double uq = ls.uniform_q;                // 0: charges differ
         const int full = (int)(s.n / kSymTile);        // tiles without padding
         const int32_t* tb = s.body_code ? s.tile_body : nullptr;  // exclusion by whole tiles
+        if (ls.sym_masked) {
+            // bodies share tiles with other ions: the built-in variants with the per-pair test
+            const BodyTiles bt{s.body_code, s.tile_bmin, s.tile_bmax};
+            if (precision == 0)
+                k_pair_f64_sym<4, 1, true, true><<<units, 256, 0, st>>>(
+                    s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb, bt);
+            else
+                k_pair_mixed_sym<8, 8, 4, 2, true, true><<<units, 256, 0, st>>>(
+                    s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb, bt);
+            return hipGetLastError();
+        }
         if (precision == 0) {
             switch (ls.sym_variant) {
                 case 1:

@@ -561,8 +561,11 @@ def test_body_exclusion_parity(torch_gpu, oracle_mod, prec, contiguous):
     rx, ry, rz, sc = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0)
     sim = _sim(w, prec, oracle_mod)
     sim.set_bodies(body)
-    for cfg in ([dict()] + [dict(i_per_lane=i, j_split=j, lds_sources=l)
-                            for i in (1, 4) for j in (1, 7) for l in (1, 2)]):
+    cfgs = [dict()] + [dict(i_per_lane=i, j_split=j, lds_sources=l, symmetric=1)
+                       for i in (1, 4) for j in (1, 7) for l in (1, 2)]
+    if prec != "mixed_kahan":
+        cfgs.append(dict(symmetric=2))  # pair-once kernels with the per-pair body test
+    for cfg in cfgs:
         if cfg:
             sim.set_config(**cfg)
         err = _m1(sim.compute_accel(), (rx, ry, rz), sc)
@@ -607,6 +610,50 @@ def test_pair_once_tile_aligned_bodies(torch_gpu, oracle_mod, prec, charges):
     print(f"tile bodies {prec} {charges}: M1={err:.3e} vs masked all-pairs {err_all:.3e}")
     assert err <= TOL[prec]
     assert err_all <= 2 * TOL[prec]
+    sym.close()
+    allp.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pair_once_bodies_sharing_tiles(torch_gpu, oracle_mod, prec):
+    """13000 ions (pair-once by default) with clusters that straddle tile
+    edges: tile pairs inside one body are skipped, pairs of tiles whose bodies
+    may meet take the per-pair test, the rest the plain loop.  Sampled
+    targets against the oracle, the field against the masked all-pairs
+    kernels, and (FP64) 20 rigid steps against them."""
+    n = 13000
+    w = li.random_cloud(n, seed=57, sigma=200e-6, light_fraction=0.2)
+    body = np.full(n, -1, dtype=np.int32)
+    for k, start in enumerate(range(100, 100 + 12 * 600, 600)):
+        body[start:start + 512] = k  # 512-ion clusters starting off tile edges
+    body[9000:9040] = 99             # a small body inside one tile
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    sym = _sim(w, prec, oracle_mod)
+    sym.set_bodies(body)
+    assert sym.config()["symmetric"] == 2
+    a = sym.compute_accel()
+    idx = np.concatenate([np.arange(95, 105), np.arange(600, 620), np.arange(9000, 9040),
+                          np.random.default_rng(8).choice(n, 128, replace=False)])
+    rx, ry, rz, sc = oracle_mod.accel_bodies_at(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0,
+                                                idx)
+    err = _m1((a[0][idx], a[1][idx], a[2][idx]), (rx, ry, rz), sc)
+    allp = _sim(w, prec, oracle_mod, symmetric=1)
+    allp.set_bodies(body)
+    b = allp.compute_accel()
+    scale = oracle_mod.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0)[3]
+    err_all = _m1(a, b, scale)
+    print(f"bodies sharing tiles {prec}: M1={err:.3e} vs masked all-pairs {err_all:.3e}")
+    assert err <= TOL[prec]
+    assert err_all <= 2 * TOL[prec]
+    if prec == "fp64":  # rigid stepping on both kernels agrees to round-off
+        outs = []
+        for s2 in (sym, allp):
+            s2.set_rigid_bodies(body)
+            s2.step(20, w.traps[0].dt)
+            outs.append(s2.get_state()[0])
+        ext = np.max(np.abs(w.x))
+        for k in ("x", "y", "z"):
+            assert np.max(np.abs(outs[0][k] - outs[1][k])) < 1e-11 * ext, k
     sym.close()
     allp.close()
 
@@ -690,20 +737,21 @@ def test_bodies_rejected_where_unsupported(torch_gpu, oracle_mod):
     shared = np.full(300, -1, dtype=np.int32)
     shared[:100] = 0  # body 0 shares the first 256-ion tile with free ions
     sim = _sim(w, "mixed", oracle_mod, symmetric=2)
-    with pytest.raises(LionError) as ei:
-        sim.set_bodies(shared)
-    assert ei.value.code == L.LION_ERR_UNSUPPORTED
-    sim.set_bodies(np.zeros(300, dtype=np.int32))  # whole tiles: accepted
+    sim.set_bodies(shared)  # per-pair test inside the pair-once kernels
+    assert sim.config()["symmetric"] == 2
+    sim.set_bodies(np.zeros(300, dtype=np.int32))  # whole tiles: tile pairs skipped
     assert sim.config()["symmetric"] == 2
     sim.set_config(symmetric=1)
     with pytest.raises(LionError) as ei:
         sim.set_bodies(np.full(300, -2, dtype=np.int32))
     assert ei.value.code == L.LION_ERR_ARG
-    sim.set_bodies(shared)
-    with pytest.raises(LionError) as ei:
-        sim.set_config(symmetric=2)
-    assert ei.value.code == L.LION_ERR_UNSUPPORTED
     sim.close()
+    k = _sim(w, "mixed_kahan", oracle_mod)
+    k.set_bodies(shared)
+    with pytest.raises(LionError) as ei:
+        k.set_config(symmetric=2)
+    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    k.close()
     b = _small_batch(n_traps=3, seed=5, n_max=20)
     bs = _sim(b, "fp64", oracle_mod)
     with pytest.raises(LionError) as ei:
