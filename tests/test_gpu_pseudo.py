@@ -30,10 +30,12 @@ def _pseudo(oracle, q_x=0.3, a_x=-0.001):
                        pseudo=True)
 
 
-def _sim(mass, charge, prec, tr, st, gamma=0.0, n_per_trap=None):
+def _sim(mass, charge, prec, tr, st, gamma=0.0, n_per_trap=None, **cfg):
     from paper_1907_10514_amd import Simulation
 
     sim = Simulation(mass, charge, prec, n_per_trap=n_per_trap)
+    if cfg:
+        sim.set_config(**cfg)
     sim.set_pseudo_trap(tr.V0, tr.Omega, tr.U0, tr.R0, tr.Z0, tr.kappa)
     sim.set_damping(gamma)
     sim.set_state(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], 0.0)
@@ -49,13 +51,15 @@ def _length_scale(tr):
     return (E * E / (4 * math.pi * analytic.EPS0 * CA * wz2)) ** (1 / 3), CA * wz2
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+@pytest.mark.parametrize("prec,sym", [("fp64", 1), ("mixed", 1), ("mixed_kahan", 1),
+                                      ("fp64", 2), ("mixed", 2)])
 @pytest.mark.parametrize("n", [1, 257, 4097])
-def test_pseudo_accel_parity(torch_gpu, oracle_mod, n, prec):
-    """Two species in the pseudopotential trap: one force evaluation."""
+def test_pseudo_accel_parity(torch_gpu, oracle_mod, n, prec, sym):
+    """Two species in the pseudopotential trap: one force evaluation, on the
+    all-pairs (sym 1) and the pair-once (sym 2) kernels."""
     w = li.random_cloud(n, seed=400 + n, sigma=60e-6, light_fraction=0.3)
     tr = _pseudo(oracle_mod)
-    sim = _sim(w.mass, w.charge, prec, tr, w.state())
+    sim = _sim(w.mass, w.charge, prec, tr, w.state(), symmetric=sym)
     a = sim.compute_accel()
     r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
     sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
@@ -126,18 +130,19 @@ def _chain_start(n, seed):
 
 
 @pytest.mark.parametrize("prec,ftol,tol", [("fp64", 1e-10, 1e-8), ("mixed", 1e-5, 1e-4)])
-@pytest.mark.parametrize("n", [2, 5, 10])
-def test_minimised_chain(torch_gpu, oracle_mod, n, prec, ftol, tol):
+@pytest.mark.parametrize("n,sym", [(2, 1), (5, 1), (10, 1), (10, 2)])
+def test_minimised_chain(torch_gpu, oracle_mod, n, sym, prec, ftol, tol):
     """Minimising from a scattered start gives the linear chain: sorted axial
     positions equal the Newton roots of the axial force balance (and the
-    oracle's minimiser).  The FP32 pair path cannot resolve forces below ~1e-7
-    of the force scale, so it stops at a looser force tolerance."""
+    oracle's minimiser), on the all-pairs and the pair-once kernels.  The FP32
+    pair path cannot resolve forces below ~1e-7 of the force scale, so it
+    stops at a looser force tolerance."""
     tr = _pseudo(oracle_mod)
     l, k = _length_scale(tr)
     fu = k * l
     st = _chain_start(n, seed=n)
     m, q = np.full(n, CA), np.full(n, E)
-    sim = _sim(m, q, prec, tr, st)
+    sim = _sim(m, q, prec, tr, st, symmetric=sym)
     it, fmax = sim.minimize(dt=2e-8, dmax=1e-6, ftol=ftol * fu, max_iter=200000)
     got, _ = sim.get_state()
     assert fmax <= ftol * fu
