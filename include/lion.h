@@ -286,11 +286,13 @@ typedef struct {
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
-                             LION_FP64 and LION_MIXED_F64ACC, one trap of N <= 131072 (else
-                             LION_ERR_UNSUPPORTED).  Built-in (0): each pair once where that is
-                             allowed and N >= 12288                                           */
+                             one trap of N <= 131072 (else LION_ERR_UNSUPPORTED).  Built-in
+                             (0): each pair once where that is allowed and N >= 12288.  With
+                             LION_MIXED_KAHAN the FP32 runs of each 256 x 256 tile pair are
+                             added in compensated FP32 and the tile-pair totals in FP64       */
     int32_t sym_variant;  /* pair-once kernel variant, 1..7 (built-in: 7 for
-                             LION_MIXED_F64ACC, 6 for LION_FP64).  FP32 pairs: reaction sums
+                             LION_MIXED_F64ACC, 6 for LION_FP64; LION_MIXED_KAHAN always
+                             runs the shape of 7).  FP32 pairs: reaction sums
                              per chunk of 8 or 4 sources, sources unrolled, register budget,
                              next source prefetched: 1: 8, two, 4 waves/SIMD; 2: 4, one,
                              5 waves; 3: 4, one, 6 waves; 4: 8, one, 5-wave budget; 5: 4, one,

@@ -164,8 +164,7 @@ void default_shape(lion_sim* s) {
     const int nb = lion::sym_tiles(n);
     // pair-once kernels: when asked for, and by default for one trap of 12288 ions or
     // more (48+ tiles: more tile pairs than workgroup slots), where they are faster
-    const bool sym_ok = nb <= lion::kMaxSymTiles && !s->batched &&
-                        s->precision != LION_MIXED_KAHAN;
+    const bool sym_ok = nb <= lion::kMaxSymTiles && !s->batched;
     const bool sym_default = s->cfg.symmetric <= 0 && n >= lion::kSymDefaultIons;
     ls.symmetric = (sym_ok && (s->cfg.symmetric == 2 || sym_default)) ? 1 : 0;
     // bodies that share tiles with other ions need the per-pair test in those kernels
@@ -1175,8 +1174,6 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->small_trap, {1, 2})) return fail(s, LION_ERR_ARG, "small_trap must be 1 or 2");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 131072");
-    if (c->symmetric == 2 && s->precision == LION_MIXED_KAHAN)
-        return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels exist for FP64 and MIXED_F64ACC");
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);

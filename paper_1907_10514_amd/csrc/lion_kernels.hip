@@ -802,7 +802,7 @@ struct BodyTiles {
 // roundings) and the run totals in FP64, the same FP32-run / FP64-flush rule
 // as the target sums.  The column total ends up in lanes with
 // (lane % P) == 0, column = lane / P.
-template <int C, int P, typename T>
+template <int C, int P, typename T, bool KH = false>
 __device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int lane) {
     static_assert(C * P <= 64 && (P == 2 || P == 4), "bad column split");
     constexpr int E = 64 / P, S = C + 1;
@@ -820,10 +820,18 @@ __device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int la
                 const float s45 = r[4 * S] + r[5 * S], s67 = r[6 * S] + r[7 * S];
                 run[g] = (double)((s01 + s23) + (s45 + s67));
             }
-            acc0 = run[0];
-            acc1 = run[1];
-            acc2 = run[2];
-            acc3 = run[3];
+            if constexpr (KH) {
+                // compensated FP32 sum of the run totals (the compensated mode)
+                float ks = 0.0f, kc = 0.0f;
+#pragma unroll
+                for (int g = 0; g < E / 8; ++g) kahan_add((float)run[g], ks, kc);
+                acc0 = (double)ks - (double)kc;
+            } else {
+                acc0 = run[0];
+                acc1 = run[1];
+                acc2 = run[2];
+                acc3 = run[3];
+            }
         } else {
 #pragma unroll
             for (int e = 0; e < E; e += 4) {
@@ -889,7 +897,9 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
 // refactoring; tiles holding zero-charge padding ions take the general path).
 // MK: some pairs of the tile pair belong to one rigid body; code[i] is ion i's
 // body id (or a number unique to a free ion) and a pair of equal codes adds 0.
-template <int L, int CH, int UNR, bool PF, bool FQ, bool MK = false>
+// KH: the compensated mode, in which the FP32 runs are added in compensated
+// FP32 (Kahan) instead of FP64 within the tile pair.
+template <int L, int CH, int UNR, bool PF, bool FQ, bool MK = false, bool KH = false>
 __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm, int64_t n,
                                                int nb, int64_t n_pad, double* __restrict__ part,
                                                int a, int b, float uq, float4* tile,
@@ -924,8 +934,12 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
     const MixedSrc* mine = reinterpret_cast<const MixedSrc*>(tile) + wave * 64;
     const int32_t* mcode = MK ? tcode + wave * 64 : nullptr;
     double sx[4], sy[4], sz[4];
+    float ksx[4], ksy[4], ksz[4], kcx[4], kcy[4], kcz[4];  // KH: compensated target sums
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sx[k] = sy[k] = sz[k] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        sx[k] = sy[k] = sz[k] = 0.0;
+        ksx[k] = ksy[k] = ksz[k] = kcx[k] = kcy[k] = kcz[k] = 0.0f;
+    }
     float* jb = reinterpret_cast<float*>(smem) + wave * 64 * S;
     // with PF the next source is read from LDS while the current one is used
     MixedSrc m_next = mine[0];
@@ -971,16 +985,23 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            sx[k] += (double)fx[k];
-            sy[k] += (double)fy[k];
-            sz[k] += (double)fz[k];
+            if constexpr (KH) {
+                kahan_add(fx[k], ksx[k], kcx[k]);
+                kahan_add(fy[k], ksy[k], kcy[k]);
+                kahan_add(fz[k], ksz[k], kcz[k]);
+            } else {
+                sx[k] += (double)fx[k];
+                sy[k] += (double)fy[k];
+                sz[k] += (double)fz[k];
+            }
         }
         if (!diag) {
             // the wave's LDS writes are visible to all its lanes after this
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const double tot = column_sum64<CH * 3, (CH * 3 * 4 <= 64 ? 4 : 2)>(jb, lane);
+            const double tot =
+                column_sum64<CH * 3, (CH * 3 * 4 <= 64 ? 4 : 2), float, KH>(jb, lane);
             constexpr int P = CH * 3 * 4 <= 64 ? 4 : 2;
             const int col = lane / P;
             if ((lane % P) == 0 && col < CH * 3) {
@@ -991,6 +1012,14 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    if constexpr (KH) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sx[k] = (double)ksx[k] - (double)kcx[k];
+            sy[k] = (double)ksy[k] - (double)kcy[k];
+            sz[k] = (double)ksz[k] - (double)kcz[k];
         }
     }
     if (FQ) {
@@ -1007,7 +1036,7 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
 
 // uq != 0: every ion carries the charge uq (units of e) and tiles below
 // full_tiles hold no padding; those tile pairs take the charge-free loop.
-template <int L, int CH, int WPE, int UNR, bool PF = false, bool MK = false>
+template <int L, int CH, int WPE, int UNR, bool PF = false, bool MK = false, bool KH = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int64_t n_pad,
                       double* __restrict__ part, int64_t* __restrict__ counter, float uq,
@@ -1025,12 +1054,14 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
     if (sym_unit_excluded(tile_body, a, b))
         sym_unit_zero(part, n, n_pad, a, b);
     else if (MK && bt.may_share(a, b))
-        mixed_sym_body<L, CH, UNR, PF, false, true>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem,
-                                                    bt.code, tcode);
+        mixed_sym_body<L, CH, UNR, PF, false, true, KH>(srcm, n, nb, n_pad, part, a, b, uq, tile,
+                                                        smem, bt.code, tcode);
     else if (uq != 0.0f && b < full_tiles)
-        mixed_sym_body<L, CH, UNR, PF, true>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
+        mixed_sym_body<L, CH, UNR, PF, true, false, KH>(srcm, n, nb, n_pad, part, a, b, uq, tile,
+                                                        smem);
     else
-        mixed_sym_body<L, CH, UNR, PF, false>(srcm, n, nb, n_pad, part, a, b, uq, tile, smem);
+        mixed_sym_body<L, CH, UNR, PF, false, false, KH>(srcm, n, nb, n_pad, part, a, b, uq, tile,
+                                                         smem);
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
@@ -2156,9 +2187,19 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
         const double uq = ls.uniform_q;                // 0: charges differ
         const int full = (int)(s.n / kSymTile);        // tiles without padding
         const int32_t* tb = s.body_code ? s.tile_body : nullptr;  // exclusion by whole tiles
+        const BodyTiles bt{s.body_code, s.tile_bmin, s.tile_bmax};
+        if (precision == 2) {
+            // the compensated mode: the built-in FP32 shape with Kahan sums
+            if (ls.sym_masked)
+                k_pair_mixed_sym<8, 8, 4, 2, true, true, true><<<units, 256, 0, st>>>(
+                    s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb, bt);
+            else
+                k_pair_mixed_sym<8, 8, 4, 2, true, false, true><<<units, 256, 0, st>>>(
+                    s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
+            return hipGetLastError();
+        }
         if (ls.sym_masked) {
             // bodies share tiles with other ions: the built-in variants with the per-pair test
-            const BodyTiles bt{s.body_code, s.tile_bmin, s.tile_bmax};
             if (precision == 0)
                 k_pair_f64_sym<4, 1, true, true><<<units, 256, 0, st>>>(
                     s.src, s.qe, s.n, nb, s.n_pad, s.part, ctr, uq, full, tb, bt);

@@ -104,7 +104,9 @@ def single_candidates(n: int, precision: int):
                 yield dict(symmetric=2, sym_variant=v)
     else:
         for i, j, lds in itertools.product((1, 2, 4), js, (1, 2)):
-            yield dict(i_per_lane=i, j_split=j, lds_sources=lds)
+            yield dict(i_per_lane=i, j_split=j, lds_sources=lds, symmetric=1)
+        if (n + 255) // 256 <= 512:
+            yield dict(symmetric=2)
 
 
 def _cloud(n, seed=12345, sigma=200e-6):

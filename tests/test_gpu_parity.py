@@ -130,7 +130,7 @@ def test_accel_parity_full_size_sampled(torch_gpu, oracle_mod, prec):
 SYM_SIZES = [1, 2, 3, 100, 255, 256, 257, 1000, 4097, 8191]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 @pytest.mark.parametrize("n", SYM_SIZES)
 def test_accel_parity_pair_once(torch_gpu, oracle_mod, n, prec):
     """The kernels that evaluate each unordered pair once (tile pairs, reaction
@@ -166,7 +166,7 @@ def _divergence_envelope(oracle_mod, w, nsteps, rel):
     return max(np.max(np.abs(a[k] - b[k])) for k in ("x", "y", "z"))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
     """Pair-once kernels at 16384 ions (sampled targets) and over 45 steps:
     bitwise reproducible, and equal to the all-pairs kernels within tol x
@@ -219,7 +219,7 @@ def test_pair_once_variants(torch_gpu, oracle_mod, prec, variant):
         sim.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 @pytest.mark.parametrize("q", [-1, 3])
 def test_pair_once_uniform_charge(torch_gpu, oracle_mod, prec, q):
     """All ions of one charge other than +1 e: tile pairs without padding take
@@ -238,11 +238,12 @@ def test_pair_once_uniform_charge(torch_gpu, oracle_mod, prec, q):
 
 
 def test_pair_once_rejected_where_unsupported(torch_gpu, oracle_mod):
+    """Batched handles have no pair-once kernels: asking for them is refused."""
     from paper_1907_10514_amd import LionError
     from paper_1907_10514_amd import lion as L
 
-    w = li.random_cloud(300, seed=1)
-    sim = _sim(w, "mixed_kahan", oracle_mod)
+    b = _small_batch(n_traps=3, seed=5, n_max=20)
+    sim = _sim(b, "mixed", oracle_mod)
     with pytest.raises(LionError) as ei:
         sim.set_config(symmetric=2)
     assert ei.value.code == L.LION_ERR_UNSUPPORTED
@@ -589,7 +590,7 @@ def _tile_body_cloud(n, seed, charge_e=None):
     return w, body
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 @pytest.mark.parametrize("charges", ["uniform", "mixed"])
 def test_pair_once_tile_aligned_bodies(torch_gpu, oracle_mod, prec, charges):
     """Bodies that fill whole 256-ion tiles on the pair-once kernels: tile pairs
@@ -614,7 +615,7 @@ def test_pair_once_tile_aligned_bodies(torch_gpu, oracle_mod, prec, charges):
     allp.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_pair_once_bodies_sharing_tiles(torch_gpu, oracle_mod, prec):
     """13000 ions (pair-once by default) with clusters that straddle tile
     edges: tile pairs inside one body are skipped, pairs of tiles whose bodies
@@ -675,7 +676,7 @@ def test_pair_once_rigid_steps(torch_gpu, oracle_mod):
         assert np.max(np.abs(outs[0][k] - outs[1][k])) < 1e-11 * ext, k
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 @pytest.mark.parametrize("n", [40000, 100000])
 def test_pair_once_above_32768(torch_gpu, oracle_mod, prec, n):
     """Pair-once kernels at 40000 and 100000 ions (157 and 391 tiles, one
@@ -748,9 +749,8 @@ def test_bodies_rejected_where_unsupported(torch_gpu, oracle_mod):
     sim.close()
     k = _sim(w, "mixed_kahan", oracle_mod)
     k.set_bodies(shared)
-    with pytest.raises(LionError) as ei:
-        k.set_config(symmetric=2)
-    assert ei.value.code == L.LION_ERR_UNSUPPORTED
+    k.set_config(symmetric=2)  # the compensated mode has the per-pair test too
+    assert k.config()["symmetric"] == 2
     k.close()
     b = _small_batch(n_traps=3, seed=5, n_max=20)
     bs = _sim(b, "fp64", oracle_mod)

@@ -52,7 +52,7 @@ def _length_scale(tr):
 
 
 @pytest.mark.parametrize("prec,sym", [("fp64", 1), ("mixed", 1), ("mixed_kahan", 1),
-                                      ("fp64", 2), ("mixed", 2)])
+                                      ("fp64", 2), ("mixed", 2), ("mixed_kahan", 2)])
 @pytest.mark.parametrize("n", [1, 257, 4097])
 def test_pseudo_accel_parity(torch_gpu, oracle_mod, n, prec, sym):
     """Two species in the pseudopotential trap: one force evaluation, on the
