@@ -436,6 +436,53 @@ def test_batch_trajectory_matches_oracle(torch_gpu, oracle_mod):
     sim.close()
 
 
+def _large_trap_batch():
+    """Traps of the maximum 1024 ions down to 2, with a ragged one of 257 and
+    mixed charges."""
+    w = li.batch512(n_traps=7, n_min=2, n_max=512, seed=37, nsteps=0)
+    sizes = np.array([1024, 600, 257, 256, 255, 40, 2])
+    rng = np.random.default_rng(38)
+    w.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(w.offsets[-1])
+    w.mass = np.full(n, li.REF_MASS)
+    w.charge = rng.choice([1, 1, 2], n) * li.E_CHARGE
+    w.x, w.y, w.z = rng.normal(0, 30e-6, (3, n))
+    w.vx, w.vy, w.vz = rng.normal(0, 1.0, (3, n))
+    return w
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-4), ("mixed_kahan", 1e-4)])
+@pytest.mark.parametrize("block", [256, 1024])
+def test_batch_large_traps_run(torch_gpu, oracle_mod, prec, tol, block):
+    """Traps up to the 1024-ion maximum in the batched kernel: forces, and a
+    60-step run of every trap (4 targets per thread at 256 threads, 2 at 1024)
+    against the oracle."""
+    w = _large_trap_batch()
+    traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
+    dts = np.array([s.dt for s in w.traps])
+    sim = _sim(w, prec, oracle_mod, batch_block=block, chunk_steps=25)
+    a = sim.compute_accel()
+    r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
+                               np.zeros(w.n_traps))
+    for k in range(w.n_traps):
+        o, e = w.offsets[k], w.offsets[k + 1]
+        sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e],
+                                    traps[k], 0.0)
+        assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
+    sim.step(60, dts)
+    st, _ = sim.get_state()
+    assert sim.check_finite() == 0
+    sim.close()
+    ref = oracle_mod.step_batch(w.offsets, w.state(), w.charge, w.mass, traps,
+                                np.array([s.gamma for s in w.traps]), np.zeros(w.n_traps), dts,
+                                60)
+    for k in range(w.n_traps):
+        o, e = int(w.offsets[k]), int(w.offsets[k + 1])
+        disp = np.max(np.abs(ref["x"][o:e] - w.x[o:e])) + 1e-12
+        for c in ("x", "y", "z"):
+            assert np.max(np.abs(st[c][o:e] - ref[c][o:e])) < tol * disp, (k, c)
+
+
 def test_batch_equals_single_trap_path(torch_gpu, oracle_mod):
     """One trap run through the batched kernel and through the single-trap
     kernels gives the same trajectory (FP64, to roundoff)."""
