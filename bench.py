@@ -29,6 +29,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "mixed_kahan": 157.3}
 DTYPE = {"fp64": "f64", "mixed": "f32", "mixed_kahan": "f32"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1907_10514_amd", "csrc", "lion_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu.json")
 
 
 def log(msg):
@@ -40,12 +41,12 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def traffic_for(kernel_key: str, launch: dict):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+def profile_value(path: str, kernel_key: str, launch: dict, field: str):
+    """A per-launch figure of a kernel from a committed rocprofv3 counter
     summary, or None if absent, taken on a different kernel source, or taken
     with a different launch shape."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             data = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -54,7 +55,12 @@ def traffic_for(kernel_key: str, launch: dict):
         return None
     if any(launch.get(k) != v for k, v in ent.get("launch", {}).items()):
         return None
-    return ent.get("bytes_per_launch")
+    return ent.get(field)
+
+
+def traffic_for(kernel_key: str, launch: dict):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return profile_value(TRAFFIC_FILE, kernel_key, launch, "bytes_per_launch")
 
 
 def sync(torch):
@@ -418,6 +424,12 @@ def main():
         "algorithmic_flop_per_launch": FLOP_PER_PAIR * pairs,
         "avg_launch_ms": r["pair_kernel_ms"],
     }
+    # issued FLOP per launch from the VALU instruction counters (each unordered
+    # pair is evaluated once, so fewer are issued than credited)
+    issued = profile_value(VALU_FILE, kern_key, r["launch"], "issued_flop_per_launch")
+    out["roofline"]["issued_flop_per_launch"] = issued
+    out["roofline"]["issued_tflops"] = (issued / (r["pair_kernel_ms"] * 1e-3) / 1e12
+                                        if issued else None)
     if not args.no_batch:
         out["batch512"] = {}
         for p in ("mixed", "fp64"):
