@@ -149,6 +149,51 @@ def test_accel_parity_pair_once(torch_gpu, oracle_mod, n, prec):
     sim.close()
 
 
+COINCIDENT = ((1, 2), (10, 500), (999, 3), (256, 257), (0, 255))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+@pytest.mark.parametrize("sym", [1, 2])
+def test_coincident_ions(torch_gpu, oracle_mod, prec, sym):
+    """Exactly coincident ions (within a tile, across tiles, at tile edges) add
+    nothing to each other's field, a select and not softening, on the
+    all-pairs and the pair-once kernels; every other term meets the bar."""
+    w = li.random_cloud(1000, seed=61, sigma=60e-6,
+                        charge_e=np.random.default_rng(62).choice([1, 2, -1], 1000))
+    for i, j in COINCIDENT:
+        w.x[j], w.y[j], w.z[j] = w.x[i], w.y[i], w.z[i]
+    sim = _sim(w, prec, oracle_mod, symmetric=sym)
+    a = sim.compute_accel()
+    tr = _oracle_trap(oracle_mod, w.traps[0])
+    r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    assert all(np.all(np.isfinite(c)) for c in a)
+    err = _m1(a, r, sc)
+    print(f"coincident ions {prec} symmetric={sym}: M1={err:.3e}")
+    assert err <= TOL[prec]
+    sim.close()
+
+
+def test_coincident_ions_batched(torch_gpu, oracle_mod):
+    """The same in the batched kernel, for every precision."""
+    w = _large_trap_batch()
+    for k, (i, j) in enumerate(((5, 6), (700, 1023), (1030, 1500))):
+        w.x[j], w.y[j], w.z[j] = w.x[i], w.y[i], w.z[i]
+    traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
+    r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
+                               np.zeros(w.n_traps))
+    for prec in TOL:
+        sim = _sim(w, prec, oracle_mod)
+        a = sim.compute_accel()
+        assert all(np.all(np.isfinite(c)) for c in a)
+        for k in range(w.n_traps):
+            o, e = w.offsets[k], w.offsets[k + 1]
+            sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e],
+                                        w.mass[o:e], traps[k], 0.0)
+            assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], (prec, k)
+        sim.close()
+
+
 def _divergence_envelope(oracle_mod, w, nsteps, rel):
     """How far the oracle's own run of ``nsteps`` moves when every start
     position is moved by one ulp (rel None) or by a seeded relative amount rel
