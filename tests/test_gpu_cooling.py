@@ -212,7 +212,8 @@ def test_cooled_runs_reproducible_and_resumable(torch_gpu, oracle_mod):
     sp = _species(w)
     dt = 2.0 ** -26
     outs = []
-    for cfg in (dict(), dict(use_graph=2), dict(chunk_steps=7)):
+    base = dict(i_per_lane=2, j_split=16, flush_len=8)  # one launch shape throughout
+    for cfg in (base, dict(base, use_graph=2), dict(base, chunk_steps=7)):
         sim = _cooled_sim(w, "mixed", oracle_mod, sp, **cfg)
         sim.step(45, dt)
         outs.append(sim.get_state()[0])

@@ -375,11 +375,13 @@ def test_energy_matches_oracle(torch_gpu, oracle_mod):
 
 def test_bitwise_reproducible_and_launch_mode_independent(torch_gpu, oracle_mod):
     """Fixed-order reductions: reruns, graph vs plain launches and chunk sizes
-    give identical bits."""
+    give identical bits (one launch shape throughout: a tuned shape for this
+    size may differ from the built-in one)."""
     w = li.random_cloud(3000, seed=9, sigma=60e-6)
     spec = w.traps[0]
     outs = []
-    for cfg in (dict(), dict(), dict(use_graph=2), dict(chunk_steps=7)):
+    base = dict(i_per_lane=2, j_split=16, flush_len=8)
+    for cfg in (base, base, dict(base, use_graph=2), dict(base, chunk_steps=7)):
         sim = _sim(w, "mixed", oracle_mod, **cfg)
         sim.step(45, spec.dt)
         outs.append(sim.get_state()[0])
