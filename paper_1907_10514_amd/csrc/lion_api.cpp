@@ -156,16 +156,21 @@ void default_shape(lion_sim* s) {
     LaunchShape& ls = s->ls;
     const int64_t n = s->n;
     const bool mixed = s->precision != LION_FP64;
+    // all-pairs shapes: one target per lane and many source slices below 16384
+    // ions (measured best up to 10000), several targets per lane above
     ls.i_per_lane = s->cfg.i_per_lane > 0 ? s->cfg.i_per_lane
-                                          : (n >= 8192 ? (mixed ? 4 : 2) : (n >= 2048 ? 2 : 1));
+                                          : (n >= 16384 ? (mixed ? 4 : 2) : 1);
     ls.flush_len = s->cfg.flush_len > 0 ? s->cfg.flush_len : 8;
     ls.batch_block = s->cfg.batch_block > 0 ? s->cfg.batch_block : 256;
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
     const int nb = lion::sym_tiles(n);
-    // pair-once kernels: when asked for, and by default for one trap of 12288 ions or
-    // more (48+ tiles: more tile pairs than workgroup slots), where they are faster
+    // pair-once kernels: when asked for, and by default for one trap from the
+    // size where they measured faster (8192 ions, 10240 for FP32 pairs with FP64
+    // run sums; from 12288 on by a wide margin in every precision)
     const bool sym_ok = nb <= lion::kMaxSymTiles && !s->batched;
-    const bool sym_default = s->cfg.symmetric <= 0 && n >= lion::kSymDefaultIons;
+    const int64_t sym_from = s->precision == LION_MIXED_F64ACC ? lion::kSymDefaultIonsMixed
+                                                                : lion::kSymDefaultIons;
+    const bool sym_default = s->cfg.symmetric <= 0 && n >= sym_from;
     ls.symmetric = (sym_ok && (s->cfg.symmetric == 2 || sym_default)) ? 1 : 0;
     // bodies that share tiles with other ions need the per-pair test in those kernels
     ls.sym_masked = (ls.symmetric && s->has_bodies && !s->tile_bodies) ? 1 : 0;
@@ -177,8 +182,10 @@ void default_shape(lion_sim* s) {
     if (s->cfg.j_split > 0) {
         j = s->cfg.j_split;
     } else {
-        // aim for ~1024 blocks of 4 waves (4 waves per SIMD on 256 CUs)
-        j = (int)std::max<int64_t>(1, (1024 + blocks_x - 1) / blocks_x);
+        // aim for ~1024 blocks of 4 waves (4 waves per SIMD on 256 CUs), ~4096
+        // below 16384 ions, where more, shorter slices measured faster
+        const int64_t target = n >= 16384 ? 1024 : 4096;
+        j = (int)std::max<int64_t>(1, (target + blocks_x - 1) / blocks_x);
     }
     j = std::max(1, std::min(j, s->j_max));
     ls.jps = (int)round_up((n64 + j - 1) / j, 64);

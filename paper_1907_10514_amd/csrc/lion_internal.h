@@ -201,7 +201,10 @@ struct LaunchShape {
 // epilogue then adds one partial per tile.
 inline int sym_tiles(int64_t n) { return (int)((n + 255) / 256); }
 constexpr int kMaxSymTiles = 512;
-constexpr int64_t kSymDefaultIons = 12288;  // pair-once by default from here (48 tiles)
+// Pair-once kernels by default from here: 32 tiles for FP64 and the
+// compensated mode, 40 for FP32 pairs with FP64 run sums (measured crossovers).
+constexpr int64_t kSymDefaultIons = 8192;
+constexpr int64_t kSymDefaultIonsMixed = 10240;
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st);
