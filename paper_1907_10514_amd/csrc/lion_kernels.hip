@@ -1502,9 +1502,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const int jpart = tid / IS;
     const bool active = jpart < JP;
     const bool owner = jpart == 0;
-    const int jlen = ((m16 / JP) + 15) & ~15;
-    const int jb = min(jpart * jlen, m16);
-    const int je = min(jb + jlen, m16);
+    // sources per part when each thread has one target: whole FP32 runs of 8 in
+    // the FP32 + FP64 mode, multiples of 4 otherwise (padding beyond m adds
+    // nothing), so that the sources of a small trap spread over the parts
+    constexpr int kGran = PREC == 1 ? 8 : 4;
+    const int send = PREC == 1 ? m16 : (m + 3) & ~3;
+    const int jlen = ((send + JP - 1) / JP + kGran - 1) / kGran * kGran;
+    const int jb = min(jpart * jlen, send);
+    const int je = min(jb + jlen, send);
     const TrapDev T = traps[tr];
     const int64_t k0 = *counter;
     // pair work of larger traps: TPT targets per thread read each source once
