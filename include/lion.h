@@ -312,7 +312,7 @@ typedef struct {
 } lion_kernel_config;
 
 /* Ion count up to which a single trap is stepped inside one workgroup by default. */
-#define LION_SMALL_TRAP_IONS 128
+#define LION_SMALL_TRAP_IONS 160
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);
 int lion_get_kernel_config(const lion_sim *sim, lion_kernel_config *cfg);

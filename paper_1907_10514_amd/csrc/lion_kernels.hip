@@ -1515,7 +1515,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     // pair work of larger traps: TPT targets per thread read each source once
     // (at most 2 with 1024 threads, whose 128-VGPR budget 4 targets overflow)
     constexpr int TMAX = BLOCK >= 1024 ? 2 : 4;
-    int TPT = m >= kBatchTpt4 ? TMAX : (m >= kBatchTpt2 ? 2 : 1);
+    // a lone trap (the small-trap path) is latency-bound: one target per thread
+    // below kBatchTpt4 ions saves the extra reduction rounds
+    const int tpt2_from = gridDim.x == 1 ? kBatchTpt4 : kBatchTpt2;
+    int TPT = m >= kBatchTpt4 ? TMAX : (m >= tpt2_from ? 2 : 1);
     if (TPT > 1)
         while (TPT < TMAX && TPT * BLOCK < m) TPT *= 2;
     const int WS = ((m + 64 * TPT - 1) / (64 * TPT)) * 64;  // <= BLOCK

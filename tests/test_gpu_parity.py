@@ -552,7 +552,7 @@ def test_batch_equals_single_trap_path(torch_gpu, oracle_mod):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
-@pytest.mark.parametrize("n", [1, 8, 100, 128, 300])
+@pytest.mark.parametrize("n", [1, 8, 100, 128, 160, 300])
 def test_small_trap_path_equals_multi_workgroup_path(torch_gpu, oracle_mod, n, prec, tol):
     """A single trap stepped inside one workgroup (many steps per launch) and by
     the multi-workgroup kernels gives the same trajectory to rounding, with a
