@@ -263,6 +263,31 @@ def time_small(torch, w, steps, oracle_steps):
                             cores=oracle.num_threads()))
 
 
+def clusters_oracle(evals):
+    """The FP64 oracle's field with the body-id exclusion on the 65536-ion
+    cluster workload: `evals` force evaluations on the host cores (the GPU
+    figure beside it is the pair kernel's, which computes the same sum)."""
+    import numpy as np
+
+    import lion_inputs as li
+    import oracle
+
+    w = li.clusters65536()
+    body = w.notes["body"]
+    sizes = np.bincount(body[body >= 0])
+    pairs = w.n * (w.n - 1) - int(np.sum(sizes * (sizes - 1)))
+    spec = w.traps[0]
+    V0, U0 = oracle.voltages_for(spec.q_x, spec.a_x, spec.ref_mass, spec.ref_charge, spec.omega,
+                                 spec.r0, spec.z0, spec.kappa)
+    tr = oracle.Trap(V0=V0, Omega=spec.omega, U0=U0, R0=spec.r0, Z0=spec.z0, kappa=spec.kappa)
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        oracle.accel_bodies(w.x, w.y, w.z, w.charge, w.mass, body, tr, 0.0)
+    el = time.perf_counter() - t0
+    return dict(pairs_per_s=pairs * evals / el, cores=oracle.num_threads(), kind="oracle",
+                sample=f"{evals} force evaluations with the exclusion mask in {el:.1f} s")
+
+
 def cpu_baseline(w, seconds):
     """The FP64 oracle on the host cores, on a bounded number of steps of the
     same workload."""
@@ -454,6 +479,9 @@ def main():
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if not args.no_clusters:
+            log("[bench] clusters65536: oracle field, 2 evaluations")
+            out["clusters65536"]["oracle"] = clusters_oracle(2)
         if not args.no_small:
             out["small_configs"] = {}
             for wk, steps, osteps in ((li.crystal8(), 20000, 20000), (li.crystal1024(), 5000, 2000)):
