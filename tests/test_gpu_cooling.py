@@ -45,14 +45,17 @@ BATHS = [dict(temperature=0.5e-3, tau=40e-6, seed=0x1234_5678_9ABC, species=1),
          dict(temperature=2e-3, tau=80e-6, seed=99, species=-1)]
 
 
-def _envelope(run, state):
+def _envelope(run, state, rel=None):
     """Roundoff-growth envelope of a chaotic run: how far the oracle's own
-    trajectory moves when every start position is moved by one ulp.  Returns
-    (max |dx|, max |dv|) between the two oracle runs."""
+    trajectory moves when every start position is moved by the path's rounding
+    size, one ulp (rel None, FP64) or a seeded relative amount rel (1e-7 for
+    FP32 pair forces).  Returns (max |dx|, max |dv|) between the two runs."""
     a = run(state)
     st = {k: v.copy() for k, v in state.items()}
+    rng = np.random.default_rng(0)
     for k in ("x", "y", "z"):
-        st[k] = np.nextafter(st[k], np.inf)
+        st[k] = np.nextafter(st[k], np.inf) if rel is None else \
+            st[k] * (1 + rel * rng.normal(size=st[k].size))
     b = run(st)
     return (max(np.max(np.abs(a[k] - b[k])) for k in ("x", "y", "z")),
             max(np.max(np.abs(a[k] - b[k])) for k in ("vx", "vy", "vz")))
@@ -82,7 +85,7 @@ def _cooled_sim(w, prec, oracle, species, beams=BEAMS, baths=BATHS, **cfg):
     return sim
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5), ("mixed_kahan", 1e-5)])
 def test_cooled_run_matches_oracle(torch_gpu, oracle_mod, prec, tol):
     """Two species, a beam on each and two baths (one species-selective), run in
     two calls (120 + 80 steps) so the second continues the draw sequence.  The
@@ -109,8 +112,9 @@ def test_cooled_run_matches_oracle(torch_gpu, oracle_mod, prec, tol):
     verr = max(np.max(np.abs(st[k] - ref[k])) for k in ("vx", "vy", "vz"))
     env_x, env_v = _envelope(
         lambda s0: oracle_mod.step_cooled(s0, w.charge, w.mass, sp, tr, spec.gamma, beams=BEAMS,
-                                          baths=BATHS, dt=spec.dt, nsteps=200), w.state())
-    print(f"{prec}: |dx| {err:.3e} (disp {disp:.3e}, 1-ulp envelope {env_x:.3e}), "
+                                          baths=BATHS, dt=spec.dt, nsteps=200), w.state(),
+        None if prec == "fp64" else 1e-7)
+    print(f"{prec}: |dx| {err:.3e} (disp {disp:.3e}, envelope {env_x:.3e}), "
           f"|dv| {verr:.3e} (v {vscale:.3e}, envelope {env_v:.3e})")
     assert err < max(tol * disp, 10 * env_x)
     assert verr < max(10 * tol * vscale, 10 * env_v)
@@ -133,7 +137,7 @@ def test_beam_cooling_of_free_ions_is_exact(torch_gpu, oracle_mod):
     v = rng.normal(0, 2.0, (3, n))
     sp = (np.arange(n) % 3 == 0).astype(np.int32)
     m = np.full(n, li.REF_MASS)
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_kahan"):
         sim = Simulation(m, np.zeros(n), prec)
         sim.set_species(sp)
         sim.set_beam(2, k * 7.0, 1e6, species=0)  # normalised by the library
@@ -157,7 +161,7 @@ def test_beam_cooling_of_free_ions_is_exact(torch_gpu, oracle_mod):
         sim.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5), ("mixed_kahan", 1e-5)])
 def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec, tol):
     """Batched traps draw bath kicks by run-wide ion index (trap k's first ion is
     offsets[k]); each trap matches the oracle run with that ion_base."""
@@ -181,7 +185,8 @@ def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec, tol):
                 lambda s0: oracle_mod.step_cooled(s0, w.charge[o:e], w.mass[o:e], sp[o:e],
                                                   _oracle_trap(oracle_mod, spec), spec.gamma,
                                                   beams=BEAMS, baths=BATHS, dt=dt, nsteps=100,
-                                                  ion_base=o), sub)
+                                                  ion_base=o), sub,
+                None if prec == "fp64" else 1e-7)
             assert err < 10 * env_x, (k, err, disp, env_x)
     sim.close()
 

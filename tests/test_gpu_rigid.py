@@ -97,7 +97,7 @@ def _envelope(run, state, rel=None):
     return max(np.max(np.abs(a[k] - b[k])) for k in ("x", "y", "z"))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5), ("mixed_kahan", 1e-5)])
 @pytest.mark.parametrize("case", ["rod", "clusters"])
 def test_rigid_run_matches_oracle(torch_gpu, oracle_mod, case, prec, tol):
     """300 steps in two calls (170 + 130), rf trap and damping.  These clouds
@@ -136,7 +136,7 @@ def test_rigid_body_com_follows_single_ion_on_gpu(torch_gpu, oracle_mod):
     for k, off in (("x", 7e-6), ("y", -4e-6), ("z", 11e-6)):
         st[k] = st[k] + off
     tr = _trap(oracle_mod)
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_kahan"):
         sim = _gpu(st, m, q, body, prec, tr, 1e5)
         sim.step(2000, li.DT)
         rs = sim.rigid_state()

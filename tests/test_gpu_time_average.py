@@ -17,7 +17,7 @@ import lion_inputs as li
 pytestmark = pytest.mark.gpu
 
 DT = 2.0 ** -26
-TOL = {"fp64": 1e-10, "mixed": 1e-5}
+TOL = {"fp64": 1e-10, "mixed": 1e-5, "mixed_kahan": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +72,7 @@ def _check(oracle, avg, end, ref_samples, origin, window, tol):
     return err / scale
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_time_average_single_trap(torch_gpu, oracle_mod, prec):
     """W = 20 (one rf period at this step) from step 0, stepped in calls of 17
     and 28 steps (windows close at 20 and 40); then restarted at step 45 with
@@ -94,7 +94,7 @@ def test_time_average_single_trap(torch_gpu, oracle_mod, prec):
     sim.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_time_average_batch(torch_gpu, oracle_mod, prec):
     w = li.batch512(n_traps=10, n_min=2, n_max=200, seed=29, nsteps=0)
     sim = _sim(w, prec, oracle_mod)
