@@ -263,7 +263,7 @@ def time_small(torch, w, steps, oracle_steps):
                             cores=oracle.num_threads()))
 
 
-def clusters_oracle(evals):
+def cpu_baseline_clusters(evals):
     """The FP64 oracle's field with the body-id exclusion on the 65536-ion
     cluster workload: `evals` force evaluations on the host cores (the GPU
     figure beside it is the pair kernel's, which computes the same sum)."""
@@ -477,11 +477,12 @@ def main():
             log(f"[bench] clusters65536 {p}: {out['clusters65536'][p]['pairs_per_s']:.4e} pairs/s, "
                 f"pair kernel {out['clusters65536'][p]['pair_kernel_ms']:.3f} ms")
     if not args.no_cpu_baseline:
+        # the CPU-baseline leg: the only place the oracle runs in this script
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         if not args.no_clusters:
             log("[bench] clusters65536: oracle field, 2 evaluations")
-            out["clusters65536"]["oracle"] = clusters_oracle(2)
+            out["clusters65536"]["oracle"] = cpu_baseline_clusters(2)
         if not args.no_small:
             out["small_configs"] = {}
             for wk, steps, osteps in ((li.crystal8(), 20000, 20000), (li.crystal1024(), 5000, 2000)):
