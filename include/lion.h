@@ -266,6 +266,13 @@ int lion_get_energy(lion_sim *sim, double *kinetic, double *coulomb, double *dc_
  * LION_OK.  Synchronises. */
 int lion_check_finite(lion_sim *sim);
 
+/* Lost-ion check (the paper's simulation box grows with escaping ions; an
+ * unstable trap shows up here instead): *count receives the number of ions,
+ * over every trap of the handle, farther than r_lost_m (m) from the trap
+ * centre or with a non-finite position.  r_lost_m <= 0 or non-finite, or
+ * count NULL -> LION_ERR_ARG.  Changes no state.  Synchronises. */
+int lion_count_lost(lion_sim *sim, double r_lost_m, int64_t *count);
+
 /* Message of the last failure on this handle ("" if none; a static string for
  * sim == NULL). */
 const char *lion_last_error(const lion_sim *sim);

@@ -1153,6 +1153,22 @@ int lion_check_finite(lion_sim* s) {
     return LION_OK;
 }
 
+int lion_count_lost(lion_sim* s, double r_lost_m, int64_t* count) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (!count) return fail(s, LION_ERR_ARG, "count is NULL");
+    if (!(r_lost_m > 0.0) || !std::isfinite(r_lost_m))
+        return fail(s, LION_ERR_ARG, "r_lost must be > 0 and finite");
+    LION_HIP(s, hipSetDevice(s->device));
+    hipStream_t st = s->stream;
+    int32_t lost = 0;
+    LION_HIP(s, hipMemsetAsync(s->d.flags + 1, 0, sizeof(int32_t), st));
+    LION_HIP(s, lion::launch_count_lost(s->d, r_lost_m, st));
+    LION_HIP(s, hipMemcpyAsync(&lost, s->d.flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LION_HIP(s, hipStreamSynchronize(st));
+    *count = lost;
+    return LION_OK;
+}
+
 const char* lion_last_error(const lion_sim* s) {
     if (!s) return g_create_err.empty() ? "invalid handle" : g_create_err.c_str();
     return s->err.c_str();

@@ -231,5 +231,7 @@ int eigh_device(double* A, int m, double* W, double* E, int* info, bool vectors,
 hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
 hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
 hipError_t launch_check_finite(const DevState& s, hipStream_t st);
+// Counts ions beyond r_lost (m) of the trap centre, or non-finite, into flags[1].
+hipError_t launch_count_lost(const DevState& s, double r_lost, hipStream_t st);
 
 }  // namespace lion

@@ -1310,6 +1310,17 @@ __global__ __launch_bounds__(256) void k_check_finite(const double4* __restrict_
     if (!ok) atomicAdd(flags, 1);
 }
 
+// Lost-ion check: ions farther than sqrt(r2_lost) from the trap centre, or
+// with a non-finite position, are counted into *count.
+__global__ __launch_bounds__(256) void k_count_lost(const double4* __restrict__ src, int64_t n,
+                                                    double r2_lost, int32_t* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 p = src[i];
+    const double r2 = p.x * p.x + p.y * p.y + p.z * p.z;
+    if (!(r2 <= r2_lost)) atomicAdd(count, 1);
+}
+
 // ------------------------------------------------------------ batched traps
 //
 // One workgroup per trap, launched largest trap first so that the hardware
@@ -2410,6 +2421,11 @@ hipError_t launch_coulomb_potential(const DevState& s, int, hipStream_t st) {
 
 hipError_t launch_check_finite(const DevState& s, hipStream_t st) {
     k_check_finite<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.n, s.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_lost(const DevState& s, double r_lost, hipStream_t st) {
+    k_count_lost<<<blocks_for(s.n, 256), 256, 0, st>>>(s.src, s.n, r_lost * r_lost, s.flags + 1);
     return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.lion_compute_accel.argtypes = [vp, dp, dp, dp]
     lib.lion_get_energy.argtypes = [vp, dp, dp, dp]
     lib.lion_check_finite.argtypes = [vp]
+    lib.lion_count_lost.argtypes = [vp, d, ctypes.POINTER(ctypes.c_int64)]
     lib.lion_last_error.argtypes = [vp]
     lib.lion_last_error.restype = ctypes.c_char_p
     lib.lion_destroy.argtypes = [vp]
@@ -112,7 +113,7 @@ def load(path: str = LIB_PATH):
                  "lion_set_species", "lion_set_beam",
                  "lion_set_bath", "lion_set_step_index", "lion_set_time_average",
                  "lion_get_time_average", "lion_step", "lion_step_batch", "lion_get_state",
-                 "lion_compute_accel", "lion_get_energy", "lion_check_finite",
+                 "lion_compute_accel", "lion_get_energy", "lion_check_finite", "lion_count_lost",
                  "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
                  "lion_time_pair_kernel", "lion_time_batch_kernel"):
         getattr(lib, name).restype = ctypes.c_int
@@ -295,6 +296,12 @@ def lion_get_energy(h):
 
 def lion_check_finite(h) -> int:
     return int(load().lion_check_finite(h))
+
+
+def lion_count_lost(h, r_lost_m: float) -> int:
+    c = ctypes.c_int64()
+    _check(load().lion_count_lost(h, float(r_lost_m), ctypes.byref(c)), h)
+    return int(c.value)
 
 
 def lion_last_error(h) -> str:
@@ -486,6 +493,10 @@ class Simulation:
 
     def check_finite(self) -> int:
         return lion_check_finite(self.h)
+
+    def count_lost(self, r_lost_m: float) -> int:
+        """Ions farther than r_lost_m from the trap centre (or non-finite)."""
+        return lion_count_lost(self.h, r_lost_m)
 
     def time_pair_kernel(self, reps: int) -> float:
         return lion_time_pair_kernel(self.h, reps)
