@@ -266,8 +266,9 @@ int lion_get_energy(lion_sim *sim, double *kinetic, double *coulomb, double *dc_
  * LION_OK.  Synchronises. */
 int lion_check_finite(lion_sim *sim);
 
-/* Lost-ion check (the paper's simulation box grows with escaping ions; an
- * unstable trap shows up here instead): *count receives the number of ions,
+/* Lost-ion check (section "Simulation domain": the integration volume is
+ * expanded as ions leave it; here there is no volume, and ions that escape an
+ * unstable trap show up in this count instead): *count receives the number of ions,
  * over every trap of the handle, farther than r_lost_m (m) from the trap
  * centre or with a non-finite position.  r_lost_m <= 0 or non-finite, or
  * count NULL -> LION_ERR_ARG.  Changes no state.  Synchronises. */
