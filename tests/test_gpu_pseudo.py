@@ -129,7 +129,8 @@ def _chain_start(n, seed):
     return st
 
 
-@pytest.mark.parametrize("prec,ftol,tol", [("fp64", 1e-10, 1e-8), ("mixed", 1e-5, 1e-4)])
+@pytest.mark.parametrize("prec,ftol,tol", [("fp64", 1e-10, 1e-8), ("mixed", 1e-5, 1e-4),
+                                           ("mixed_kahan", 1e-5, 1e-4)])
 @pytest.mark.parametrize("n,sym", [(2, 1), (5, 1), (10, 1), (10, 2)])
 def test_minimised_chain(torch_gpu, oracle_mod, n, sym, prec, ftol, tol):
     """Minimising from a scattered start gives the linear chain: sorted axial
