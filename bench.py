@@ -73,6 +73,9 @@ def time_single(torch, w, precision, steps, warmup, reps):
     sim = runner.simulation_for(w, precision=precision)
     dt = w.traps[0].dt
     sim.step(warmup, dt)
+    # the launch graphs of the timed call are captured and instantiated here,
+    # outside the timed region (no step runs)
+    sim.prepare_step(steps)
     sync(torch)
     t0 = time.perf_counter()
     sim.step(steps, dt)
@@ -98,6 +101,7 @@ def chunk_times(torch, sim, dt, launches=10, steps=100):
     events on the simulation's stream: median and min over the launches."""
     import statistics
 
+    sim.prepare_step(steps)
     ms = []
     for _ in range(launches):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -161,6 +165,7 @@ def time_batch(torch, precision, steps, warmup, seq_steps):
     sim = runner.simulation_for(w, precision=precision)
     dts = runner.step_dts(w)
     sim.step(warmup, dts)
+    sim.prepare_step(steps)
     sync(torch)
     t0 = time.perf_counter()
     sim.step(steps, dts)
@@ -178,7 +183,8 @@ def time_batch(torch, precision, steps, warmup, seq_steps):
                           w.vx[o:e], w.vy[o:e], w.vz[o:e], [w.traps[k]],
                           np.array([0, e - o], dtype=np.int64), seq_steps, w.precision)
         s1 = runner.simulation_for(sub, precision=precision, batched=False)
-        s1.step(seq_steps, w.traps[k].dt)  # captures the launch graph outside the timing
+        s1.step(seq_steps, w.traps[k].dt)  # warm-up call of the same length
+        s1.prepare_step(seq_steps)
         sync(torch)
         t0 = time.perf_counter()
         s1.step(seq_steps, w.traps[k].dt)
@@ -214,6 +220,7 @@ def time_clusters(torch, precision, steps, warmup, reps):
     sim.set_rigid_bodies(body)
     dt = w.traps[0].dt
     sim.step(warmup, dt)
+    sim.prepare_step(steps)
     sync(torch)
     t0 = time.perf_counter()
     sim.step(steps, dt)
@@ -242,6 +249,7 @@ def time_small(torch, w, steps, oracle_steps):
     spec = w.traps[0]
     sim = runner.simulation_for(w, precision="fp64")
     sim.step(min(steps, 200), spec.dt)
+    sim.prepare_step(steps)
     sync(torch)
     t0 = time.perf_counter()
     sim.step(steps, spec.dt)
@@ -338,16 +346,24 @@ def host_cpu():
     return None
 
 
-def profile_pass(torch, w, precisions):
+def profile_pass(torch, w, precisions, batch=False):
     """Short run for counter collection: each benchmarked pair kernel (tuned
-    launch shape) 5 times plus 3 steps, then a device-to-device copy of 256 MiB
-    whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters."""
+    launch shape) 5 times plus 3 steps (with batch: instead, two launches of the
+    batched kernel over the 512-trap batch, 100 in-kernel steps each), then a
+    device-to-device copy of 256 MiB whose FETCH_SIZE / WRITE_SIZE readings
+    calibrate the counters."""
+    import lion_inputs as li
     from paper_1907_10514_amd import runner
 
     for p in precisions:
-        sim = runner.simulation_for(w, precision=p)
-        sim.time_pair_kernel(5)
-        sim.step(3, w.traps[0].dt)
+        if batch:
+            wb = li.batch512(nsteps=0)
+            sim = runner.simulation_for(wb, precision=p)
+            sim.time_batch_kernel(2, 100, float(wb.traps[0].dt))
+        else:
+            sim = runner.simulation_for(w, precision=p)
+            sim.time_pair_kernel(5)
+            sim.step(3, w.traps[0].dt)
         torch.cuda.synchronize()
         log(f"[profile] {p} launch shape {sim.config()}")
         sim.close()
@@ -378,6 +394,9 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="only launch the benchmarked pair kernels a few times and a 256 MiB "
                          "device copy (for rocprofv3 counter passes), then exit")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="with --profile-pass: the batched kernel over the 512-trap batch "
+                         "instead of the pair kernels")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -398,7 +417,7 @@ def main():
     props = torch.cuda.get_device_properties(0)
     w = li.mixed16384()
     if args.profile_pass:
-        profile_pass(torch, w, [p for p in args.precisions.split(",") if p])
+        profile_pass(torch, w, [p for p in args.precisions.split(",") if p], args.profile_batch)
         return
     n = w.n
     precs = [p for p in args.precisions.split(",") if p]
@@ -467,6 +486,13 @@ def main():
         if "mixed" in out["batch512"] and "fp64" in out["batch512"]:
             out["batch512"]["speedup_mixed_over_fp64"] = (
                 out["batch512"]["mixed"]["pairs_per_s"] / out["batch512"]["fp64"]["pairs_per_s"])
+        # the batched launch against the plain FP64 path on one 16384-ion trap
+        # (pair interactions per second of each)
+        if "fp64" in res:
+            for p in out["batch512"]:
+                if isinstance(out["batch512"][p], dict):
+                    out["batch512"][p]["speedup_vs_plain_fp64_n16384"] = (
+                        out["batch512"][p]["pairs_per_s"] / res["fp64"]["pairs_per_s"])
     if not args.no_clusters:
         out["clusters65536"] = {}
         for p in ("mixed", "fp64"):

@@ -25,7 +25,9 @@
  *   - Device memory: the caller allocates one workspace of
  *     lion_workspace_bytes(...) bytes (256-byte aligned) and keeps it alive
  *     until lion_destroy; the library carves all device arrays from it and
- *     never allocates or frees device memory itself.
+ *     never allocates or frees device memory itself (lion_normal_modes takes
+ *     a second caller-owned workspace for its eigen-solver).  The HIP runtime
+ *     allocates what it needs to instantiate launch graphs.
  *   - Every call runs on the HIP stream given at creation (a hipStream_t
  *     passed as void*, NULL = the default stream) and returns once its work is
  *     queued, except lion_get_state / lion_compute_accel / lion_get_energy,
@@ -66,12 +68,24 @@ enum lion_status {
 };
 
 /* Bytes of device workspace needed for n_total ions in n_traps traps (1 for a
- * single trap) at the given precision.  Returns 0 for invalid arguments. */
+ * single trap) at the given precision.  Returns 0 for invalid arguments.
+ * Host-only; the workspace holds every per-ion array of the handle (section
+ * "Creating the simulation": one object holds all the simulation's state). */
 size_t lion_workspace_bytes(int64_t n_total, int32_t n_traps, int precision);
 
 /* One trap of n ions (n >= 1) with masses (kg, > 0, finite) and charges (C,
- * finite).  Ions are created with zero position and velocity; call
- * lion_set_state before stepping.  No trap field and no damping until set. */
+ * finite) (section "Adding ions": each ion is defined by its charge and mass;
+ * here both are per ion and in SI units, where the paper gives charge in units
+ * of e and mass in atomic mass units).  masses_kg and charges_C are host
+ * arrays of length n, copied during the call.  dev_workspace: caller-owned
+ * device memory of at least lion_workspace_bytes(n, 1, precision) bytes,
+ * 256-byte aligned, alive until lion_destroy.  hip_stream: the hipStream_t
+ * every call of this handle runs on (NULL: the default stream).  Ions are
+ * created with zero position and velocity; call lion_set_state before
+ * stepping.  No trap field and no damping until set.  On failure *out is NULL
+ * and lion_last_error(NULL) says why: LION_ERR_ARG (n < 1, a mass not finite
+ * and > 0, a charge not finite, unknown precision), LION_ERR_WORKSPACE
+ * (missing, misaligned or too small), LION_ERR_HIP. */
 int lion_create(lion_sim **out, int64_t n, const double *masses_kg, const double *charges_C,
                 int precision, void *dev_workspace, size_t ws_bytes, void *hip_stream);
 
@@ -84,8 +98,12 @@ int lion_create_batch(lion_sim **out, int32_t n_traps, const int64_t *n_per_trap
                       void *dev_workspace, size_t ws_bytes, void *hip_stream);
 
 /* Positions (m) and velocities (m/s) of all ions and the current time t (s; for
- * a batch every trap's clock is set to t).  Computes the accelerations at
- * (x, t).  Non-finite input -> LION_ERR_ARG. */
+ * a batch every trap's clock is set to t) (section "Adding ions": ions placed
+ * at given coordinates, placeAtoms; the velocities are the initial condition
+ * of the equations of motion of section "Dynamics of trapped ions").  Six host
+ * arrays of length n_total, copied during the call.  Computes the
+ * accelerations at (x, t) with the kernels that step the handle.  Non-finite
+ * input or a NULL array -> LION_ERR_ARG.  Synchronises. */
 int lion_set_state(lion_sim *sim, const double *x, const double *y, const double *z,
                    const double *vx, const double *vy, const double *vz, double t);
 
@@ -219,41 +237,67 @@ int lion_set_pseudo_trap(lion_sim *sim, int32_t trap, double V_rf, double Omega_
 int lion_minimize(lion_sim *sim, double dt, double dmax_m, double ftol_N, int64_t max_iter,
                   int64_t *iterations, double *fmax_N);
 
-/* Device bytes lion_normal_modes needs for n ions (the (3n)^2 Hessian and
- * two vectors of 3n); 0 for n < 1.  Host-only. */
-size_t lion_normal_modes_workspace_bytes(int64_t n);
+/* Device bytes lion_normal_modes needs for this handle's n ions: the (3n)^2
+ * Hessian, two vectors of 3n, a status word and the scratch of rocSOLVER's
+ * dsyevd for a 3n x 3n problem.  The scratch size is asked of rocSOLVER in
+ * rocBLAS's size-query mode (nothing runs on the GPU and no device memory is
+ * allocated); the call creates the handle's rocBLAS handle on first use (kept
+ * until lion_destroy).  0 on failure (message in lion_last_error). */
+size_t lion_normal_modes_workspace_bytes(lion_sim *sim);
 
 /* Normal modes at the current positions (section "Normal modes of motion":
  * mode frequencies are the eigenvalues of the Hessian of eq. (fullPotential)).
  * A HIP kernel builds the mass-weighted Hessian D = H / sqrt(M_i M_j) of the
  * Coulomb pairs plus the static trap (pseudopotential and dc curvatures) in
  * FP64, in dev_work (caller-owned device memory, 256-byte aligned, at least
- * lion_normal_modes_workspace_bytes(n)); rocSOLVER's dsyevd diagonalises it on
- * the GPU (rocBLAS manages that solver's own scratch memory).  Outputs (host):
- * omega2 [3n] squared angular frequencies, ascending (rad^2/s^2); modes
+ * lion_normal_modes_workspace_bytes(sim) bytes); rocSOLVER's dsyevd
+ * diagonalises it on the GPU, with its scratch memory taken from the tail of
+ * dev_work (rocblas_set_workspace: rocBLAS allocates nothing for it).  Outputs
+ * (host): omega2 [3n] squared angular frequencies, ascending (rad^2/s^2); modes
  * [3n * 3n] or NULL: column k (stride 3n, column-major) is the mass-weighted
  * eigenvector of omega2[k], component 3i + axis.  A minimum of the potential
  * (lion_minimize) gives omega2 >= 0.  Time-dependent trap, batched handle or
  * rigid bodies -> LION_ERR_UNSUPPORTED; workspace too small or misaligned ->
- * LION_ERR_WORKSPACE; solver failure -> LION_ERR_HIP. */
+ * LION_ERR_WORKSPACE; solver failure -> LION_ERR_HIP.  Synchronises. */
 int lion_normal_modes(lion_sim *sim, void *dev_work, size_t bytes, double *omega2,
                       double *modes);
 
-/* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite).
- * nsteps = 0 is a no-op.  Time afterwards: t + nsteps dt.  Requires
- * lion_set_state first (else LION_ERR_STATE). */
+/* Advance every trap by nsteps (>= 0) steps of size dt (s, > 0, finite)
+ * (section "Time evolution": evolve(N) integrates the Newtonian equations of
+ * motion for N steps of the set time step; section "Integration": velocity
+ * Verlet; the step is written out at the top of this header).  nsteps = 0 is
+ * a no-op.  Time afterwards: t + nsteps dt; within the call
+ * t_k = t_call_start + k dt.  Runs as captured launch graphs of
+ * lion_kernel_config.chunk_steps steps; returns once they are queued.
+ * Requires lion_set_state first (else LION_ERR_STATE); nsteps < 0 or a bad
+ * dt -> LION_ERR_ARG. */
 int lion_step(lion_sim *sim, int64_t nsteps, double dt);
 
 /* As lion_step with a per-trap time step dt[k] (batches only). */
 int lion_step_batch(lion_sim *sim, int64_t nsteps, const double *dt_per_trap);
 
+/* Capture and instantiate the launch graphs that a following lion_step (or
+ * lion_step_batch) of nsteps steps replays, without running anything: no
+ * state, clock or step index changes.  For callers that keep graph
+ * instantiation out of a timed or latency-critical region.  The graphs hold
+ * the current launch shape and cooling switches; a later change of either
+ * drops them (they are then captured again on use).  nsteps < 0 ->
+ * LION_ERR_ARG; nsteps = 0 or plain launches (use_graph = 2) do nothing. */
+int lion_prepare_step(lion_sim *sim, int64_t nsteps);
+
 /* Copy the state to host arrays of length n_total (any pointer may be NULL to
- * skip it); *t receives the time (trap 0's clock for a batch). Synchronises. */
+ * skip it); *t receives the time (trap 0's clock for a batch) (section
+ * "Writing/reading data": the per-ion coordinates x, y, z and velocities vx,
+ * vy, vz that dump writes, in ion index order).  Synchronises. */
 int lion_get_state(const lion_sim *sim, double *x, double *y, double *z, double *vx,
                    double *vy, double *vz, double *t);
 
-/* Accelerations (m/s^2) at the current positions and time, recomputed now
- * (length n_total host arrays).  Synchronises. */
+/* Accelerations (m/s^2) at the current positions and time, recomputed now by
+ * the kernels that step the handle (length n_total host arrays): a_i =
+ * (Q_i/M_i)(E_c,i + E_ext(r_i, t)), eq. (field) with the Coulomb sum of eq.
+ * (fullPotential) (section "Dynamics of trapped ions"; the force of section
+ * "Forces and fields" that evolve integrates).  NULL output -> LION_ERR_ARG;
+ * state not set -> LION_ERR_STATE.  Synchronises. */
 int lion_compute_accel(lion_sim *sim, double *ax, double *ay, double *az);
 
 /* Kinetic energy sum M v^2/2, Coulomb energy sum_{i<j} k_e Q_i Q_j / r_ij

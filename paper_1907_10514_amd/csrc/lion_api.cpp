@@ -53,6 +53,7 @@ struct lion_sim {
     size_t body_off[5] = {0, 0, 0, 0, 0};
     bool tile_bodies = false;  // every 256-ion tile holds ions of one body only, or none
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (chunk length, kind)
+    void* eigh = nullptr;  // rocBLAS handle of the normal-mode solver (created on first use)
     std::string err;
 };
 
@@ -260,12 +261,19 @@ int upload_cooling(lion_sim* s, double dt) {
     return LION_OK;
 }
 
-// Accelerations at the current positions and clocks.
+// A single trap stepped inside one workgroup (the batched kernel with one trap).
+bool small_path_active(const lion_sim* s) {
+    return !s->batched && s->ls.small_path && s->n <= kMaxTrap && !s->has_bodies &&
+           s->d.nbodies == 0;
+}
+
+// Accelerations at the current positions and clocks, by the kernels that step
+// the handle (so a trap stepped inside one workgroup gets them from that kernel).
 int refresh_accel(lion_sim* s) {
     for (int k = 0; k < s->n_traps; ++k) s->traps[k].t_start = s->t_now[k];
     int rc = upload_traps(s);
     if (rc) return rc;
-    if (s->batched) {
+    if (s->batched || small_path_active(s)) {
         LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), s->stream));
         LION_HIP(s, lion::launch_batch_accel(s->d, s->precision, s->n_traps, s->max_trap, s->ls,
                                              s->stream));
@@ -284,7 +292,7 @@ hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
         if (e != hipSuccess) return e;
         return lion::launch_counter_add(s->d, L, st);
     }
-    if (s->ls.small_path && s->n <= kMaxTrap && !s->has_bodies && s->d.nbodies == 0) {
+    if (small_path_active(s)) {
         // the whole trap inside one workgroup, L steps per launch
         e = lion::launch_batch(s->d, s->precision, 1, (int)s->n, s->ls, (int)L, 0, st);
         if (e == hipSuccess) e = lion::launch_counter_add(s->d, L, st);
@@ -322,11 +330,9 @@ hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
     return hipSuccess;
 }
 
-int run_chunk(lion_sim* s, int64_t L) {
-    if (s->cfg.use_graph == 2) {
-        LION_HIP(s, enqueue_chunk(s, L, s->stream));
-        return LION_OK;
-    }
+// The captured graph of a chunk of L steps, captured and instantiated on
+// first use.
+int chunk_graph(lion_sim* s, int64_t L, hipGraphExec_t* out) {
     auto key = std::make_pair(L, 0);
     auto it = s->graphs.find(key);
     if (it == s->graphs.end()) {
@@ -345,8 +351,29 @@ int run_chunk(lion_sim* s, int64_t L) {
         if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
         it = s->graphs.emplace(key, ex).first;
     }
-    LION_HIP(s, hipGraphLaunch(it->second, s->stream));
+    *out = it->second;
     return LION_OK;
+}
+
+int run_chunk(lion_sim* s, int64_t L) {
+    if (s->cfg.use_graph == 2) {
+        LION_HIP(s, enqueue_chunk(s, L, s->stream));
+        return LION_OK;
+    }
+    hipGraphExec_t ex = nullptr;
+    int rc = chunk_graph(s, L, &ex);
+    if (rc) return rc;
+    LION_HIP(s, hipGraphLaunch(ex, s->stream));
+    return LION_OK;
+}
+
+// Whether the cooling kernels are needed by the current beams, baths and time
+// average (the launch graphs hold kernels built with or without them).
+bool cooling_on(const lion_sim* s) {
+    bool on = s->avg_window > 0;
+    for (const auto& B : s->beams) on = on || B.gamma > 0.0;
+    for (const auto& T : s->baths) on = on || T.tau > 0.0;
+    return on;
 }
 
 // K minimisation iterations: reduce + stopping test, move, forces at the new
@@ -616,6 +643,24 @@ int rigid_setup(lion_sim* s) {
     s->d.dbody = dbody;
     s->d.rmembers = members;
     s->d.rstart = start;
+    return LION_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Bytes of the fixed part of the normal-mode workspace: the (3n)^2 matrix, two
+// vectors of 3n and the solver's status word.
+size_t modes_fixed_bytes(int64_t n) {
+    const size_t m = (size_t)(3 * n);
+    return align_up(m * m * 8) + 2 * align_up(m * 8) + align_up(sizeof(int));
+}
+
+int modes_handle(lion_sim* s) {
+    if (s->eigh) return LION_OK;
+    std::string err;
+    if (lion::eigh_handle_create(&s->eigh, err) != 0) return fail(s, LION_ERR_HIP, err);
     return LION_OK;
 }
 
@@ -984,6 +1029,30 @@ int lion_step_batch(lion_sim* s, int64_t nsteps, const double* dt_per_trap) {
     return step_common(s, nsteps, dt_per_trap);
 }
 
+int lion_prepare_step(lion_sim* s, int64_t nsteps) {
+    if (check_handle(s)) return LION_ERR_ARG;
+    if (nsteps < 0) return fail(s, LION_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps == 0 || s->cfg.use_graph == 2) return LION_OK;
+    LION_HIP(s, hipSetDevice(s->device));
+    const bool on = cooling_on(s);
+    if (on != s->ls.cool_on) {
+        LION_HIP(s, hipStreamSynchronize(s->stream));  // no launch of a graph still pending
+        clear_graphs(s);
+        s->ls.cool_on = on;
+    }
+    const int64_t S = std::max(1, s->cfg.chunk_steps);
+    hipGraphExec_t ex = nullptr;
+    if (nsteps >= S) {
+        int rc = chunk_graph(s, S, &ex);
+        if (rc) return rc;
+    }
+    if (nsteps % S) {
+        int rc = chunk_graph(s, nsteps % S, &ex);
+        if (rc) return rc;
+    }
+    return LION_OK;
+}
+
 int lion_get_state(const lion_sim* cs, double* x, double* y, double* z, double* vx, double* vy,
                    double* vz, double* t) {
     lion_sim* s = const_cast<lion_sim*>(cs);
@@ -1022,10 +1091,20 @@ int lion_compute_accel(lion_sim* s, double* ax, double* ay, double* az) {
     return LION_OK;
 }
 
-size_t lion_normal_modes_workspace_bytes(int64_t n) {
-    if (n < 1) return 0;
-    const size_t m = (size_t)(3 * n);
-    return align_up(m * m * 8) + 2 * align_up(m * 8) + align_up(sizeof(int));
+size_t lion_normal_modes_workspace_bytes(lion_sim* s) {
+    if (check_handle(s) || s->n < 1 || 3 * s->n > 2147483647 / (3 * s->n)) return 0;
+    if (hipSetDevice(s->device) != hipSuccess || modes_handle(s) != LION_OK) return 0;
+    const int m = (int)(3 * s->n);
+    // sizes only: the solver is asked in query mode, with device addresses of
+    // the handle's own workspace standing in for the arrays
+    double* any = (double*)s->ws;
+    size_t scratch = 0;
+    std::string err;
+    if (lion::eigh_scratch_bytes(s->eigh, m, true, any, any, any, (int*)s->ws, &scratch, err) != 0) {
+        s->err = err;
+        return 0;
+    }
+    return modes_fixed_bytes(s->n) + align_up(scratch);
 }
 
 int lion_normal_modes(lion_sim* s, void* dev_work, size_t bytes, double* omega2, double* modes) {
@@ -1040,7 +1119,11 @@ int lion_normal_modes(lion_sim* s, void* dev_work, size_t bytes, double* omega2,
                     "normal modes need a static trap (pseudopotential trap or no rf)");
     if (3 * s->n > 2147483647 / (3 * s->n))
         return fail(s, LION_ERR_UNSUPPORTED, "too many ions for one dense eigen-problem");
-    int rc = check_ws(s, dev_work, bytes, lion_normal_modes_workspace_bytes(s->n));
+    const size_t fixed = modes_fixed_bytes(s->n);
+    int rc = check_ws(s, dev_work, bytes, fixed);
+    if (rc) return rc;
+    LION_HIP(s, hipSetDevice(s->device));
+    rc = modes_handle(s);
     if (rc) return rc;
     const int m = (int)(3 * s->n);
     char* base = (char*)dev_work;
@@ -1048,11 +1131,18 @@ int lion_normal_modes(lion_sim* s, void* dev_work, size_t bytes, double* omega2,
     double* W = (double*)(base + align_up((size_t)m * m * 8));
     double* E = (double*)(base + align_up((size_t)m * m * 8) + align_up((size_t)m * 8));
     int* info = (int*)(base + align_up((size_t)m * m * 8) + 2 * align_up((size_t)m * 8));
-    hipStream_t st = s->stream;
-    LION_HIP(s, hipSetDevice(s->device));
-    LION_HIP(s, lion::launch_hessian(s->d, T, A, st));
     std::string err;
-    if (lion::eigh_device(A, m, W, E, info, modes != nullptr, st, err) != 0)
+    size_t scratch = 0;
+    if (lion::eigh_scratch_bytes(s->eigh, m, modes != nullptr, A, W, E, info, &scratch, err) != 0)
+        return fail(s, LION_ERR_HIP, err);
+    if (bytes < fixed + scratch)
+        return fail(s, LION_ERR_WORKSPACE,
+                    "normal-mode workspace too small: need " + std::to_string(fixed + scratch) +
+                        " bytes (lion_normal_modes_workspace_bytes), got " + std::to_string(bytes));
+    hipStream_t st = s->stream;
+    LION_HIP(s, lion::launch_hessian(s->d, T, A, st));
+    if (lion::eigh_device(s->eigh, A, m, W, E, info, modes != nullptr, base + fixed,
+                          bytes - fixed, st, err) != 0)
         return fail(s, LION_ERR_HIP, err);
     int info_h = 0;
     LION_HIP(s, hipMemcpyAsync(omega2, W, (size_t)m * 8, hipMemcpyDeviceToHost, st));
@@ -1179,6 +1269,7 @@ void lion_destroy(lion_sim* s) {
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);
+    lion::eigh_handle_destroy(s->eigh);  // after the synchronisation: no solver work pending
     if (s->capture) (void)hipStreamDestroy(s->capture);
     delete s;
 }

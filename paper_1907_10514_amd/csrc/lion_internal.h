@@ -225,9 +225,17 @@ hipError_t launch_min_move(const DevState& s, int precision, hipStream_t st);
 hipError_t launch_hessian(const DevState& s, const TrapDev& T, double* D, hipStream_t st);
 // Eigenvalues (ascending, into W) and optionally eigenvectors (into A's
 // columns) of the symmetric m x m matrix A (upper triangle read) with
-// rocSOLVER; E is m doubles of scratch.  Returns 0 or -1 with err set.
-int eigh_device(double* A, int m, double* W, double* E, int* info, bool vectors, hipStream_t st,
-                std::string& err);
+// rocSOLVER on the rocBLAS handle h; E is m doubles of scratch and the solver
+// works in scratch (scratch_bytes from eigh_scratch_bytes).  Returns 0 or -1
+// with err set (lion_modes.cpp).
+int eigh_handle_create(void** h, std::string& err);
+void eigh_handle_destroy(void* h);
+// Solver scratch for an m x m problem, asked of rocSOLVER in rocBLAS's size
+// query mode (nothing runs; the pointers are device arrays of the call's sizes).
+int eigh_scratch_bytes(void* h, int m, bool vectors, double* A, double* W, double* E, int* info,
+                       size_t* bytes, std::string& err);
+int eigh_device(void* h, double* A, int m, double* W, double* E, int* info, bool vectors,
+                void* scratch, size_t scratch_bytes, hipStream_t st, std::string& err);
 hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
 hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
 hipError_t launch_check_finite(const DevState& s, hipStream_t st);

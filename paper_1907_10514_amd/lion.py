@@ -76,7 +76,7 @@ def load(path: str = LIB_PATH):
     lib.lion_set_species.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lion_set_pseudo_trap.argtypes = [vp, i32, d, d, d, d, d, d]
     lib.lion_minimize.argtypes = [vp, d, d, d, i64, ctypes.POINTER(ctypes.c_int64), dp]
-    lib.lion_normal_modes_workspace_bytes.argtypes = [i64]
+    lib.lion_normal_modes_workspace_bytes.argtypes = [vp]
     lib.lion_normal_modes_workspace_bytes.restype = sz
     lib.lion_normal_modes.argtypes = [vp, vp, sz, dp, dp]
     lib.lion_set_rigid_bodies.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.lion_get_time_average.argtypes = [vp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lion_step.argtypes = [vp, i64, d]
     lib.lion_step_batch.argtypes = [vp, i64, dp]
+    lib.lion_prepare_step.argtypes = [vp, i64]
     lib.lion_get_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
     lib.lion_compute_accel.argtypes = [vp, dp, dp, dp]
     lib.lion_get_energy.argtypes = [vp, dp, dp, dp]
@@ -109,10 +110,11 @@ def load(path: str = LIB_PATH):
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
                  "lion_set_damping", "lion_set_bodies", "lion_set_rigid_bodies",
                  "lion_get_rigid_state", "lion_set_pseudo_trap", "lion_minimize",
-                 "lion_normal_modes_workspace_bytes", "lion_normal_modes",
+                 "lion_normal_modes",
                  "lion_set_species", "lion_set_beam",
                  "lion_set_bath", "lion_set_step_index", "lion_set_time_average",
-                 "lion_get_time_average", "lion_step", "lion_step_batch", "lion_get_state",
+                 "lion_get_time_average", "lion_step", "lion_step_batch", "lion_prepare_step",
+                 "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite", "lion_count_lost",
                  "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
                  "lion_time_pair_kernel", "lion_time_batch_kernel"):
@@ -216,8 +218,11 @@ def lion_minimize(h, dt, dmax, ftol, max_iter):
     return int(it.value), float(fm.value)
 
 
-def lion_normal_modes_workspace_bytes(n):
-    return int(load().lion_normal_modes_workspace_bytes(int(n)))
+def lion_normal_modes_workspace_bytes(h):
+    nb = int(load().lion_normal_modes_workspace_bytes(h))
+    if nb == 0:
+        raise LionError(LION_ERR_HIP, lion_last_error(h))
+    return nb
 
 
 def lion_normal_modes(h, n, ws_ptr, ws_bytes, vectors=False):
@@ -273,6 +278,10 @@ def lion_step(h, nsteps, dt):
 def lion_step_batch(h, nsteps, dts):
     d = _f64(dts)
     _check(load().lion_step_batch(h, int(nsteps), _dp(d)), h)
+
+
+def lion_prepare_step(h, nsteps):
+    _check(load().lion_prepare_step(h, int(nsteps)), h)
 
 
 def lion_get_state(h, n):
@@ -433,7 +442,7 @@ class Simulation:
         the current positions; device scratch is a temporary torch tensor."""
         import torch
 
-        nb = lion_normal_modes_workspace_bytes(self.n)
+        nb = lion_normal_modes_workspace_bytes(self.h)
         ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
         ptr = (ws.data_ptr() + 255) // 256 * 256
         try:
@@ -481,6 +490,11 @@ class Simulation:
             lion_step_batch(self.h, nsteps, dt)
         else:
             lion_step(self.h, nsteps, dt)
+
+    def prepare_step(self, nsteps):
+        """Capture the launch graphs of a following step(nsteps, ...) call
+        without running it."""
+        lion_prepare_step(self.h, nsteps)
 
     def get_state(self):
         return lion_get_state(self.h, self.n)

@@ -139,13 +139,10 @@ def test_binding_fails_loudly_without_library(tmp_path):
         lion._lib = saved
 
 
-def test_normal_modes_workspace_size():
-    from paper_1907_10514_amd import lion as L
-
-    def up(b):
-        return (b + 255) // 256 * 256
-
-    assert L.lion_normal_modes_workspace_bytes(0) == 0
-    for n in (1, 7, 1000):
-        m = 3 * n
-        assert L.lion_normal_modes_workspace_bytes(n) == up(m * m * 8) + 2 * up(m * 8) + up(4)
+def test_null_handle_sizes_and_prepare_are_rejected():
+    """The normal-mode workspace size is asked of the handle (it includes the
+    eigen-solver's scratch): no handle, no size.  Preparing graphs needs a
+    handle too."""
+    lib = lion.load()
+    assert lib.lion_normal_modes_workspace_bytes(None) == 0
+    assert lib.lion_prepare_step(None, 10) == lion.LION_ERR_ARG

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import lion_inputs as li
+from tests import trajectory_bar as tb
 
 pytestmark = pytest.mark.gpu
 
@@ -226,32 +227,17 @@ def test_lost_ion_check(torch_gpu, oracle_mod):
     assert lost[0.3] == 0 and lost[1.2] > 250
 
 
-def _divergence_envelope(oracle_mod, w, nsteps, rel):
-    """How far the oracle's own run of ``nsteps`` moves when every start
-    position is moved by one ulp (rel None) or by a seeded relative amount rel
-    (the chaotic-cloud bar: 10x this envelope)."""
-    spec = w.traps[0]
-    tr = _oracle_trap(oracle_mod, spec)
-    s1 = w.state()
-    s2 = {k: v.copy() for k, v in s1.items()}
-    rng = np.random.default_rng(0)
-    for k in ("x", "y", "z"):
-        s2[k] = np.nextafter(s2[k], np.inf) if rel is None else \
-            s2[k] * (1 + rel * rng.normal(size=s2[k].size))
-    a = oracle_mod.step(s1, w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, nsteps)
-    b = oracle_mod.step(s2, w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, nsteps)
-    return max(np.max(np.abs(a[k] - b[k])) for k in ("x", "y", "z"))
-
-
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
-    """Pair-once kernels at 16384 ions (sampled targets) and over 45 steps:
-    bitwise reproducible, and equal to the all-pairs kernels within tol x
-    extent, or, where this dense cloud's chaos amplifies rounding beyond that,
-    within 10x the oracle's own divergence under a start perturbation of the
-    path's rounding size (one ulp for FP64, 1e-7 relative for FP32 pairs)."""
+    """Pair-once kernels at 16384 ions: sampled targets against the oracle;
+    45 steps bitwise reproducible; and the first SEGMENT steps of the pair-once
+    and of the all-pairs kernels against the oracle, ion by ion within 10x the
+    envelope of the oracle's own run under per-step kicks of dt M1 A_i (M1 the
+    larger measured force error of the two).  FP64 also compares 45 steps of
+    the two kernels within max(1e-12 x extent, 10x the one-ulp envelope)."""
     w = li.mixed16384()
-    tr = _oracle_trap(oracle_mod, w.traps[0])
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
     sim = _sim(w, prec, oracle_mod, symmetric=2)
     a = sim.compute_accel()
     idx = np.random.default_rng(1).choice(w.n, 512, replace=False)
@@ -259,24 +245,48 @@ def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
     err = _m1((a[0][idx], a[1][idx], a[2][idx]), (rx, ry, rz), sc)
     print(f"pair-once N=16384 {prec} sampled M1={err:.3e}")
     assert err <= TOL[prec]
+    sim.close()
+    # the segment against the oracle, both kernels
+    ref_a = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    scale = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    segs, m1 = {}, 0.0
+    for sym in (2, 1):
+        s2 = _sim(w, prec, oracle_mod, symmetric=sym)
+        m1 = max(m1, tb.m1(s2.compute_accel(), ref_a, scale))
+        s2.step(tb.SEGMENT, spec.dt)
+        segs[sym] = s2.get_state()[0]
+        s2.close()
+    ref = oracle_mod.step(w.state(), w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, tb.SEGMENT)
+    kicked = tb.kicked_run(
+        lambda st, k: oracle_mod.step(st, w.charge, w.mass, tr, spec.gamma, k * spec.dt, spec.dt, 1),
+        tb.nudge(w.state()), tb.SEGMENT, tb.kick(scale, max(m1, tb.M1_FLOOR), spec.dt))
+    for sym, got in segs.items():
+        r = (tb.ratio(got, ref, kicked, tb.X), tb.ratio(got, ref, kicked, tb.V))
+        print(f"N=16384 {prec} symmetric={sym}: {tb.SEGMENT} steps, M1 {m1:.2e}, "
+              f"|dx| {r[0]:.2f} bars, |dv| {r[1]:.2f} bars")
+        assert r[0] <= 1 and r[1] <= 1, sym
+    if prec != "fp64":
+        assert m1 <= tb.M1_REF
+    # 45 steps: reproducible bits; FP64 also equal across kernels to roundoff growth
     outs = []
     for sym in (2, 2, 1):
         s2 = _sim(w, prec, oracle_mod, symmetric=sym)
-        s2.step(45, w.traps[0].dt)
+        s2.step(45, spec.dt)
         outs.append(s2.get_state()[0])
         s2.close()
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
-    ext = np.max(np.abs(w.x))
-    tol = 1e-12 if prec == "fp64" else 1e-6
-    err = max(np.max(np.abs(outs[0][k] - outs[2][k])) for k in ("x", "y", "z"))
-    bar = tol * ext
-    if err >= bar:
-        env = _divergence_envelope(oracle_mod, w, 45, None if prec == "fp64" else 1e-7)
-        print(f"pair-once N=16384 {prec}: 45-step |dx| {err:.3e} > {bar:.3e}; envelope {env:.3e}")
-        bar = max(bar, 10 * env)
-    assert err < bar
-    sim.close()
+    if prec == "fp64":
+        ext = np.max(np.abs(w.x))
+        err = tb.divergence(outs[0], outs[2], tb.X)
+        bar = 1e-12 * ext
+        if err >= bar:
+            env, _ = tb.ulp_envelope(
+                lambda st: oracle_mod.step(st, w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, 45),
+                w.state())
+            print(f"pair-once N=16384 fp64: 45-step |dx| {err:.3e} > {bar:.3e}; envelope {env:.3e}")
+            bar = max(bar, 10 * env)
+        assert err < bar
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -578,9 +588,17 @@ def test_batch_equals_single_trap_path(torch_gpu, oracle_mod):
         sim.step(120, li.DT)
         out.append(sim.get_state()[0])
         sim.close()
+    # two FP64 paths of different summation order: within max(1e-12 x extent,
+    # 10x the oracle's divergence under a one-ulp start shift) over 120 steps
     ext = np.max(np.abs(w.x))
-    for k in ("x", "y", "z"):
-        assert np.max(np.abs(out[0][k] - out[1][k])) < 1e-10 * ext
+    err = tb.divergence(out[0], out[1], tb.X)
+    bar = 1e-12 * ext
+    if err >= bar:
+        env, _ = tb.ulp_envelope(
+            lambda st: oracle_mod.step(st, w.charge, w.mass, tr, 1e5, 0.0, li.DT, 120), w.state())
+        print(f"batched vs single-trap kernels: 120-step |dx| {err:.3e}, ulp envelope {env:.3e}")
+        bar = max(bar, 10 * env)
+    assert err < bar
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
@@ -615,6 +633,68 @@ def test_small_trap_path_equals_multi_workgroup_path(torch_gpu, oracle_mod, n, p
     for k in ("vx", "vy", "vz"):
         assert np.max(np.abs(a[k] - b[k])) < tol * 1e3 * vs, k
     assert np.max(np.abs(fa - fb)) <= tol * 1e3 * np.max(np.abs(fa))
+
+
+SMALL_SIZES = [1, 2, 3, 8, 31, 32, 33, 63, 64, 65, 100, 128, 129, 160]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+@pytest.mark.parametrize("charges", ["common", "mixed"])
+def test_small_trap_accel_parity(torch_gpu, oracle_mod, prec, charges):
+    """A single trap stepped inside one workgroup evaluates its forces with that
+    kernel (lone trap: one target per thread, sources split over the parts);
+    at every size up to the default limit the force meets the bar."""
+    for n in SMALL_SIZES:
+        q = None if charges == "common" else np.random.default_rng(n).choice([1, 2, -1], n)
+        w = li.random_cloud(n, seed=900 + n, sigma=20e-6 * max(1, n / 8) ** (1 / 3),
+                            light_fraction=0.3, charge_e=q)
+        sim = _sim(w, prec, oracle_mod, small_trap=2)
+        assert sim.config()["small_trap"] == 2
+        tr = _oracle_trap(oracle_mod, w.traps[0])
+        r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+        sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+        err = _m1(sim.compute_accel(), r, sc)
+        assert err <= TOL[prec], (n, err)
+        sim.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "mixed_kahan"])
+@pytest.mark.parametrize("n", [8, 64, 100, 160])
+def test_small_trap_fp32_run_matches_oracle(torch_gpu, oracle_mod, n, prec):
+    """The one-workgroup stepping path (the default for <= 160 ions) in the FP32
+    modes over 200 steps: at steps 0, 100 and 190 the run is re-anchored and
+    its next SEGMENT steps are compared with the oracle's run from the GPU's
+    state, ion by ion within 10x the envelope of the oracle's own segment under
+    per-step kicks of dt M1 A_i, M1 measured on that kernel's force there."""
+    w = li.random_cloud(n, seed=800 + n, sigma=20e-6 * max(1, n / 8) ** (1 / 3),
+                        light_fraction=0.3)
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
+    sim = _sim(w, prec, oracle_mod, small_trap=2)
+    assert sim.config()["small_trap"] == 2
+    anchors = (0, 100, 190)
+    states, done = {0: (w.state(), 0.0, sim.compute_accel())}, 0
+    for k in (10, 100, 110, 190, 200):
+        sim.step(k - done, spec.dt)
+        done = k
+        st, t = sim.get_state()
+        states[k] = (st, t, sim.compute_accel() if k in anchors else None)
+    for k0 in anchors:
+        s0, t0, a0 = states[k0]
+        ra = oracle_mod.accel(s0["x"], s0["y"], s0["z"], w.charge, w.mass, tr, t0)
+        sc = oracle_mod.accel_scale(s0["x"], s0["y"], s0["z"], w.charge, w.mass, tr, t0)
+        m1 = tb.m1(a0, ra, sc)
+        ref = oracle_mod.step(s0, w.charge, w.mass, tr, spec.gamma, t0, spec.dt, tb.SEGMENT)
+        kicked = tb.kicked_run(
+            lambda st, k: oracle_mod.step(st, w.charge, w.mass, tr, spec.gamma, t0 + k * spec.dt,
+                                          spec.dt, 1),
+            tb.nudge(s0), tb.SEGMENT, tb.kick(sc, max(m1, tb.M1_FLOOR), spec.dt))
+        got = states[k0 + tb.SEGMENT][0]
+        rx, rv = tb.ratio(got, ref, kicked, tb.X), tb.ratio(got, ref, kicked, tb.V)
+        print(f"n={n} {prec} from step {k0}: M1 {m1:.2e}, |dx| {rx:.2f} bars, |dv| {rv:.2f} bars")
+        assert m1 <= min(TOL[prec], tb.M1_REF), (k0, m1)
+        assert rx <= 1 and rv <= 1, (k0, rx, rv)
+    sim.close()
 
 
 def test_crystal8_full_run_matches_oracle_on_both_paths(torch_gpu, oracle_mod):

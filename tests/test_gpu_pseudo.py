@@ -297,3 +297,31 @@ def test_normal_modes_single_ion_and_rejections(torch_gpu, oracle_mod):
         L.lion_normal_modes(sim.h, 1, small.data_ptr(), 256)
     assert ei.value.code == L.LION_ERR_WORKSPACE
     sim.close()
+
+
+def test_normal_modes_workspace_holds_the_solver_scratch(torch_gpu, oracle_mod):
+    """The solver's scratch is part of the caller's workspace: the size asked of
+    the handle covers the Hessian, two vectors and the rocSOLVER scratch; one
+    byte less than the Hessian part is refused, and the full size works twice
+    in a row on one handle (one rocBLAS handle per simulation)."""
+    from paper_1907_10514_amd import LionError
+    from paper_1907_10514_amd import lion as L
+    import torch
+
+    tr, m, q, st = _modes_case(oracle_mod, "chain6")
+    sim = _sim(m, q, "fp64", tr, st)
+    n = len(m)
+    up = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    fixed = up((3 * n) ** 2 * 8) + 2 * up(3 * n * 8) + up(4)
+    nb = L.lion_normal_modes_workspace_bytes(sim.h)
+    assert nb > fixed
+    buf = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    ptr = (buf.data_ptr() + 255) // 256 * 256
+    with pytest.raises(LionError) as ei:
+        L.lion_normal_modes(sim.h, n, ptr, fixed - 1)
+    assert ei.value.code == L.LION_ERR_WORKSPACE
+    ref, _ = oracle_mod.normal_modes(st["x"], st["y"], st["z"], q, m, tr)
+    for vectors in (True, False):
+        w2, _ = L.lion_normal_modes(sim.h, n, ptr, nb, vectors)
+        assert np.max(np.abs(w2 - ref)) < 1e-12 * np.max(np.abs(ref))
+    sim.close()
