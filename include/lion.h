@@ -383,6 +383,30 @@ int lion_time_pair_kernel(lion_sim *sim, int32_t reps, double *ms_avg);
 int lion_time_batch_kernel(lion_sim *sim, int32_t reps, int32_t nsteps, double dt,
                            double *ms_avg);
 
+/* Allocation-free force evaluation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The accelerations (m/s^2) that lion_compute_accel gives
+ * on a single-trap handle of these ions with this trap (lion_set_trap's
+ * parameters, full rf field, no bodies) at time t, from the same all-pairs
+ * kernels: a_i = (Q_i/M_i)(E_c,i + E_ext(r_i, t)).  No handle, no workspace:
+ * x, y, z (m), charges_C, masses_kg and the outputs ax, ay, az are device
+ * arrays of n doubles owned by the caller; the packed source streams, Q/M,
+ * the trap and the per-slice partial sums live in one 8 MiB device array of
+ * the library (a file-scope __device__ array, its address taken once per
+ * device on the first call there, held until the process ends).  Hence
+ * 1 <= n <= 65536 (else LION_ERR_ARG, before any device work), and calls on
+ * one GPU share that array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  Runs on hip_stream
+ * (NULL: the default stream) and returns once queued; calls no hipMalloc,
+ * hipFree or allocating library routine.  NULL pointers, a bad trap (as
+ * lion_set_trap), a non-finite t or an unknown precision -> LION_ERR_ARG;
+ * lion_last_error(NULL) gives the message. */
+int lion_accel_noalloc(int64_t n, const double *x, const double *y, const double *z,
+                       const double *charges_C, const double *masses_kg, double V_rf,
+                       double Omega_rad_s, double U_dc, double r0, double z0, double kappa,
+                       double t, int precision, double *ax, double *ay, double *az,
+                       void *hip_stream);
+
 /* Host-only helper, eq. (Mathieuaq): the (V0, U0) giving Mathieu coefficients
  * (q_x, a_x) to an ion of mass M (kg) and charge Q (C) in a trap of angular
  * frequency Omega and geometry (r0, z0, kappa).  LION_ERR_ARG on invalid input. */

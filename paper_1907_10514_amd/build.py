@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblion.so")
-SOURCES = ["lion_kernels.hip", "lion_api.cpp", "lion_rigid_host.cpp", "lion_modes.cpp"]
+SOURCES = ["lion_kernels.hip", "lion_noalloc.hip", "lion_api.cpp", "lion_rigid_host.cpp",
+           "lion_modes.cpp"]
 # rocSOLVER (with rocBLAS) diagonalises the normal-mode Hessian
 LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 

@@ -427,7 +427,8 @@ int check_ws(lion_sim* s, void* ws, size_t bytes, size_t need) {
     return LION_OK;
 }
 
-// Message of the last failed create on this thread (no handle exists then).
+// Message of the last failed call without a handle on this thread (a failed
+// create, the allocation-free force evaluation).
 thread_local std::string g_create_err;
 
 int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, int64_t n,
@@ -647,6 +648,8 @@ int rigid_setup(lion_sim* s) {
 }
 
 }  // namespace
+
+void lion::set_handle_free_error(const std::string& msg) { g_create_err = msg; }
 
 namespace {
 

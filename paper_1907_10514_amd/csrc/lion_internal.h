@@ -213,6 +213,13 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
 hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls, int mode,
                          bool use_counter, hipStream_t st);
 hipError_t launch_pack_mixed(const DevState& s, hipStream_t st);
+// Device arrays x, y, z, charge (C), mass (kg) of s.n ions into s.src, s.srcm
+// (if set), s.qm, s.qe (zero charge up to s.n_pad) and T into s.traps[0].
+hipError_t launch_pack_inputs(const double* x, const double* y, const double* z,
+                              const double* charge, const double* mass, const DevState& s,
+                              const TrapDev& T, hipStream_t st);
+// Message returned by lion_last_error(NULL) (calls without a handle).
+void set_handle_free_error(const std::string& msg);
 hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_trap,
                         const LaunchShape& ls, int nsteps, int mode_first, hipStream_t st);
 hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int max_trap,

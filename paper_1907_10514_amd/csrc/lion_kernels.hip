@@ -410,6 +410,37 @@ __global__ __launch_bounds__(256) void k_drift(double4* __restrict__ src,
     if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
 }
 
+// Inputs of the allocation-free force evaluation in the layout of the pair and
+// epilogue kernels: the FP64 source stream {x, y, z, 1.5 q/e}, the FP32 stream
+// (mixed precisions), Q/M and Q/e per ion (zero charge from n up to n_pad), and
+// the trap parameters (written by thread 0).
+__global__ __launch_bounds__(256) void k_pack_inputs(const double* __restrict__ x,
+                                                     const double* __restrict__ y,
+                                                     const double* __restrict__ z,
+                                                     const double* __restrict__ charge,
+                                                     const double* __restrict__ mass, int64_t n,
+                                                     int64_t n_pad, double4* __restrict__ src,
+                                                     MixedSrc* __restrict__ srcm,
+                                                     double* __restrict__ qm,
+                                                     double* __restrict__ qe, TrapDev T,
+                                                     TrapDev* __restrict__ tout) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *tout = T;
+    if (i >= n_pad) return;
+    if (i < n) {
+        const double q = charge[i] / kElementaryCharge;
+        src[i] = make_double4(x[i], y[i], z[i], 1.5 * q);
+        if (srcm) srcm[i] = make_src(x[i], y[i], z[i], q);
+        qm[i] = charge[i] / mass[i];
+        qe[i] = q;
+    } else {
+        src[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (srcm) srcm[i] = make_src(0.0, 0.0, 0.0, 0.0);
+        qm[i] = 0.0;
+        qe[i] = 0.0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pack_mixed(const double4* __restrict__ src,
                                                     MixedSrc* __restrict__ srcm,
                                                     const double* __restrict__ qe, int64_t n,
@@ -2188,6 +2219,15 @@ hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st) {
         k_drift<false><<<blocks_for(s.n, 256), 256, 0, st>>>(
             s.src, s.srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qe, s.mass, s.species, s.traps,
             s.cool, s.counter, s.rb, s.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_inputs(const double* x, const double* y, const double* z,
+                              const double* charge, const double* mass, const DevState& s,
+                              const TrapDev& T, hipStream_t st) {
+    k_pack_inputs<<<blocks_for(s.n_pad, 256), 256, 0, st>>>(x, y, z, charge, mass, s.n, s.n_pad,
+                                                            s.src, s.srcm, s.qm, s.qe, T,
+                                                            s.traps);
     return hipGetLastError();
 }
 

@@ -105,6 +105,8 @@ def load(path: str = LIB_PATH):
     lib.lion_time_pair_kernel.argtypes = [vp, i32, dp]
     lib.lion_time_batch_kernel.argtypes = [vp, i32, i32, d, dp]
     lib.lion_mathieu_to_voltages.argtypes = [d, d, d, d, d, d, d, d, dp, dp]
+    lib.lion_accel_noalloc.argtypes = [i64, vp, vp, vp, vp, vp, d, d, d, d, d, d, d,
+                                       ctypes.c_int, vp, vp, vp, vp]
     lib.lion_constants.argtypes = [dp, dp, dp]
     lib.lion_constants.restype = None
     for name in ("lion_create", "lion_create_batch", "lion_set_state", "lion_set_trap",
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH):
                  "lion_get_state",
                  "lion_compute_accel", "lion_get_energy", "lion_check_finite", "lion_count_lost",
                  "lion_set_kernel_config", "lion_get_kernel_config", "lion_mathieu_to_voltages",
-                 "lion_time_pair_kernel", "lion_time_batch_kernel"):
+                 "lion_time_pair_kernel", "lion_time_batch_kernel", "lion_accel_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -344,6 +346,18 @@ def lion_time_batch_kernel(h, reps, nsteps, dt) -> float:
     _check(load().lion_time_batch_kernel(h, int(reps), int(nsteps), float(dt), ctypes.byref(ms)),
            h)
     return ms.value
+
+
+def lion_accel_noalloc(n, x_ptr, y_ptr, z_ptr, charge_ptr, mass_ptr, V_rf, Omega, U_dc, r0, z0,
+                       kappa, t, precision, ax_ptr, ay_ptr, az_ptr, stream_ptr):
+    """Allocation-free force evaluation; every array argument is a device
+    address (int) of n doubles."""
+    vp = ctypes.c_void_p
+    _check(load().lion_accel_noalloc(int(n), vp(x_ptr), vp(y_ptr), vp(z_ptr), vp(charge_ptr),
+                                     vp(mass_ptr), float(V_rf), float(Omega), float(U_dc),
+                                     float(r0), float(z0), float(kappa), float(t),
+                                     int(precision), vp(ax_ptr), vp(ay_ptr), vp(az_ptr),
+                                     vp(stream_ptr)))
 
 
 def lion_mathieu_to_voltages(q_x, a_x, M, Q, Omega, r0, z0, kappa):

@@ -146,3 +146,15 @@ def test_null_handle_sizes_and_prepare_are_rejected():
     lib = lion.load()
     assert lib.lion_normal_modes_workspace_bytes(None) == 0
     assert lib.lion_prepare_step(None, 10) == lion.LION_ERR_ARG
+
+
+def test_allocation_free_call_refuses_sizes_beyond_its_scratch():
+    """lion_accel_noalloc checks its size against the fixed scratch array before
+    any device work (no GPU here)."""
+    lib = lion.load()
+    d = ctypes.c_double
+    for n in (0, 65537):
+        rc = lib.lion_accel_noalloc(n, 8, 8, 8, 8, 8, d(9.0), d(li.OMEGA), d(0.24), d(li.R0),
+                                    d(li.Z0), d(li.KAPPA), d(0.0), 0, 8, 8, 8, None)
+        assert rc == lion.LION_ERR_ARG
+        assert "65536" in lib.lion_last_error(None).decode()
