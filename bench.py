@@ -511,7 +511,7 @@ def main():
             out["clusters65536"]["oracle"] = cpu_baseline_clusters(2)
         if not args.no_small:
             out["small_configs"] = {}
-            for wk, steps, osteps in ((li.crystal8(), 20000, 20000), (li.crystal1024(), 5000, 2000)):
+            for wk, steps, osteps in ((li.crystal8(), 20000, 20000), (li.crystal1024(), 50000, 2000)):
                 log(f"[bench] {wk.name}: {steps} GPU steps, {osteps} oracle steps")
                 out["small_configs"][wk.name] = time_small(torch, wk, steps, osteps)
                 r = out["small_configs"][wk.name]

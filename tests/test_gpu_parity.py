@@ -371,6 +371,54 @@ def test_crystal1024_short_run(torch_gpu, oracle_mod, prec, tol):
     sim.close()
 
 
+def test_crystal1024_observables_match_oracle(torch_gpu, oracle_mod):
+    """The 1024-ion cooling run (gamma = 2e5/s, 50000 steps, FP64) forms a
+    crystal; its trajectories are chaotic, so its label-free observables are
+    compared (section "Verifications / Cooling mechanisms"): the kinetic
+    temperature every 1000 steps (every 50 rf periods) and the final energy
+    per ion, against the oracle's run stored in tests/golden (written by
+    make_crystal1024_observables.py).  Stated tolerance per sample: 3x the
+    largest deviation from the oracle's run of its twins (the same run from
+    starts moved by one ulp), and at least 0.5 % of the temperature; energies
+    per ion within 3x the twins' largest deviation."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "crystal1024_observables.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    w = li.crystal1024()
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
+    sim = _sim(w, "fp64", oracle_mod)
+    every = gold["every"]
+    temps = [float(np.sum(0.5 * w.mass * (w.vx ** 2 + w.vy ** 2 + w.vz ** 2))
+                   / (1.5 * w.n * li.K_B))]
+    for _ in range(w.nsteps // every):
+        sim.step(every, spec.dt)
+        st, t = sim.get_state()
+        v2 = st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2
+        temps.append(float(np.sum(0.5 * w.mass * v2) / (1.5 * w.n * li.K_B)))
+    assert t == pytest.approx(gold["base"]["t_end"], rel=1e-15, abs=0)
+    base = np.array(gold["base"]["temperature_K"])
+    twins = np.array([tw["temperature_K"] for tw in gold["twins"]])
+    tol = np.maximum(3 * np.max(np.abs(twins - base), axis=0), 5e-3 * base)
+    dev = np.abs(np.array(temps) - base)
+    k = int(np.argmax(dev / tol))
+    print(f"temperature: worst sample {k * every} steps, GPU {temps[k]:.5e} K, oracle "
+          f"{base[k]:.5e} K, deviation {dev[k] / tol[k]:.2f} of the tolerance; final "
+          f"{temps[-1]:.5e} K against {base[-1]:.5e} K")
+    assert np.all(dev <= tol)
+    kin, coul, dc = sim.energy()
+    for name, val in (("kinetic", kin), ("coulomb", coul), ("dc_trap", dc)):
+        ref = gold["base"]["energy_per_ion_J"][name]
+        spread = max(abs(tw["energy_per_ion_J"][name] - ref) for tw in gold["twins"])
+        print(f"energy per ion {name}: GPU {val / w.n:.6e} J, oracle {ref:.6e} J, "
+              f"twin spread {spread:.2e}")
+        assert abs(val / w.n - ref) <= 3 * spread, name
+    sim.close()
+
+
 def test_centre_of_mass_follows_single_ion_on_gpu(torch_gpu, oracle_mod):
     """Kohn: with one species the centre of mass of the GPU run follows the
     oracle's single-ion trajectory (full rf, damping)."""
