@@ -1361,10 +1361,26 @@ __global__ __launch_bounds__(256) void k_count_lost(const double4* __restrict__ 
 // in registers for the whole launch; the trap's source stream lives in LDS.
 
 constexpr int kMaxTrap = 1024;
-constexpr double kFarPad = 1e6;  // m: position of padding sources on the common-charge path
 // Traps of at least kBatchTpt4 (kBatchTpt2) ions give each thread 4 (2) targets.
 constexpr int kBatchTpt4 = 256;
 constexpr int kBatchTpt2 = 128;
+
+
+// One source of the batched FP32 pair loops: the position scaled by 2^20 per
+// metre (exact) in FP64, so that the difference to a target is formed in FP64
+// and rounded once to FP32 (three FP64 subtractions and three conversions per
+// pair, against nine FP32 operations on float-float parts), then the negated
+// charge and the r^2 floor as FP32 operands.
+struct BatchMixedSrc {
+    double x, y, z;
+    float nq, r2floor;
+};
+
+// Whether the batched loops of precision prec factor a common charge out of
+// the pair sums: FP64 and FP32 + FP64 runs (the 512-trap batch: 34.8 against
+// 35.4 us and 29.8 against 30.2 us per step); not the compensated mode, whose
+// loop measured 10 % slower without the charge multiply.
+__device__ __forceinline__ bool batch_fq_on(int prec) { return prec != 2; }
 
 template <int PREC>
 struct BatchSrc;
@@ -1374,18 +1390,45 @@ struct BatchSrc<0> {
 };
 template <>
 struct BatchSrc<1> {
-    using T = MixedSrc;
+    using T = BatchMixedSrc;
 };
 template <>
 struct BatchSrc<2> {
-    using T = MixedSrc;
+    using T = MixedSrc;  // the compensated mode keeps float-float differences
 };
 
+__device__ __forceinline__ BatchMixedSrc make_batch_src(double x, double y, double z, double qe) {
+    BatchMixedSrc s;
+    s.x = x * kMixedScale;
+    s.y = y * kMixedScale;
+    s.z = z * kMixedScale;
+    s.nq = (float)(-qe);
+    s.r2floor = kR2FloorF32;
+    return s;
+}
+
+// One FP32 pair term from a batched source: d rounded once from the FP64
+// difference; returns r^-3 d (UNIT) or -q r^-3 d in (tx, ty, tz).
+template <bool UNIT>
+__device__ __forceinline__ void batch_pair_f32(const BatchMixedSrc& p, double xi, double yi,
+                                               double zi, float& tx, float& ty, float& tz) {
+    const float dx = (float)(p.x - xi), dy = (float)(p.y - yi), dz = (float)(p.z - zi);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, p.r2floor)));
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float w = UNIT ? y * (y * y) : (p.nq * y) * (y * y);
+    tx = w * dx;
+    ty = w * dy;
+    tz = w * dz;
+}
+
 // Field sums of TPT targets per thread over the sources [jb, je) of the LDS
-// stream: each source is read once for all TPT targets (il_k = slot + ws k),
+// stream (je <= m: only the trap's ions, no padding): each source is read once
+// for all TPT targets (il_k = slot + ws k),
 // which cuts the broadcast LDS reads per pair by TPT.  Per target the sums run
 // over the sources in order, as with one target per thread (FP32 runs of 8
 // flushed to FP64, or Kahan).  Targets at or beyond m give unused sums.
+// FQ: every ion carries the charge uq (units of e); the sums run over r^-3 d
+// alone and are scaled by the charge once.
 template <int PREC, int TPT, bool FQ>
 __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>::T* __restrict__ lds,
                                                   int m, int slot, int ws, int jb, int je,
@@ -1407,7 +1450,22 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
             zi[k] = me.z;
             sx[k] = sy[k] = sz[k] = 0.0;
         }
-        for (int j = jb; j < je; ++j) {
+        // sources four at a time, then the last one to three
+        const int j4 = jb + ((je - jb) & ~3);
+        for (int j = jb; j < j4; j += 4) {
+#pragma unroll
+            for (int uu = 0; uu < 4; ++uu) {
+                const double4 p = lds[j + uu];
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    if constexpr (FQ)
+                        pair_f64_unit(p, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                    else
+                        pair_f64(p, xi[k], yi[k], zi[k], sx[k], sy[k], sz[k]);
+                }
+            }
+        }
+        for (int j = j4; j < je; ++j) {
             const double4 p = lds[j];
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
@@ -1424,81 +1482,113 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
             Sy[k] = FQ ? sy[k] * cq : sy[k];
             Sz[k] = FQ ? sz[k] * cq : sz[k];
         }
-    } else if constexpr (PREC == 1) {
-        FF t[TPT];
-        double sx[TPT], sy[TPT], sz[TPT];
+    } else {
+        // the unit-weight terms leave out the -q_j factor
+        const double cs = FQ ? -uq * kMixedFieldScale : kMixedFieldScale;
+        if constexpr (PREC == 1) {
+            double xi[TPT], yi[TPT], zi[TPT];
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            const MixedSrc me = lds[il[k]];
-            t[k].xh = me.xh;
-            t[k].yh = me.yh;
-            t[k].zh = me.zh;
-            t[k].xl = me.xl;
-            t[k].yl = me.yl;
-            t[k].zl = me.zl;
-            sx[k] = sy[k] = sz[k] = 0.0;
-        }
-        for (int j = jb; j < je; j += 8) {
-            float fx[TPT], fy[TPT], fz[TPT];
+            for (int k = 0; k < TPT; ++k) {
+                const BatchMixedSrc me = lds[il[k]];
+                xi[k] = me.x;
+                yi[k] = me.y;
+                zi[k] = me.z;
+            }
+            double sx[TPT], sy[TPT], sz[TPT];
 #pragma unroll
-            for (int k = 0; k < TPT; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+            for (int k = 0; k < TPT; ++k) sx[k] = sy[k] = sz[k] = 0.0;
+            // FP32 runs of 8 sources (the last one shorter) flushed to FP64
+            for (int j = jb; j < je; j += 8) {
+                float fx[TPT], fy[TPT], fz[TPT];
 #pragma unroll
-            for (int uu = 0; uu < 8; ++uu) {
-                const MixedSrc q = lds[j + uu];
+                for (int k = 0; k < TPT; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+                if (j + 8 <= je) {
+#pragma unroll
+                    for (int uu = 0; uu < 8; ++uu) {
+                        const BatchMixedSrc q = lds[j + uu];
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k) {
+                            float tx, ty, tz;
+                            batch_pair_f32<FQ>(q, xi[k], yi[k], zi[k], tx, ty, tz);
+                            fx[k] += tx;
+                            fy[k] += ty;
+                            fz[k] += tz;
+                        }
+                    }
+                } else {
+                    for (int jj = j; jj < je; ++jj) {
+                        const BatchMixedSrc q = lds[jj];
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k) {
+                            float tx, ty, tz;
+                            batch_pair_f32<FQ>(q, xi[k], yi[k], zi[k], tx, ty, tz);
+                            fx[k] += tx;
+                            fy[k] += ty;
+                            fz[k] += tz;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < TPT; ++k) {
-                    if constexpr (FQ)
-                        pair_f32_unit(q, t[k], fx[k], fy[k], fz[k]);
-                    else
-                        pair_f32(q, t[k], fx[k], fy[k], fz[k]);
+                    sx[k] += (double)fx[k];
+                    sy[k] += (double)fy[k];
+                    sz[k] += (double)fz[k];
                 }
             }
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
-                sx[k] += (double)fx[k];
-                sy[k] += (double)fy[k];
-                sz[k] += (double)fz[k];
+                Sx[k] = sx[k] * cs;
+                Sy[k] = sy[k] * cs;
+                Sz[k] = sz[k] * cs;
             }
-        }
-        // pair_f32_unit leaves out the -q_j factor
-        const double cs = FQ ? -uq * kMixedFieldScale : kMixedFieldScale;
-#pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            Sx[k] = sx[k] * cs;
-            Sy[k] = sy[k] * cs;
-            Sz[k] = sz[k] * cs;
-        }
-    } else {
-        FF t[TPT];
-        float sx[TPT], sy[TPT], sz[TPT], cx[TPT], cy[TPT], cz[TPT];
-#pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            const MixedSrc me = lds[il[k]];
-            t[k].xh = me.xh;
-            t[k].yh = me.yh;
-            t[k].zh = me.zh;
-            t[k].xl = me.xl;
-            t[k].yl = me.yl;
-            t[k].zl = me.zl;
-            sx[k] = sy[k] = sz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
-        }
-        for (int j = jb; j < je; ++j) {
-            const MixedSrc q = lds[j];
+        } else {
+            FF t[TPT];
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
-                float tx, ty, tz;
-                pair_f32_terms<FQ>(q, t[k], tx, ty, tz);
-                kahan_add(tx, sx[k], cx[k]);
-                kahan_add(ty, sy[k], cy[k]);
-                kahan_add(tz, sz[k], cz[k]);
+                const MixedSrc me = lds[il[k]];
+                t[k].xh = me.xh;
+                t[k].yh = me.yh;
+                t[k].zh = me.zh;
+                t[k].xl = me.xl;
+                t[k].yl = me.yl;
+                t[k].zl = me.zl;
             }
-        }
-        const double cs = FQ ? -uq * kMixedFieldScale : kMixedFieldScale;
+            float sx[TPT], sy[TPT], sz[TPT], cx[TPT], cy[TPT], cz[TPT];
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            Sx[k] = ((double)sx[k] - (double)cx[k]) * cs;
-            Sy[k] = ((double)sy[k] - (double)cy[k]) * cs;
-            Sz[k] = ((double)sz[k] - (double)cz[k]) * cs;
+            for (int k = 0; k < TPT; ++k) sx[k] = sy[k] = sz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
+            // sources four at a time, then the last one to three
+            const int j4 = jb + ((je - jb) & ~3);
+            for (int j = jb; j < j4; j += 4) {
+#pragma unroll
+                for (int uu = 0; uu < 4; ++uu) {
+                    const MixedSrc q = lds[j + uu];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        float tx, ty, tz;
+                        pair_f32_terms<FQ>(q, t[k], tx, ty, tz);
+                        kahan_add(tx, sx[k], cx[k]);
+                        kahan_add(ty, sy[k], cy[k]);
+                        kahan_add(tz, sz[k], cz[k]);
+                    }
+                }
+            }
+            for (int j = j4; j < je; ++j) {
+                const MixedSrc q = lds[j];
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    float tx, ty, tz;
+                    pair_f32_terms<FQ>(q, t[k], tx, ty, tz);
+                    kahan_add(tx, sx[k], cx[k]);
+                    kahan_add(ty, sy[k], cy[k]);
+                    kahan_add(tz, sz[k], cz[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                Sx[k] = ((double)sx[k] - (double)cx[k]) * cs;
+                Sy[k] = ((double)sy[k] - (double)cy[k]) * cs;
+                Sz[k] = ((double)sz[k] - (double)cz[k]) * cs;
+            }
         }
     }
 }
@@ -1524,14 +1614,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  double* __restrict__ vavg, int64_t n_pad,
                                                  int nsteps, int accel_only, double uq) {
     constexpr int KMAX = kMaxTrap / BLOCK;  // ions per owner thread at most
-    // uq != 0: every ion carries the charge uq (units of e); the FP64 pair sums
-    // then run over r^-3 d alone and are scaled by the charge once.  (The FP32
-    // loops without the charge multiply measured slower, 34.1 against 32.1 us
-    // per step of the 512-trap batch, so they keep it.)
-    const bool fq = PREC == 0 && uq != 0.0;
+    // pair work of larger traps: TPT targets per thread read each source once
+    // (at most 2 with 1024 threads, whose 128-VGPR budget 4 targets overflow)
+    constexpr int TMAX = BLOCK >= 1024 ? 2 : 4;
+    // uq != 0: every ion carries the charge uq (units of e); the pair sums then
+    // run over r^-3 d alone and are scaled by the charge once.
+    const bool fq = uq != 0.0 && batch_fq_on(PREC);
     using S = typename BatchSrc<PREC>::T;
     __shared__ S lds[kMaxTrap];
-    __shared__ double red[3][BLOCK];
+    // partial sums of every (component, target k, thread): one barrier per step
+    __shared__ double red[3 * TMAX * BLOCK];
 
     const int tr = order[blockIdx.x];
     const int64_t o = offsets[tr];
@@ -1554,9 +1646,6 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const int je = min(jb + jlen, send);
     const TrapDev T = traps[tr];
     const int64_t k0 = *counter;
-    // pair work of larger traps: TPT targets per thread read each source once
-    // (at most 2 with 1024 threads, whose 128-VGPR budget 4 targets overflow)
-    constexpr int TMAX = BLOCK >= 1024 ? 2 : 4;
     // a lone trap (the small-trap path) is latency-bound: one target per thread
     // below kBatchTpt4 ions saves the extra reduction rounds
     const int tpt2_from = gridDim.x == 1 ? kBatchTpt4 : kBatchTpt2;
@@ -1599,17 +1688,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             sp[k] = 0;
         }
     }
-    // zero-charge padding of the source stream; with a common charge the sums
-    // weigh every source alike, so padding sits 1e6 m away, where its term is
-    // ~1e-20 of a neighbour's at 1e-4 m (below FP64 rounding)
-    const double pad = fq ? kFarPad : 0.0;
-    for (int il = m + tid; il < m16; il += BLOCK) {
-        if constexpr (PREC == 0) {
-            lds[il] = make_double4(pad, pad, pad, 0.0);
-        } else {
-            lds[il] = make_src(pad, pad, pad, 0.0);
-        }
-    }
+    // the source ranges stop at m: no padding source is ever read
+    const int jr0 = min(jb, m), jr1 = min(je, m);
+    const int wjr0 = min(wjb, m), wjr1 = min(wje, m);
 
     const int total = accel_only ? 1 : nsteps;
     const int64_t step0 = cool->step_base + k0 + 1;  // run-wide number of the first step
@@ -1625,6 +1706,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                     z[k], u[k], v[k], w[k], a0[k], a1[k], a2[k]);
                 if constexpr (PREC == 0) {
                     lds[il] = make_double4(x[k], y[k], z[k], 1.5 * q_e[k]);
+                } else if constexpr (PREC == 1) {
+                    lds[il] = make_batch_src(x[k], y[k], z[k], q_e[k]);
                 } else {
                     lds[il] = make_src(x[k], y[k], z[k], q_e[k]);
                 }
@@ -1641,42 +1724,41 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                 if constexpr (TMAX >= 4) {
                     if (TPT == 4) {
                         if (fq)
-                            batch_pairs_multi<PREC, 4, true>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                            batch_pairs_multi<PREC, 4, true>(lds, m, wslot, WS, wjr0, wjr1, uq, Wx, Wy, Wz);
                         else
-                            batch_pairs_multi<PREC, 4, false>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                            batch_pairs_multi<PREC, 4, false>(lds, m, wslot, WS, wjr0, wjr1, uq, Wx, Wy, Wz);
                     } else if (fq) {
-                        batch_pairs_multi<PREC, 2, true>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                        batch_pairs_multi<PREC, 2, true>(lds, m, wslot, WS, wjr0, wjr1, uq, Wx, Wy, Wz);
                     } else {
-                        batch_pairs_multi<PREC, 2, false>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                        batch_pairs_multi<PREC, 2, false>(lds, m, wslot, WS, wjr0, wjr1, uq, Wx, Wy, Wz);
                     }
                 } else if (fq) {
-                    batch_pairs_multi<PREC, 2, true>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                    batch_pairs_multi<PREC, 2, true>(lds, m, wslot, WS, wjr0, wjr1, uq, Wx, Wy, Wz);
                 } else {
-                    batch_pairs_multi<PREC, 2, false>(lds, m, wslot, WS, wjb, wje, uq, Wx, Wy, Wz);
+                    batch_pairs_multi<PREC, 2, false>(lds, m, wslot, WS, wjr0, wjr1, uq, Wx, Wy, Wz);
                 }
             }
+            if (wactive) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (k >= TPT) break;
-                if (wactive) {
-                    red[0][tid] = Wx[k];
-                    red[1][tid] = Wy[k];
-                    red[2][tid] = Wz[k];
+                for (int k = 0; k < TMAX; ++k) {
+                    if (k >= TPT) break;
+                    red[(0 * TMAX + k) * BLOCK + tid] = Wx[k];
+                    red[(1 * TMAX + k) * BLOCK + tid] = Wy[k];
+                    red[(2 * TMAX + k) * BLOCK + tid] = Wz[k];
                 }
-                __syncthreads();
+            }
+            __syncthreads();
 #pragma unroll
-                for (int kk = 0; kk < KMAX; ++kk) {
-                    const int il = slot + IS * kk;
-                    if (owner && il < m && il / WS == k) {
-                        const int r = il - WS * k;
-                        for (int pp = 0; pp < JPW; ++pp) {
-                            Sx[kk] += red[0][pp * WS + r];
-                            Sy[kk] += red[1][pp * WS + r];
-                            Sz[kk] += red[2][pp * WS + r];
-                        }
+            for (int kk = 0; kk < KMAX; ++kk) {
+                const int il = slot + IS * kk;
+                if (owner && il < m) {
+                    const int k = il / WS, r = il - WS * k;
+                    for (int pp = 0; pp < JPW; ++pp) {
+                        Sx[kk] += red[(0 * TMAX + k) * BLOCK + pp * WS + r];
+                        Sy[kk] += red[(1 * TMAX + k) * BLOCK + pp * WS + r];
+                        Sz[kk] += red[(2 * TMAX + k) * BLOCK + pp * WS + r];
                     }
                 }
-                __syncthreads();
             }
         }
         // pair field of this thread's targets over its source part (one target per thread)
@@ -1686,9 +1768,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             if (TPT > 1 || !active || il >= m) continue;
             double W1x[4], W1y[4], W1z[4];
             if (fq)
-                batch_pairs_multi<PREC, 1, true>(lds, m, il, IS, jb, je, uq, W1x, W1y, W1z);
+                batch_pairs_multi<PREC, 1, true>(lds, m, il, IS, jr0, jr1, uq, W1x, W1y, W1z);
             else
-                batch_pairs_multi<PREC, 1, false>(lds, m, il, IS, jb, je, uq, W1x, W1y, W1z);
+                batch_pairs_multi<PREC, 1, false>(lds, m, il, IS, jr0, jr1, uq, W1x, W1y, W1z);
             Sx[k] = W1x[0];
             Sy[k] = W1y[0];
             Sz[k] = W1z[0];
@@ -1697,20 +1779,22 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
             // deterministic reduction over source parts: owners add parts in order
             // (only KMAX == 1 can have JP > 1, since JP > 1 needs m <= BLOCK / 2)
             if (active && jpart > 0) {
-                red[0][tid] = Sx[0];
-                red[1][tid] = Sy[0];
-                red[2][tid] = Sz[0];
+                red[0 * TMAX * BLOCK + tid] = Sx[0];
+                red[1 * TMAX * BLOCK + tid] = Sy[0];
+                red[2 * TMAX * BLOCK + tid] = Sz[0];
             }
             __syncthreads();
             if (owner) {
                 for (int p = 1; p < JP; ++p) {
-                    Sx[0] += red[0][slot + p * IS];
-                    Sy[0] += red[1][slot + p * IS];
-                    Sz[0] += red[2][slot + p * IS];
+                    Sx[0] += red[0 * TMAX * BLOCK + slot + p * IS];
+                    Sy[0] += red[1 * TMAX * BLOCK + slot + p * IS];
+                    Sz[0] += red[2 * TMAX * BLOCK + slot + p * IS];
                 }
             }
         }
-        __syncthreads();
+        // every thread is past the pair loops before the next step writes the
+        // source stream: the reductions above had a barrier, else one here
+        if (TPT == 1 && JP == 1) __syncthreads();
         const double t = T.t_start + (double)(k0 + step + (accel_only ? 0 : 1)) * T.dt;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
