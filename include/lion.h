@@ -361,6 +361,10 @@ typedef struct {
                              kernel with one trap; N <= 1024, no body exclusion or rigid
                              bodies, else the multi-workgroup kernels run).  Built-in: 2
                              for N <= LION_SMALL_TRAP_IONS, else 1                           */
+    int32_t batch_tpt;    /* batched kernel (and the one-workgroup path): targets per thread
+                             for traps of 128 ions or more: 1, 2 or 4 (at most 2 with 1024
+                             threads per trap).  Built-in: 2 (4 below 1024 threads) from 256
+                             ions, 2 from 128 in a batch; 1 below                            */
 } lion_kernel_config;
 
 /* Ion count up to which a single trap is stepped inside one workgroup by default. */

@@ -195,6 +195,7 @@ void default_shape(lion_sim* s) {
     // epilogue: 4 waves per 64 ions unless set (8 and 16 measured no faster)
     ls.update_waves = s->cfg.update_waves > 0 ? s->cfg.update_waves : 4;
     ls.uniform_q = s->uniform_q;
+    ls.batch_tpt = s->cfg.batch_tpt > 0 ? s->cfg.batch_tpt : 0;
     ls.small_path = s->cfg.small_trap > 0 ? (s->cfg.small_trap == 2 ? 1 : 0)
                                           : (n <= LION_SMALL_TRAP_IONS ? 1 : 0);
     // one-workgroup stepping of a single trap: 256 threads up to 32 ions, 512 up
@@ -1294,6 +1295,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->sym_variant, {1, 2, 3, 4, 5, 6, 7})) return fail(s, LION_ERR_ARG, "sym_variant must be 1..7");
     if (!in(c->update_waves, {4, 8, 16})) return fail(s, LION_ERR_ARG, "update_waves must be 4, 8 or 16");
     if (!in(c->small_trap, {1, 2})) return fail(s, LION_ERR_ARG, "small_trap must be 1 or 2");
+    if (!in(c->batch_tpt, {1, 2, 4})) return fail(s, LION_ERR_ARG, "batch_tpt must be 1, 2 or 4");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 131072");
     (void)hipSetDevice(s->device);
@@ -1310,6 +1312,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.sym_variant = c->sym_variant;
     s->cfg.update_waves = c->update_waves;
     s->cfg.small_trap = c->small_trap;
+    s->cfg.batch_tpt = c->batch_tpt;
     default_shape(s);
     return LION_OK;
 }
@@ -1327,6 +1330,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->sym_variant = s->ls.sym_variant + 1;
     c->update_waves = s->ls.update_waves;
     c->small_trap = s->ls.small_path ? 2 : 1;
+    c->batch_tpt = s->ls.batch_tpt;
     return LION_OK;
 }
 

@@ -192,6 +192,7 @@ struct LaunchShape {
     int sym_variant;  // pair-once kernel variant (0-based)
     int update_waves; // waves per 64 ions in the step epilogue (4, 8 or 16)
     int small_path;   // single trap stepped by the one-workgroup kernel (k_batch, one trap)
+    int batch_tpt;    // batched kernel: targets per thread for traps of >= 128 ions (0: by size)
     bool cool_on;     // a beam, bath or time average is on: the kernels built with them run
     double uniform_q;  // every ion's charge in units of e when all are equal, else 0
     int sym_masked;    // pair-once kernels with the per-pair body test (bodies share tiles)

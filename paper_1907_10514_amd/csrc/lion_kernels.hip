@@ -1612,7 +1612,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  const int64_t* __restrict__ counter,
                                                  double* __restrict__ vacc,
                                                  double* __restrict__ vavg, int64_t n_pad,
-                                                 int nsteps, int accel_only, double uq) {
+                                                 int nsteps, int accel_only, double uq,
+                                                 int tpt_req) {
     constexpr int KMAX = kMaxTrap / BLOCK;  // ions per owner thread at most
     // pair work of larger traps: TPT targets per thread read each source once
     // (at most 2 with 1024 threads, whose 128-VGPR budget 4 targets overflow)
@@ -1652,6 +1653,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     int TPT = m >= kBatchTpt4 ? TMAX : (m >= tpt2_from ? 2 : 1);
     if (TPT > 1)
         while (TPT < TMAX && TPT * BLOCK < m) TPT *= 2;
+    // a requested count (launch-shape tuning) for traps of kBatchTpt2 ions or more
+    if (tpt_req > 0 && m >= kBatchTpt2) TPT = min(tpt_req, TMAX);
     const int WS = ((m + 64 * TPT - 1) / (64 * TPT)) * 64;  // <= BLOCK
     const int JPW = BLOCK / WS;
     const int wslot = tid % WS, wpart = tid / WS;
@@ -2266,30 +2269,30 @@ hipError_t pair_mixed_dispatch_l(const DevState& s, const LaunchShape& ls, int64
 
 template <int PREC, int BLOCK, bool X>
 hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only, double uq,
-                        hipStream_t st) {
+                        int tpt, hipStream_t st) {
     k_batch<PREC, BLOCK, X><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                        s.az, s.qm, s.qe, s.mass, s.species,
                                                        s.traps, s.cool, s.offsets, s.order,
                                                        s.counter, s.vacc, s.vavg, s.n_pad,
-                                                       nsteps, accel_only, uq);
+                                                       nsteps, accel_only, uq, tpt);
     return hipGetLastError();
 }
 
 template <int PREC, bool X>
 hipError_t batch_dispatch_x(const DevState& s, int n_traps, int block, int nsteps,
-                            int accel_only, double uq, hipStream_t st) {
+                            int accel_only, double uq, int tpt, hipStream_t st) {
     switch (block) {
-        case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, uq, st);
-        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, uq, st);
-        default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, uq, st);
+        case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
+        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
+        default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
     }
 }
 
 template <int PREC>
 hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps, int accel_only,
-                          bool cool_on, double uq, hipStream_t st) {
-    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, block, nsteps, accel_only, uq, st)
-                   : batch_dispatch_x<PREC, false>(s, n_traps, block, nsteps, accel_only, uq, st);
+                          bool cool_on, double uq, int tpt, hipStream_t st) {
+    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, block, nsteps, accel_only, uq, tpt, st)
+                   : batch_dispatch_x<PREC, false>(s, n_traps, block, nsteps, accel_only, uq, tpt, st);
 }
 
 }  // namespace
@@ -2516,9 +2519,9 @@ hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_t
                         const LaunchShape& ls, int nsteps, int, hipStream_t st) {
     (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, st);
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
     }
 }
 
@@ -2526,9 +2529,9 @@ hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int
                               const LaunchShape& ls, hipStream_t st) {
     (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, st);
+        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
+        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
+        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
     }
 }
 

@@ -509,24 +509,26 @@ def _small_batch(n_traps=24, seed=13, n_max=300):
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 @pytest.mark.parametrize("charges", ["common", "mixed"])
 def test_batch_accel_parity(torch_gpu, oracle_mod, prec, charges):
-    """Batched field against the oracle for every workgroup size, with one
-    common charge (sums scaled by it once, padding placed far away) and with
-    per-ion charges."""
+    """Batched field against the oracle for every launch shape the tuner may
+    pick (workgroup size x targets per thread), with one common charge (sums
+    scaled by it once) and with per-ion charges."""
     w = _small_batch()
     if charges == "mixed":
         w.charge = np.random.default_rng(7).choice([1, 2, -1], w.n) * li.E_CHARGE
     traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
     r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
                                np.zeros(w.n_traps))
-    for block in (256, 512, 1024):
-        sim = _sim(w, prec, oracle_mod, batch_block=block)
+    from paper_1907_10514_amd import tune
+
+    for cfg in tune.batch_candidates():  # every shape the tuner may pick
+        sim = _sim(w, prec, oracle_mod, **cfg)
         a = sim.compute_accel()
         for k in range(w.n_traps):
             o, e = w.offsets[k], w.offsets[k + 1]
             sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e],
                                         traps[k], 0.0)
             err = _m1([c[o:e] for c in a], [c[o:e] for c in r], sc)
-            assert err <= TOL[prec], (block, k, err)
+            assert err <= TOL[prec], (cfg, k, err)
         sim.close()
 
 

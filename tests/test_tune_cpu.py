@@ -22,6 +22,7 @@ ALLOWED = {
     "sym_variant": set(range(1, 8)),
     "update_waves": {4, 8, 16},
     "small_trap": {1, 2},
+    "batch_tpt": {1, 2, 4},
 }
 
 
@@ -84,7 +85,30 @@ def test_shipped_cache_is_valid():
             assert v in ALLOWED[k], (key, k, v)
         meas = ent["measured"]
         assert all(ent["config"].get(k) == v for k, v in meas["config"].items()), key
+        # every stored shape passed its accuracy gate against the FP64 path
+        assert meas["ok"] and meas["m1_vs_fp64"] <= 0.5 * tune.BAR[p], key
         if shape == "single":
-            assert meas["ok"] and meas["m1_vs_fp64"] <= tune.BAR[p], key
             if ent["config"].get("symmetric") == 2:
                 assert (int(nb[1:]) + 255) // 256 <= 512, key
+
+
+def test_batch_candidates():
+    """Workgroup sizes x targets per thread, with no 4 targets at 1024 threads
+    (their register budget); every candidate a valid configuration."""
+    cands = list(tune.batch_candidates())
+    assert len(cands) == 8
+    assert {(c["batch_block"], c["batch_tpt"]) for c in cands} == \
+        {(b, t) for b in (256, 512, 1024) for t in (1, 2, 4)} - {(1024, 4)}
+    for c in cands:
+        for k, v in c.items():
+            assert v in ALLOWED[k], (k, v)
+
+
+def test_batch_scale_is_per_trap():
+    """The batch accuracy gate's scale counts sources of the ion's own trap only."""
+    import numpy as np
+
+    x = np.array([0.0, 1.0, 10.0, 11.0])
+    z0 = np.zeros(4)
+    s = tune._batch_scale([2, 2], x, z0, z0)
+    assert np.allclose(s, [1.0, 1.0, 1.0, 1.0])
