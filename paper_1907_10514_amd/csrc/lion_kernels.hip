@@ -1099,7 +1099,7 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
 // One tile pair (a, b) of the FP64 pair-once kernel.  With FQ every ion in
 // both tiles carries the charge uq: the sums run over c d alone and are scaled
 // by the charge once, at the end.
-template <int UNR, bool PF, bool FQ, bool MK = false>
+template <int UNR, bool PF, bool FQ, bool MK, bool DG>
 __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
                                              const double* __restrict__ qe, int64_t n,
                                              int64_t n_pad, double* __restrict__ part, int a,
@@ -1107,7 +1107,7 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
                                              const int32_t* __restrict__ code = nullptr) {
     constexpr int CH = 4;
     constexpr int S = CH * 3 + 1;
-    const bool diag = (a == b);
+    constexpr bool diag = DG;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t base = (int64_t)a * kSymTile + lane;
@@ -1152,20 +1152,20 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
                 sx[k] = fma(wi, dx, sx[k]);
                 sy[k] = fma(wi, dy, sy[k]);
                 sz[k] = fma(wi, dz, sz[k]);
-                if (!diag) {
+                if constexpr (!diag) {
                     const double wj = FQ ? c : c * nqi[k];  // -1.5 q_i c = q_i r^-3
                     tx = fma(wj, dx, tx);
                     ty = fma(wj, dy, ty);
                     tz = fma(wj, dz, tz);
                 }
             }
-            if (!diag) {
+            if constexpr (!diag) {
                 jb[lane * S + 3 * uu + 0] = tx;
                 jb[lane * S + 3 * uu + 1] = ty;
                 jb[lane * S + 3 * uu + 2] = tz;
             }
         }
-        if (!diag) {
+        if constexpr (!diag) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1192,6 +1192,20 @@ __device__ __forceinline__ void f64_sym_body(const double4* __restrict__ src,
     reduce_store_in<4>(sx, sy, sz, part, b, n, n_pad, base, smem);
 }
 
+// A diagonal tile pair (a == b) adds no reactions: it gets a loop of its own,
+// so the loop of the other tile pairs carries no branch on it.
+template <int UNR, bool PF, bool FQ, bool MK>
+__device__ __forceinline__ void f64_sym_unit(const double4* __restrict__ src,
+                                             const double* __restrict__ qe, int64_t n,
+                                             int64_t n_pad, double* __restrict__ part, int a,
+                                             int b, double uq, double* smem,
+                                             const int32_t* __restrict__ code = nullptr) {
+    if (a == b)
+        f64_sym_body<UNR, PF, FQ, MK, true>(src, qe, n, n_pad, part, a, b, uq, smem, code);
+    else
+        f64_sym_body<UNR, PF, FQ, MK, false>(src, qe, n, n_pad, part, a, b, uq, smem, code);
+}
+
 // WPE: the occupancy the register allocation aims at; UNR: sources unrolled.
 // uq != 0: every ion carries the charge uq (units of e) and tiles below
 // full_tiles hold no padding; those tile pairs take the charge-free loop.
@@ -1209,11 +1223,11 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
     if (sym_unit_excluded(tile_body, a, b))
         sym_unit_zero(part, n, n_pad, a, b);
     else if (MK && bt.may_share(a, b))
-        f64_sym_body<UNR, PF, false, true>(src, qe, n, n_pad, part, a, b, uq, smem, bt.code);
+        f64_sym_unit<UNR, PF, false, true>(src, qe, n, n_pad, part, a, b, uq, smem, bt.code);
     else if (uq != 0.0 && b < full_tiles)
-        f64_sym_body<UNR, PF, true>(src, qe, n, n_pad, part, a, b, uq, smem);
+        f64_sym_unit<UNR, PF, true, false>(src, qe, n, n_pad, part, a, b, uq, smem);
     else
-        f64_sym_body<UNR, PF, false>(src, qe, n, n_pad, part, a, b, uq, smem);
+        f64_sym_unit<UNR, PF, false, false>(src, qe, n, n_pad, part, a, b, uq, smem);
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
