@@ -351,9 +351,12 @@ def host_cpu():
 def profile_pass(torch, w, precisions, batch=False):
     """Short run for counter collection: each benchmarked pair kernel (tuned
     launch shape) 5 times plus 3 steps (with batch: instead, two launches of the
-    batched kernel over the 512-trap batch, 100 in-kernel steps each), then a
+    batched kernel over the 512-trap batch, 100 in-kernel steps each, then two
+    over its largest trap alone, a one-workgroup launch), then a
     device-to-device copy of 256 MiB whose FETCH_SIZE / WRITE_SIZE readings
     calibrate the counters."""
+    import numpy as np
+
     import lion_inputs as li
     from paper_1907_10514_amd import runner
 
@@ -362,6 +365,15 @@ def profile_pass(torch, w, precisions, batch=False):
             wb = li.batch512(nsteps=0)
             sim = runner.simulation_for(wb, precision=p)
             sim.time_batch_kernel(2, 100, float(wb.traps[0].dt))
+            torch.cuda.synchronize()
+            sim.close()
+            k = int(np.argmax(np.diff(wb.offsets)))
+            o, e = int(wb.offsets[k]), int(wb.offsets[k + 1])
+            one = li.Workload(f"trap{k}", wb.mass[o:e], wb.charge[o:e], wb.x[o:e], wb.y[o:e],
+                              wb.z[o:e], wb.vx[o:e], wb.vy[o:e], wb.vz[o:e], [wb.traps[k]],
+                              np.array([0, e - o], dtype=np.int64), 0, wb.precision)
+            sim = runner.simulation_for(one, precision=p, batched=True)
+            sim.time_batch_kernel(2, 100, float(wb.traps[k].dt))
         else:
             sim = runner.simulation_for(w, precision=p)
             sim.time_pair_kernel(5)
