@@ -351,6 +351,8 @@ int chunk_graph(lion_sim* s, int64_t L, hipGraphExec_t* out) {
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
         it = s->graphs.emplace(key, ex).first;
+        // resident on the device now rather than at the first launch
+        LION_HIP(s, hipGraphUpload(ex, s->stream));
     }
     *out = it->second;
     return LION_OK;
