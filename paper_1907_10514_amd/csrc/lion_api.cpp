@@ -61,6 +61,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxTrap = 1024;
+// traps of at most this many ions step on one wave (64-thread workgroups): at 8
+// ions 0.95 against 1.24 us per step (256 threads), at 16 ions 1.42 against 1.26
+constexpr int64_t kOneWaveIons = 12;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -202,10 +205,11 @@ void default_shape(lion_sim* s) {
     // to 64, then 1024 (measured per size; e.g. 64 ions: 1.94 us per step at 512
     // against 2.13 at 256 and 2.27 at 1024)
     if (!s->batched && ls.small_path && s->cfg.batch_block <= 0)
-        ls.batch_block = n <= 32 ? 256 : (n <= 64 ? 512 : 1024);
+        ls.batch_block = n <= kOneWaveIons ? 64 : (n <= 32 ? 256 : (n <= 64 ? 512 : 1024));
     // batches whose largest trap holds 256 ions or more: 1024 threads per trap
     // (the 512-trap batch of 2-512 ions: 4.0 against 6.8 ms per 100 steps at 256)
     if (s->batched && s->cfg.batch_block <= 0 && s->max_trap >= 256) ls.batch_block = 1024;
+    if (s->batched && s->cfg.batch_block <= 0 && s->max_trap <= kOneWaveIons) ls.batch_block = 64;
 }
 
 void clear_graphs(lion_sim* s) {
@@ -1289,8 +1293,10 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (c->j_split > 64) return fail(s, LION_ERR_ARG, "j_split must be <= 64");
     if (c->chunk_steps > 1000) return fail(s, LION_ERR_ARG, "chunk_steps must be <= 1000");
     if (!in(c->flush_len, {4, 8, 16})) return fail(s, LION_ERR_ARG, "flush_len must be 4, 8 or 16");
-    if (!in(c->batch_block, {256, 512, 1024}))
-        return fail(s, LION_ERR_ARG, "batch_block must be 256, 512 or 1024");
+    if (!in(c->batch_block, {64, 256, 512, 1024}))
+        return fail(s, LION_ERR_ARG, "batch_block must be 64, 256, 512 or 1024");
+    if (c->batch_block == 64 && (s->batched ? s->max_trap : s->n) > 64)
+        return fail(s, LION_ERR_ARG, "batch_block 64 takes traps of at most 64 ions");
     if (!in(c->use_graph, {1, 2})) return fail(s, LION_ERR_ARG, "use_graph must be 1 or 2");
     if (!in(c->lds_sources, {1, 2})) return fail(s, LION_ERR_ARG, "lds_sources must be 1 or 2");
     if (!in(c->symmetric, {1, 2})) return fail(s, LION_ERR_ARG, "symmetric must be 1 or 2");

@@ -196,9 +196,10 @@ __device__ __forceinline__ MixedSrc make_src(double x, double y, double z, doubl
 
 // --------------------------------------------------------- trap field
 
-__device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm, double x,
-                                           double y, double z, double Sx, double Sy, double Sz,
-                                           double& ax, double& ay, double& az) {
+// c = cos(Omega t) of the step's time (unused by the pseudopotential trap).
+__device__ __forceinline__ void trap_accel_c(const TrapDev& T, double c, double qm, double x,
+                                             double y, double z, double Sx, double Sy,
+                                             double Sz, double& ax, double& ay, double& az) {
 #pragma clang fp contract(off)
     if (T.ps != 0.0) {
         // pseudopotential trap: static radial field -(Q/M) A_rf^2/(2 Omega^2) (x, y, 0)
@@ -211,13 +212,18 @@ __device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm
         az = qm * (kKeE * Sz + ez);
         return;
     }
-    const double c = cos(T.omega * t);
     const double ex = T.a_rf * c * x + T.a_dc * x;
     const double ey = -T.a_rf * c * y + T.a_dc * y;
     const double ez = -2.0 * T.a_dc * z;
     ax = qm * (kKeE * Sx + ex);
     ay = qm * (kKeE * Sy + ey);
     az = qm * (kKeE * Sz + ez);
+}
+
+__device__ __forceinline__ void trap_accel(const TrapDev& T, double t, double qm, double x,
+                                           double y, double z, double Sx, double Sy, double Sz,
+                                           double& ax, double& ay, double& az) {
+    trap_accel_c(T, T.ps != 0.0 ? 0.0 : cos(T.omega * t), qm, x, y, z, Sx, Sy, Sz, ax, ay, az);
 }
 
 // ------------------------------------------------------------ cooling
@@ -1628,7 +1634,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
                                                  double* __restrict__ vavg, int64_t n_pad,
                                                  int nsteps, int accel_only, double uq,
                                                  int tpt_req) {
-    constexpr int KMAX = kMaxTrap / BLOCK;  // ions per owner thread at most
+    // ions per owner thread at most (a 64-thread block takes traps of <= 64 ions only)
+    constexpr int KMAX = BLOCK >= 256 ? kMaxTrap / BLOCK : 1;
     // pair work of larger traps: TPT targets per thread read each source once
     // (at most 2 with 1024 threads, whose 128-VGPR budget 4 targets overflow)
     constexpr int TMAX = BLOCK >= 1024 ? 2 : 4;
@@ -1639,6 +1646,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     __shared__ S lds[kMaxTrap];
     // partial sums of every (component, target k, thread): one barrier per step
     __shared__ double red[3 * TMAX * BLOCK];
+    // cos(Omega t) of kRf consecutive steps, computed one step per thread ahead of
+    // them (off the steps' dependent chain); two buffers, so that a refill never
+    // meets a read of the steps before
+    constexpr int kRf = 64;
+    __shared__ double rf[2][kRf];
 
     const int tr = order[blockIdx.x];
     const int64_t o = offsets[tr];
@@ -1713,6 +1725,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const int64_t step0 = cool->step_base + k0 + 1;  // run-wide number of the first step
     const CoolRef cr = cool_switches<X>(cool);
     for (int step = 0; step < total; ++step) {
+        if (step % kRf == 0 && T.ps == 0.0 && tid < kRf && step + tid < total) {
+            // read after the barrier below
+            const int sq = step + tid;
+            const double tq = T.t_start + (double)(k0 + sq + (accel_only ? 0 : 1)) * T.dt;
+            rf[(step / kRf) & 1][tid] = cos(T.omega * tq);
+        }
         // first half of the step; positions into the LDS source stream
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
@@ -1812,13 +1830,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
         // every thread is past the pair loops before the next step writes the
         // source stream: the reductions above had a barrier, else one here
         if (TPT == 1 && JP == 1) __syncthreads();
-        const double t = T.t_start + (double)(k0 + step + (accel_only ? 0 : 1)) * T.dt;
+        const double crf = T.ps == 0.0 ? rf[(step / kRf) & 1][step % kRf] : 0.0;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const int il = slot + IS * k;
             if (owner && il < m) {
-                trap_accel(T, t, q_m[k], x[k], y[k], z[k], Sx[k], Sy[k], Sz[k], a0[k], a1[k],
-                           a2[k]);
+                trap_accel_c(T, crf, q_m[k], x[k], y[k], z[k], Sx[k], Sy[k], Sz[k], a0[k],
+                             a1[k], a2[k]);
                 if (!accel_only) {
                     end_kick(T, cr, o + il, sp[k], m_i[k], step0 + step, u[k], v[k], w[k],
                              a0[k], a1[k], a2[k]);
@@ -2296,6 +2314,7 @@ template <int PREC, bool X>
 hipError_t batch_dispatch_x(const DevState& s, int n_traps, int block, int nsteps,
                             int accel_only, double uq, int tpt, hipStream_t st) {
     switch (block) {
+        case 64: return batch_launch<PREC, 64, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
         case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
         case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
         default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);

@@ -575,6 +575,92 @@ def test_batch_trajectory_matches_oracle(torch_gpu, oracle_mod):
     sim.close()
 
 
+def _tiny_trap_batch(sizes, seed):
+    w = li.batch512(n_traps=len(sizes), n_min=2, n_max=12, seed=seed, nsteps=0)
+    rng = np.random.default_rng(seed + 1)
+    w.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(w.offsets[-1])
+    w.mass = rng.choice([li.REF_MASS, 17 * li.AMU], n)
+    w.charge = rng.choice([1, 1, 2], n) * li.E_CHARGE
+    w.x, w.y, w.z = rng.normal(0, 15e-6, (3, n))
+    w.vx, w.vy, w.vz = rng.normal(0, 1.0, (3, n))
+    return w
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+def test_one_wave_traps_match_oracle(torch_gpu, oracle_mod, prec):
+    """Traps of at most 12 ions step on one wave (64-thread workgroups, the
+    built-in shape).  Forces of every trap against the oracle before and after
+    a 130-step run (three launches of 50 steps, so the per-launch table of RF
+    phases is refilled within a launch and across launches); in FP64 the run
+    itself against the oracle's batched steps."""
+    sizes = np.array([1, 2, 3, 5, 7, 8, 9, 11, 12, 12, 4, 6])
+    w = _tiny_trap_batch(sizes, seed=61)
+    traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
+    sim = _sim(w, prec, oracle_mod, chunk_steps=50)
+    assert sim.config()["batch_block"] == 64
+    r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
+                               np.zeros(w.n_traps))
+    a = sim.compute_accel()
+    for k in range(w.n_traps):
+        o, e = w.offsets[k], w.offsets[k + 1]
+        sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e],
+                                    traps[k], 0.0)
+        assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
+    g = np.array([s.gamma for s in w.traps])
+    dts = np.array([s.dt for s in w.traps]) * np.linspace(0.8, 1.2, w.n_traps)
+    sim.step(130, dts)
+    st, _ = sim.get_state()
+    t = 130 * dts
+    r = oracle_mod.accel_batch(w.offsets, st["x"], st["y"], st["z"], w.charge, w.mass, traps, t)
+    a = sim.compute_accel()
+    for k in range(w.n_traps):
+        o, e = w.offsets[k], w.offsets[k + 1]
+        sc = oracle_mod.accel_scale(st["x"][o:e], st["y"][o:e], st["z"][o:e], w.charge[o:e],
+                                    w.mass[o:e], traps[k], t[k])
+        assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
+    if prec == "fp64":
+        ref = oracle_mod.step_batch(w.offsets, w.state(), w.charge, w.mass, traps, g,
+                                    np.zeros(w.n_traps), dts, 130)
+        for k in range(w.n_traps):
+            o, e = w.offsets[k], w.offsets[k + 1]
+            disp = np.max(np.abs(ref["x"][o:e] - w.x[o:e])) + 1e-12
+            for c in ("x", "y", "z"):
+                assert np.max(np.abs(st[c][o:e] - ref[c][o:e])) < 1e-10 * disp, (k, c)
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [13, 40, 64])
+def test_one_wave_shape_up_to_64_ions(torch_gpu, oracle_mod, n):
+    """The 64-thread shape, asked for explicitly, on lone traps above the
+    built-in threshold: forces and a 60-step FP64 run against the oracle."""
+    w = li.random_cloud(n, seed=300 + n, sigma=20e-6, light_fraction=0.2)
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
+    sim = _sim(w, "fp64", oracle_mod, small_trap=2, batch_block=64)
+    assert sim.config()["batch_block"] == 64
+    r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    assert _m1(sim.compute_accel(), r, sc) <= TOL["fp64"]
+    ref = oracle_mod.step(w.state(), w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, 60)
+    sim.step(60, spec.dt)
+    st, _ = sim.get_state()
+    disp = np.max(np.abs(ref["x"] - w.x)) + 1e-12
+    for c in ("x", "y", "z"):
+        assert np.max(np.abs(st[c] - ref[c])) < 1e-10 * disp, c
+    sim.close()
+
+
+def test_one_wave_shape_refused_above_64_ions(torch_gpu, oracle_mod):
+    from paper_1907_10514_amd.lion import LionError
+
+    w = li.random_cloud(65, seed=7, sigma=20e-6)
+    sim = _sim(w, "fp64", oracle_mod)
+    with pytest.raises(LionError, match="at most 64"):
+        sim.set_config(batch_block=64)
+    sim.close()
+
+
 def _large_trap_batch():
     """Traps of the maximum 1024 ions down to 2, with a ragged one of 257 and
     mixed charges."""
