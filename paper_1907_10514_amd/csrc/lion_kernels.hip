@@ -1643,7 +1643,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     // run over r^-3 d alone and are scaled by the charge once.
     const bool fq = uq != 0.0 && batch_fq_on(PREC);
     using S = typename BatchSrc<PREC>::T;
-    __shared__ S lds[kMaxTrap];
+    // the trap's source stream, sized at launch for the batch's largest trap
+    static_assert(sizeof(S) == sizeof(double4), "source records of 32 bytes");
+    extern __shared__ double4 lds_stream[];
+    S* lds = reinterpret_cast<S*>(lds_stream);
     // partial sums of every (component, target k, thread): one barrier per step
     __shared__ double red[3 * TMAX * BLOCK];
     // cos(Omega t) of kRf consecutive steps, computed one step per thread ahead of
@@ -2300,9 +2303,10 @@ hipError_t pair_mixed_dispatch_l(const DevState& s, const LaunchShape& ls, int64
 }
 
 template <int PREC, int BLOCK, bool X>
-hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_only, double uq,
-                        int tpt, hipStream_t st) {
-    k_batch<PREC, BLOCK, X><<<n_traps, BLOCK, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay,
+hipError_t batch_launch(const DevState& s, int n_traps, int max_trap, int nsteps,
+                        int accel_only, double uq, int tpt, hipStream_t st) {
+    const size_t stream_bytes = (size_t)max_trap * sizeof(double4);
+    k_batch<PREC, BLOCK, X><<<n_traps, BLOCK, stream_bytes, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay,
                                                        s.az, s.qm, s.qe, s.mass, s.species,
                                                        s.traps, s.cool, s.offsets, s.order,
                                                        s.counter, s.vacc, s.vavg, s.n_pad,
@@ -2311,21 +2315,21 @@ hipError_t batch_launch(const DevState& s, int n_traps, int nsteps, int accel_on
 }
 
 template <int PREC, bool X>
-hipError_t batch_dispatch_x(const DevState& s, int n_traps, int block, int nsteps,
+hipError_t batch_dispatch_x(const DevState& s, int n_traps, int max_trap, int block, int nsteps,
                             int accel_only, double uq, int tpt, hipStream_t st) {
     switch (block) {
-        case 64: return batch_launch<PREC, 64, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
-        case 512: return batch_launch<PREC, 512, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
-        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
-        default: return batch_launch<PREC, 256, X>(s, n_traps, nsteps, accel_only, uq, tpt, st);
+        case 64: return batch_launch<PREC, 64, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
+        case 512: return batch_launch<PREC, 512, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
+        case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
+        default: return batch_launch<PREC, 256, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
     }
 }
 
 template <int PREC>
-hipError_t batch_dispatch(const DevState& s, int n_traps, int block, int nsteps, int accel_only,
+hipError_t batch_dispatch(const DevState& s, int n_traps, int max_trap, int block, int nsteps, int accel_only,
                           bool cool_on, double uq, int tpt, hipStream_t st) {
-    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, block, nsteps, accel_only, uq, tpt, st)
-                   : batch_dispatch_x<PREC, false>(s, n_traps, block, nsteps, accel_only, uq, tpt, st);
+    return cool_on ? batch_dispatch_x<PREC, true>(s, n_traps, max_trap, block, nsteps, accel_only, uq, tpt, st)
+                   : batch_dispatch_x<PREC, false>(s, n_traps, max_trap, block, nsteps, accel_only, uq, tpt, st);
 }
 
 }  // namespace
@@ -2550,21 +2554,19 @@ hipError_t launch_hessian(const DevState& s, const TrapDev& T, double* D, hipStr
 
 hipError_t launch_batch(const DevState& s, int precision, int n_traps, int max_trap,
                         const LaunchShape& ls, int nsteps, int, hipStream_t st) {
-    (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
+        case 0: return batch_dispatch<0>(s, n_traps, max_trap, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
+        case 2: return batch_dispatch<2>(s, n_traps, max_trap, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
+        default: return batch_dispatch<1>(s, n_traps, max_trap, ls.batch_block, nsteps, 0, ls.cool_on, ls.uniform_q, ls.batch_tpt, st);
     }
 }
 
 hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int max_trap,
                               const LaunchShape& ls, hipStream_t st) {
-    (void)max_trap;
     switch (precision) {
-        case 0: return batch_dispatch<0>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
-        case 2: return batch_dispatch<2>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
-        default: return batch_dispatch<1>(s, n_traps, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
+        case 0: return batch_dispatch<0>(s, n_traps, max_trap, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
+        case 2: return batch_dispatch<2>(s, n_traps, max_trap, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
+        default: return batch_dispatch<1>(s, n_traps, max_trap, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
     }
 }
 
