@@ -369,10 +369,21 @@ typedef struct {
                              for traps of 128 ions or more: 1, 2 or 4 (at most 2 with 1024
                              threads per trap).  Built-in: 2 (4 below 1024 threads) from 256
                              ions, 2 from 128 in a batch; 1 below                            */
+    int32_t step_launches; /* single trap stepped by the multi-workgroup kernels: 1: one
+                             launch per step (each workgroup owns a few targets, takes all
+                             sources, reduces over the workgroup and ends the step for its
+                             targets; positions alternate between two buffers); 2: the pair
+                             kernel, then the epilogue.  Handles with body exclusion or
+                             rigid bodies take 2.  Built-in: 1 for N <= LION_ONE_LAUNCH_IONS
+                             when the all-pairs kernels are selected, else 2                  */
 } lion_kernel_config;
 
 /* Ion count up to which a single trap is stepped inside one workgroup by default. */
-#define LION_SMALL_TRAP_IONS 160
+#define LION_SMALL_TRAP_IONS 128
+
+/* Ion count up to which a single trap on the multi-workgroup kernels takes one
+ * launch per step by default. */
+#define LION_ONE_LAUNCH_IONS 2048
 
 int lion_set_kernel_config(lion_sim *sim, const lion_kernel_config *cfg);
 int lion_get_kernel_config(const lion_sim *sim, lion_kernel_config *cfg);

@@ -90,7 +90,7 @@ int slices_for(int64_t n) {
 struct Layout {
     size_t src, srcm, v, a, qm, qe, mass, trap_of, part, scratch, traps, offsets, order, counter,
         flags, body_code, tile_body, tile_brange, body_gmin, body_gmax, cool, species, vacc, vavg, rigid, rb, dbody,
-        rmembers, rstart, minst, minpart, total;
+        rmembers, rstart, minst, minpart, src2, srcm2, total;
 };
 
 Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
@@ -134,6 +134,9 @@ Layout layout_for(int64_t n, int32_t n_traps, int precision, bool batched) {
     L.rstart = batched ? SIZE_MAX : take((np + 1) * sizeof(int32_t));
     L.minst = take(sizeof(lion::MinDev));
     L.minpart = take((size_t)3 * ((np + 255) / 256) * sizeof(double));
+    // second position buffers of the one-launch step (single trap)
+    L.src2 = batched ? SIZE_MAX : take(np * sizeof(double4));
+    L.srcm2 = (precision != LION_FP64 && !batched) ? take(np * sizeof(lion::MixedSrc)) : SIZE_MAX;
     L.total = o;
     return L;
 }
@@ -197,6 +200,16 @@ void default_shape(lion_sim* s) {
     if (ls.symmetric) ls.j_split = nb;               // one partial per tile
     // epilogue: 4 waves per 64 ions unless set (8 and 16 measured no faster)
     ls.update_waves = s->cfg.update_waves > 0 ? s->cfg.update_waves : 4;
+    // one launch per step: asked for, or built in up to LION_ONE_LAUNCH_IONS on the
+    // all-pairs kernels (FP64, us per step against the pair kernel + epilogue: 200
+    // ions 3.7 / 6.0, 1024 ions 4.9 / 6.3, 2048 ions 7.3 / 8.2); one target per
+    // workgroup up to 1024 ions, two above (2048 ions: 8.7 against 7.3 us)
+    ls.rows = (!s->batched && (s->cfg.step_launches == 1 ||
+                               (s->cfg.step_launches <= 0 && !ls.symmetric &&
+                                n <= LION_ONE_LAUNCH_IONS)))
+                  ? 1
+                  : 0;
+    ls.rows_tr = n <= 1024 ? 1 : 2;
     ls.uniform_q = s->uniform_q;
     ls.batch_tpt = s->cfg.batch_tpt > 0 ? s->cfg.batch_tpt : 0;
     ls.small_path = s->cfg.small_trap > 0 ? (s->cfg.small_trap == 2 ? 1 : 0)
@@ -272,6 +285,12 @@ bool small_path_active(const lion_sim* s) {
            s->d.nbodies == 0;
 }
 
+// The single trap steps with one launch per step (k_rows).
+bool rows_active(const lion_sim* s) {
+    return !s->batched && s->ls.rows && !small_path_active(s) && !s->has_bodies &&
+           s->d.nbodies == 0 && s->d.src2 && (s->precision == LION_FP64 || s->d.srcm2);
+}
+
 // Accelerations at the current positions and clocks, by the kernels that step
 // the handle (so a trap stepped inside one workgroup gets them from that kernel).
 int refresh_accel(lion_sim* s) {
@@ -282,6 +301,11 @@ int refresh_accel(lion_sim* s) {
         LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), s->stream));
         LION_HIP(s, lion::launch_batch_accel(s->d, s->precision, s->n_traps, s->max_trap, s->ls,
                                              s->stream));
+        return LION_OK;
+    }
+    if (rows_active(s)) {
+        LION_HIP(s, lion::launch_rows(s->d, s->precision, s->ls, lion::kModeAccel, 0, 0, true,
+                                      s->stream));
         return LION_OK;
     }
     LION_HIP(s, lion::launch_pair(s->d, s->precision, s->ls, false, s->stream));
@@ -305,6 +329,19 @@ hipError_t enqueue_chunk(lion_sim* s, int64_t L, hipStream_t st) {
         return e;
     }
     const bool rigid = s->d.nbodies > 0;
+    if (rows_active(s)) {
+        // one launch per step; positions alternate between the two buffers and
+        // the last step of the chunk leaves them in the first
+        e = lion::launch_drift(s->d, s->ls.cool_on, st);
+        for (int64_t k = 0; k < L && e == hipSuccess; ++k) {
+            const bool last = k + 1 == L;
+            e = lion::launch_rows(s->d, s->precision, s->ls,
+                                  last ? lion::kModeEnd : lion::kModeEndDrift, (int)k,
+                                  (int)(k & 1), last, st);
+        }
+        if (e == hipSuccess) e = lion::launch_counter_add(s->d, L, st);
+        return e;
+    }
     if (rigid) {
         // force and torque at the starting positions, then the bodies' first half-step
         e = lion::launch_rigid_wrench(s->d, false, st);
@@ -504,6 +541,8 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     d.vavg = (double*)(base + L.vavg);
     d.minst = (lion::MinDev*)(base + L.minst);
     d.minpart = (double*)(base + L.minpart);
+    d.src2 = L.src2 == SIZE_MAX ? nullptr : (double4*)(base + L.src2);
+    d.srcm2 = L.srcm2 == SIZE_MAX ? nullptr : (lion::MixedSrc*)(base + L.srcm2);
     d.nbodies = 0;  // set by lion_set_rigid_bodies
     d.rigid = nullptr;
     d.rb = nullptr;
@@ -1304,6 +1343,8 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     if (!in(c->update_waves, {4, 8, 16})) return fail(s, LION_ERR_ARG, "update_waves must be 4, 8 or 16");
     if (!in(c->small_trap, {1, 2})) return fail(s, LION_ERR_ARG, "small_trap must be 1 or 2");
     if (!in(c->batch_tpt, {1, 2, 4})) return fail(s, LION_ERR_ARG, "batch_tpt must be 1, 2 or 4");
+    if (!in(c->step_launches, {1, 2}))
+        return fail(s, LION_ERR_ARG, "step_launches must be 1 or 2");
     if (c->symmetric == 2 && (s->batched || lion::sym_tiles(s->n) > lion::kMaxSymTiles))
         return fail(s, LION_ERR_UNSUPPORTED, "pair-once kernels need one trap of N <= 131072");
     (void)hipSetDevice(s->device);
@@ -1321,6 +1362,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.update_waves = c->update_waves;
     s->cfg.small_trap = c->small_trap;
     s->cfg.batch_tpt = c->batch_tpt;
+    s->cfg.step_launches = c->step_launches;
     default_shape(s);
     return LION_OK;
 }
@@ -1339,6 +1381,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     c->update_waves = s->ls.update_waves;
     c->small_trap = s->ls.small_path ? 2 : 1;
     c->batch_tpt = s->ls.batch_tpt;
+    c->step_launches = rows_active(s) ? 1 : 2;
     return LION_OK;
 }
 

@@ -179,6 +179,9 @@ struct DevState {
     int32_t* tile_bmax;  // [n_pad / 256] largest body id in a tile (-1: none)
     int32_t* body_gmin;  // [n_pad / 16] smallest body id >= 0 in each group of 16 ions
     int32_t* body_gmax;  // [n_pad / 16] largest body id (-1 if none)
+    // second position buffers of the one-launch step (NULL when not allocated)
+    double4* src2;
+    MixedSrc* srcm2;
 };
 
 struct LaunchShape {
@@ -196,6 +199,8 @@ struct LaunchShape {
     bool cool_on;     // a beam, bath or time average is on: the kernels built with them run
     double uniform_q;  // every ion's charge in units of e when all are equal, else 0
     int sym_masked;    // pair-once kernels with the per-pair body test (bodies share tiles)
+    int rows;          // one launch per step (k_rows) for the single trap
+    int rows_tr;       // targets per workgroup of that launch: 2, 4 or 8
 };
 
 // Tiles of 256 ions used by the pair kernels that evaluate each pair once; the
@@ -244,6 +249,11 @@ int eigh_scratch_bytes(void* h, int m, bool vectors, double* A, double* W, doubl
                        size_t* bytes, std::string& err);
 int eigh_device(void* h, double* A, int m, double* W, double* E, int* info, bool vectors,
                 void* scratch, size_t scratch_bytes, hipStream_t st, std::string& err);
+// One step (or, with kModeAccel, one force evaluation) of one trap in a single
+// launch: positions read from buffer parity_in (0: src/srcm, 1: src2/srcm2);
+// drifted positions written to the other buffer, or with home_out to buffer 0.
+hipError_t launch_rows(const DevState& s, int precision, const LaunchShape& ls, int mode,
+                       int k_in_chunk, int parity_in, bool home_out, hipStream_t st);
 hipError_t launch_counter_add(const DevState& s, int64_t k, hipStream_t st);
 hipError_t launch_coulomb_potential(const DevState& s, int n_traps, hipStream_t st);
 hipError_t launch_check_finite(const DevState& s, hipStream_t st);

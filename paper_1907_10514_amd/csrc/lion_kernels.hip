@@ -1237,6 +1237,88 @@ void k_pair_f64_sym(const double4* __restrict__ src, const double* __restrict__ 
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
 
+// The per-ion inputs of the end of a step.
+struct IonIn {
+    double4 p;  // position (w: the FP64 source weight, carried along)
+    double u, v, w, qm, qe, mass;
+    int32_t sp;
+};
+
+__device__ __forceinline__ IonIn load_ion(int64_t i, const double4* src_in,
+                                          const double* __restrict__ vx,
+                                          const double* __restrict__ vy,
+                                          const double* __restrict__ vz,
+                                          const double* __restrict__ qm,
+                                          const double* __restrict__ qe,
+                                          const double* __restrict__ mass,
+                                          const int32_t* __restrict__ species) {
+    IonIn r;
+    r.p = src_in[i];
+    r.u = vx[i];
+    r.v = vy[i];
+    r.w = vz[i];
+    r.qm = qm[i];
+    r.qe = qe[i];
+    r.mass = mass[i];
+    r.sp = species[i];
+    return r;
+}
+
+// The end of a step for ion i (inputs in) from its summed pair field S
+// (scaled), with c = cos(Omega t) of the step's time: the trap field, then
+// (mode kModeEnd) the closing half kick with damping, or (kModeEndDrift) also
+// the first half of the next step, whose position goes to src_out;
+// kModeAccel stores the acceleration only.  kc is the call's step counter
+// after this step (numbers the cooling draws).
+template <bool X>
+__device__ __forceinline__ void end_step_vals(
+    int mode, int64_t i, int64_t kc, const TrapDev& T, double c, double Sx, double Sy,
+    double Sz, IonIn in, double4* src_out, MixedSrc* __restrict__ srcm_out,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+    double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az, int64_t n_pad,
+    const CoolDev* __restrict__ cool, double* __restrict__ vacc, double* __restrict__ vavg) {
+    double4 p = in.p;
+    double a_x, a_y, a_z;
+    trap_accel_c(T, c, in.qm, p.x, p.y, p.z, Sx, Sy, Sz, a_x, a_y, a_z);
+    ax[i] = a_x;
+    ay[i] = a_y;
+    az[i] = a_z;
+    if (mode == kModeAccel) return;
+    const int64_t step = cool->step_base + kc;  // the step this epilogue completes
+    double u = in.u, v = in.v, w = in.w;
+    const CoolRef cr = cool_switches<X>(cool);
+    end_kick(T, cr, i, in.sp, in.mass, step, u, v, w, a_x, a_y, a_z);
+    time_average(cr, i, n_pad, step, vacc, vavg, u, v, w);
+    if (mode == kModeEndDrift) {
+        half_step_drift(T, cr, i, in.sp, in.mass, step + 1, p.x, p.y, p.z, u, v, w, a_x, a_y,
+                        a_z);
+        src_out[i] = p;
+        if (srcm_out) srcm_out[i] = make_src(p.x, p.y, p.z, in.qe);
+    }
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+}
+
+// As end_step_vals, loading the inputs first; rigid-body members (rb[i] >= 0)
+// only get their acceleration (their body kicks them).
+template <bool X>
+__device__ __forceinline__ void end_step_ion(
+    int mode, int64_t i, int64_t kc, const TrapDev& T, double t, double Sx, double Sy,
+    double Sz, const double4* src_in, double4* src_out, MixedSrc* __restrict__ srcm_out,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+    double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az,
+    const double* __restrict__ qm, const double* __restrict__ qe,
+    const double* __restrict__ mass, const int32_t* __restrict__ species, int64_t n_pad,
+    const CoolDev* __restrict__ cool, double* __restrict__ vacc, double* __restrict__ vavg,
+    const int32_t* __restrict__ rb) {
+    const IonIn in = load_ion(i, src_in, vx, vy, vz, qm, qe, mass, species);
+    const double c = T.ps != 0.0 ? 0.0 : cos(T.omega * t);
+    const int m = (mode != kModeAccel && rb && rb[i] >= 0) ? kModeAccel : mode;
+    end_step_vals<X>(m, i, kc, T, c, Sx, Sy, Sz, in, src_out, srcm_out, vx, vy, vz, ax, ay, az,
+                     n_pad, cool, vacc, vavg);
+}
+
 // Per-ion epilogue of a step (or a plain force evaluation): reduce the slice
 // partials in slice order, add the trap field, then kick / damp / drift.
 // Per-ion epilogue of a step (or a plain force evaluation).  A block covers 64
@@ -1291,34 +1373,174 @@ __global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
         Sy += red[w][1][lane];
         Sz += red[w][2][lane];
     }
-    Sx *= field_scale;
-    Sy *= field_scale;
-    Sz *= field_scale;
     const TrapDev T = traps[0];
     const double t = counter ? T.t_start + (double)(*counter) * T.dt : T.t_start;
-    double4 p = src[i];
-    double a_x, a_y, a_z;
-    trap_accel(T, t, qm[i], p.x, p.y, p.z, Sx, Sy, Sz, a_x, a_y, a_z);
-    ax[i] = a_x;
-    ay[i] = a_y;
-    az[i] = a_z;
-    if (MODE == kModeAccel) return;
-    if (rb && rb[i] >= 0) return;  // rigid-body members: kicked through their body
-    const int64_t step = cool->step_base + *counter;  // the step this epilogue completes
-    const int32_t sp = species[i];
-    const double mi = mass[i];
-    double u = vx[i], v = vy[i], w = vz[i];
-    const CoolRef cr = cool_switches<X>(cool);
-    end_kick(T, cr, i, sp, mi, step, u, v, w, a_x, a_y, a_z);
-    time_average(cr, i, n_pad, step, vacc, vavg, u, v, w);
-    if (MODE == kModeEndDrift) {
-        half_step_drift(T, cr, i, sp, mi, step + 1, p.x, p.y, p.z, u, v, w, a_x, a_y, a_z);
-        src[i] = p;
-        if (srcm) srcm[i] = make_src(p.x, p.y, p.z, qe[i]);
+    end_step_ion<X>(MODE, i, counter ? *counter : 0, T, t, Sx * field_scale, Sy * field_scale,
+                    Sz * field_scale, src, src, srcm, vx, vy, vz, ax, ay, az, qm, qe, mass,
+                    species, n_pad, cool, vacc, vavg, rb);
+}
+
+// ---------------------------------------------- one launch per step (mid-size traps)
+//
+// One trap of n ions, one launch per step.  Workgroup g owns the TR targets
+// [g TR, g TR + TR); thread t takes the sources t, t + kRowsBlock, ... for all
+// of them.  The per-thread sums are added over each wave by a fixed butterfly
+// (every lane ends with the same sum) and over the waves in wave order, and the
+// owning threads end the step for their targets.  Every workgroup reads all
+// positions of the step, so the drifted positions go to the other buffer.
+
+constexpr int kRowsBlock = 256;
+
+struct RowsArgs {
+    const double4* src_in;
+    double4* src_out;        // drifted positions (kModeEndDrift), or the home buffer
+    const MixedSrc* srcm_in;
+    MixedSrc* srcm_out;
+    double *vx, *vy, *vz, *ax, *ay, *az;
+    const double *qm, *qe, *mass;
+    const int32_t* species;
+    const TrapDev* traps;
+    const CoolDev* cool;
+    const int64_t* counter;  // the call's step counter at the start of the chunk
+    double *vacc, *vavg;
+    int64_t n, n_pad;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <int PREC, int TR, bool X>
+__global__ __launch_bounds__(kRowsBlock) void k_rows(const RowsArgs A, int mode, int k_in_chunk) {
+    __shared__ double red[kRowsBlock / 64][3 * TR];
+    const int64_t n = A.n;
+    const int64_t i0 = (int64_t)blockIdx.x * TR;
+    const int tid = threadIdx.x;
+    // the owners' inputs and the step's time first, so that their loads overlap
+    // the pair work
+    const TrapDev T = A.traps[0];
+    const bool counted = mode != kModeAccel;
+    const int64_t kc = counted ? *A.counter + k_in_chunk + 1 : 0;
+    const bool own = tid < TR && i0 + tid < n;
+    IonIn me{};
+    if (own)
+        me = load_ion(i0 + tid, A.src_in, A.vx, A.vy, A.vz, A.qm, A.qe, A.mass, A.species);
+    double sx[TR], sy[TR], sz[TR];
+#pragma unroll
+    for (int k = 0; k < TR; ++k) sx[k] = sy[k] = sz[k] = 0.0;
+    // sources four at a time (all four loads in flight); past n the last ion again,
+    // with zero weight
+    constexpr int U = 4;
+    if constexpr (PREC == 0) {
+        double tx[TR], ty[TR], tz[TR];
+#pragma unroll
+        for (int k = 0; k < TR; ++k) {
+            const double4 p = A.src_in[min(i0 + k, n - 1)];
+            tx[k] = p.x;
+            ty[k] = p.y;
+            tz[k] = p.z;
+        }
+        for (int64_t j0 = tid; j0 < n; j0 += U * kRowsBlock) {
+            double4 P[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = j0 + (int64_t)u * kRowsBlock;
+                P[u] = A.src_in[min(j, n - 1)];
+                if (j >= n) P[u].w = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < TR; ++k)
+                    pair_f64(P[u], tx[k], ty[k], tz[k], sx[k], sy[k], sz[k]);
+        }
+    } else {
+        FF tf[TR];
+#pragma unroll
+        for (int k = 0; k < TR; ++k) {
+            const MixedSrc m = A.srcm_in[min(i0 + k, n - 1)];
+            tf[k] = FF{m.xh, m.yh, m.zh, m.xl, m.yl, m.zl};
+        }
+        float fx[TR], fy[TR], fz[TR], cx[TR], cy[TR], cz[TR];
+#pragma unroll
+        for (int k = 0; k < TR; ++k) fx[k] = fy[k] = fz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
+        int run = 0;
+        for (int64_t j0 = tid; j0 < n; j0 += U * kRowsBlock) {
+            MixedSrc Q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = j0 + (int64_t)u * kRowsBlock;
+                Q[u] = A.srcm_in[min(j, n - 1)];
+                if (j >= n) Q[u].nq = 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int k = 0; k < TR; ++k) {
+                    if constexpr (PREC == 2) {
+                        float ux, uy, uz;
+                        pair_f32_terms(Q[u], tf[k], ux, uy, uz);
+                        kahan_add(ux, fx[k], cx[k]);
+                        kahan_add(uy, fy[k], cy[k]);
+                        kahan_add(uz, fz[k], cz[k]);
+                    } else {
+                        pair_f32(Q[u], tf[k], fx[k], fy[k], fz[k]);
+                    }
+                }
+            }
+            // FP32 runs of 8 sources, flushed to FP64 (compensated: one run)
+            run += U;
+            if (PREC == 1 && run == 8) {
+                run = 0;
+#pragma unroll
+                for (int k = 0; k < TR; ++k) {
+                    sx[k] += (double)fx[k];
+                    sy[k] += (double)fy[k];
+                    sz[k] += (double)fz[k];
+                    fx[k] = fy[k] = fz[k] = 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TR; ++k) {
+            sx[k] += (double)fx[k] - (double)cx[k];
+            sy[k] += (double)fy[k] - (double)cy[k];
+            sz[k] += (double)fz[k] - (double)cz[k];
+        }
     }
-    vx[i] = u;
-    vy[i] = v;
-    vz[i] = w;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < TR; ++k) {
+        const double x = wave_sum(sx[k]), y = wave_sum(sy[k]), z = wave_sum(sz[k]);
+        if (lane == 0) {
+            red[wave][3 * k + 0] = x;
+            red[wave][3 * k + 1] = y;
+            red[wave][3 * k + 2] = z;
+        }
+    }
+    const double t = counted ? T.t_start + (double)kc * T.dt : T.t_start;
+    const double crf = (own && T.ps == 0.0) ? cos(T.omega * t) : 0.0;
+    __syncthreads();
+    if (!own) return;
+    const int k = tid;
+    double Sx = red[0][3 * k], Sy = red[0][3 * k + 1], Sz = red[0][3 * k + 2];
+#pragma unroll
+    for (int w = 1; w < kRowsBlock / 64; ++w) {
+        Sx += red[w][3 * k];
+        Sy += red[w][3 * k + 1];
+        Sz += red[w][3 * k + 2];
+    }
+    const double fs = PREC == 0 ? 1.0 : kMixedFieldScale;
+    const int64_t i = i0 + k;
+    end_step_vals<X>(mode, i, kc, T, crf, Sx * fs, Sy * fs, Sz * fs, me, A.src_out, A.srcm_out,
+                     A.vx, A.vy, A.vz, A.ax, A.ay, A.az, A.n_pad, A.cool, A.vacc, A.vavg);
+    // the last step of a launch sequence leaves the positions in the home buffer
+    if (mode == kModeEnd && A.src_out != A.src_in) {
+        A.src_out[i] = me.p;
+        if (A.srcm_out) A.srcm_out[i] = A.srcm_in[i];
+    }
 }
 
 __global__ void k_counter_add(int64_t* counter, int64_t k) {
@@ -2567,6 +2789,65 @@ hipError_t launch_batch_accel(const DevState& s, int precision, int n_traps, int
         case 0: return batch_dispatch<0>(s, n_traps, max_trap, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
         case 2: return batch_dispatch<2>(s, n_traps, max_trap, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
         default: return batch_dispatch<1>(s, n_traps, max_trap, ls.batch_block, 0, 1, false, ls.uniform_q, ls.batch_tpt, st);
+    }
+}
+
+namespace {
+
+template <int PREC, int TR>
+hipError_t rows_launch(const RowsArgs& A, bool cool_on, int mode, int k, hipStream_t st) {
+    const unsigned g = (unsigned)((A.n + TR - 1) / TR);
+    if (cool_on && mode != kModeAccel)
+        k_rows<PREC, TR, true><<<g, kRowsBlock, 0, st>>>(A, mode, k);
+    else
+        k_rows<PREC, TR, false><<<g, kRowsBlock, 0, st>>>(A, mode, k);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t rows_dispatch(const RowsArgs& A, int tr, bool cool_on, int mode, int k,
+                         hipStream_t st) {
+    switch (tr) {
+        case 1: return rows_launch<PREC, 1>(A, cool_on, mode, k, st);
+        case 2: return rows_launch<PREC, 2>(A, cool_on, mode, k, st);
+        case 8: return rows_launch<PREC, 8>(A, cool_on, mode, k, st);
+        default: return rows_launch<PREC, 4>(A, cool_on, mode, k, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rows(const DevState& s, int precision, const LaunchShape& ls, int mode,
+                       int k_in_chunk, int parity_in, bool home_out, hipStream_t st) {
+    if (!s.src2 || (precision != 0 && (!s.srcm || !s.srcm2))) return hipErrorInvalidValue;
+    RowsArgs A{};
+    double4* buf[2] = {s.src, s.src2};
+    MixedSrc* bufm[2] = {s.srcm, s.srcm2};
+    A.src_in = buf[parity_in];
+    A.src_out = home_out ? buf[0] : buf[1 - parity_in];
+    A.srcm_in = precision == 0 ? nullptr : bufm[parity_in];
+    A.srcm_out = precision == 0 ? nullptr : (home_out ? bufm[0] : bufm[1 - parity_in]);
+    A.vx = s.vx;
+    A.vy = s.vy;
+    A.vz = s.vz;
+    A.ax = s.ax;
+    A.ay = s.ay;
+    A.az = s.az;
+    A.qm = s.qm;
+    A.qe = s.qe;
+    A.mass = s.mass;
+    A.species = s.species;
+    A.traps = s.traps;
+    A.cool = s.cool;
+    A.counter = s.counter;
+    A.vacc = s.vacc;
+    A.vavg = s.vavg;
+    A.n = s.n;
+    A.n_pad = s.n_pad;
+    switch (precision) {
+        case 0: return rows_dispatch<0>(A, ls.rows_tr, ls.cool_on, mode, k_in_chunk, st);
+        case 2: return rows_dispatch<2>(A, ls.rows_tr, ls.cool_on, mode, k_in_chunk, st);
+        default: return rows_dispatch<1>(A, ls.rows_tr, ls.cool_on, mode, k_in_chunk, st);
     }
 }
 

@@ -42,7 +42,8 @@ class KernelConfig(ctypes.Structure):
                 ("batch_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("lds_sources", ctypes.c_int32), ("symmetric", ctypes.c_int32),
                 ("sym_variant", ctypes.c_int32), ("update_waves", ctypes.c_int32),
-                ("small_trap", ctypes.c_int32), ("batch_tpt", ctypes.c_int32)]
+                ("small_trap", ctypes.c_int32), ("batch_tpt", ctypes.c_int32),
+                ("step_launches", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

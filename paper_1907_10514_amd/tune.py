@@ -2,7 +2,8 @@
 
 For a given workload size and precision it times every candidate launch shape
 (targets per lane I, source slices J, FP32 run length L, LDS or scalar source
-feed, pair-once kernel variant; for batches the workgroup size per trap and the
+feed, pair-once kernel variant, one launch per step or pair kernel + epilogue;
+for batches the workgroup size per trap and the
 targets per thread) with the library's own kernel timer, rejects candidates
 whose forces differ from the FP64 path by more than half the precision's bar on
 a validation cloud (for batches, on every trap of the batch), times the fastest again as whole
@@ -28,6 +29,9 @@ from . import lion as L
 CACHE_ENV = "LION_TUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 BAR = {L.LION_FP64: 1e-12, L.LION_MIXED_F64ACC: 1e-6, L.LION_MIXED_KAHAN: 1e-6}
+# largest single trap for which the one-launch step is a candidate (its workgroups
+# each read every source, so it loses to the pair kernels well before this)
+ONE_LAUNCH_MAX = 8192
 
 
 def cache_path() -> str:
@@ -90,6 +94,13 @@ def _scale(x, y, z, q_e):
 
 
 def single_candidates(n: int, precision: int):
+    """Pair kernel + epilogue shapes (step_launches=2); the one-launch step,
+    which has no pair kernel of its own, is timed with the whole steps."""
+    for cfg in _two_launch_candidates(n, precision):
+        yield dict(cfg, step_launches=2)
+
+
+def _two_launch_candidates(n: int, precision: int):
     js = [j for j in (1, 2, 4, 8, 12, 16, 24, 32, 48, 64)]
     if precision == L.LION_FP64:
         for i, j in itertools.product((1, 2, 4), js):
@@ -176,6 +187,19 @@ def tune_single(n: int, precision: int, reps: int = 20, verbose: bool = True,
             times.append(1e3 * (time.perf_counter() - t0) / step_reps)
         return sorted(times)[1]
 
+    # one launch per step (up to ONE_LAUNCH_MAX ions), accuracy-gated like the rest
+    if n <= ONE_LAUNCH_MAX:
+        cfg = dict(step_launches=1)
+        sim.set_config(**cfg)
+        val.set_config(**cfg)
+        a = np.array(val.compute_accel())
+        err = float(np.max(np.linalg.norm(a - a_ref, axis=0) / sc))
+        ent = dict(config=cfg, pair_ms=None, m1_vs_fp64=err, ok=err <= BAR[precision] * 0.5)
+        results.append(ent)
+        if ent["ok"]:
+            ok.append(ent)
+        elif verbose:
+            print(f"  {cfg} M1 {err:.2e}  REJECT", flush=True)
     for r in ok:
         r["step_ms"] = median_step_ms(r["config"])
         if verbose:

@@ -92,7 +92,8 @@ def _segment_ratios(oracle, w, sp, tr, spec, k0, a_gpu, s0, t0, got, ion_base=0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
-def test_cooled_run_matches_oracle(torch_gpu, oracle_mod, prec):
+@pytest.mark.parametrize("launches", [1, 2])
+def test_cooled_run_matches_oracle(torch_gpu, oracle_mod, prec, launches):
     """Two species, a beam on each and two baths (one species-selective), run in
     four calls (10 + 110 + 10 + 70 steps), each continuing the draw sequence.
     The cloud is chaotic, so the GPU is compared in two re-anchored segments:
@@ -101,13 +102,15 @@ def test_cooled_run_matches_oracle(torch_gpu, oracle_mod, prec):
     envelope of the oracle's own segment under per-step velocity kicks of
     dt M1 A_i (M1 the GPU's measured force error there).  The CPU controls show
     that a wrong draw, species or rate moves such a segment by >= 10 bars.
-    FP64 also matches the whole 200-step run within 10x the one-ulp envelope."""
+    FP64 also matches the whole 200-step run within 10x the one-ulp envelope.
+    Both the one-launch step and the pair kernel + epilogue are run."""
     w = li.random_cloud(700, seed=41, sigma=200e-6, light_fraction=0.3)
     wd = dict(charge=w.charge, mass=w.mass)
     sp = _species(w)
     spec = w.traps[0]
     tr = _oracle_trap(oracle_mod, spec)
-    sim = _cooled_sim(w, prec, oracle_mod, sp)
+    sim = _cooled_sim(w, prec, oracle_mod, sp, step_launches=launches)
+    assert sim.config()["step_launches"] == launches
     states = {0: (w.state(), 0.0, sim.compute_accel())}
     for k, n in ((10, 10), (120, 110), (130, 10), (200, 70)):
         sim.step(n, spec.dt)

@@ -33,6 +33,8 @@ def _pseudo(oracle, q_x=0.3, a_x=-0.001):
 def _sim(mass, charge, prec, tr, st, gamma=0.0, n_per_trap=None, **cfg):
     from paper_1907_10514_amd import Simulation
 
+    if cfg.get("symmetric") == 1:
+        cfg.setdefault("step_launches", 2)  # the all-pairs pair kernel and its epilogue
     sim = Simulation(mass, charge, prec, n_per_trap=n_per_trap)
     if cfg:
         sim.set_config(**cfg)

@@ -23,6 +23,7 @@ ALLOWED = {
     "update_waves": {4, 8, 16},
     "small_trap": {1, 2},
     "batch_tpt": {1, 2, 4},
+    "step_launches": {1, 2},
 }
 
 
