@@ -348,16 +348,18 @@ typedef struct {
                              (N >= 10240 for LION_MIXED_F64ACC).  With
                              LION_MIXED_KAHAN the FP32 runs of each 256 x 256 tile pair are
                              added in compensated FP32 and the tile-pair totals in FP64       */
-    int32_t sym_variant;  /* pair-once kernel variant, 1..7 (built-in: 7 for
+    int32_t sym_variant;  /* pair-once kernel variant, 1..9 (built-in: 9 for
                              LION_MIXED_F64ACC, 6 for LION_FP64; LION_MIXED_KAHAN always
                              runs the shape of 7).  FP32 pairs: reaction sums
                              per chunk of 8 or 4 sources, sources unrolled, register budget,
                              next source prefetched: 1: 8, two, 4 waves/SIMD; 2: 4, one,
                              5 waves; 3: 4, one, 6 waves; 4: 8, one, 5-wave budget; 5: 4, one,
                              4 waves; 6: 8, one, 5-wave budget, prefetch; 7: 8, two, 4 waves,
-                             prefetch.  FP64: 1: two sources unrolled, 3 waves/SIMD; 2: one,
-                             4 waves; 3: one, 3 waves; 4: two, 4 waves (spills); 5: two,
-                             2 waves; 6: one, 4 waves, prefetch; 7: two, 3 waves, prefetch   */
+                             prefetch; the target sums in FP32 runs of 8 sources (1-7),
+                             16 (8: the shape of 7) or 64 (9: the shape of 7).  FP64: 1: two
+                             sources unrolled, 3 waves/SIMD; 2: one, 4 waves; 3: one,
+                             3 waves; 4: two, 4 waves (spills); 5: two, 2 waves; 6: one,
+                             4 waves, prefetch; 7, 8, 9: two, 3 waves, prefetch              */
     int32_t update_waves; /* waves that share the slice sums of 64 ions in the step
                              epilogue: 4, 8 or 16 (built-in: 4)                               */
     int32_t small_trap;   /* single trap: 1: always the multi-workgroup kernels; 2: step the

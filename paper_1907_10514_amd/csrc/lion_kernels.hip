@@ -927,8 +927,9 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
     }
 }
 
-// CH: sources per reaction-sum chunk (LDS per block grows with it); WPE: the
-// occupancy the register allocation aims at.
+// L: sources per FP32 run of the target sums (a multiple of CH), after which
+// they go into the FP64 sums; CH: sources per reaction-sum chunk (LDS per block
+// grows with it); WPE: the occupancy the register allocation aims at.
 // FQ: every ion of the tile pair carries the same charge uq (in units of e), so
 // the per-pair charge factors are applied once per sum instead (an exact
 // refactoring; tiles holding zero-charge padding ions take the general path).
@@ -980,10 +981,16 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
     float* jb = reinterpret_cast<float*>(smem) + wave * 64 * S;
     // with PF the next source is read from LDS while the current one is used
     MixedSrc m_next = mine[0];
-    for (int s0 = 0; s0 < 64; s0 += CH) {
-        float fx[4], fy[4], fz[4];
+    // target sums: FP32 runs of L sources (a multiple of CH), then into FP64
+    static_assert(L % CH == 0 && 64 % L == 0, "runs of whole chunks");
+    float fx[4], fy[4], fz[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+    for (int k = 0; k < 4; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+    for (int s0 = 0; s0 < 64; s0 += CH) {
+        if (KH) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+        }
 #pragma unroll UNR
         for (int uu = 0; uu < CH; ++uu) {
             MixedSrc m;
@@ -1020,16 +1027,20 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
                 jb[lane * S + 3 * uu + 2] = tz;
             }
         }
+        if constexpr (KH) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if constexpr (KH) {
+            for (int k = 0; k < 4; ++k) {
                 kahan_add(fx[k], ksx[k], kcx[k]);
                 kahan_add(fy[k], ksy[k], kcy[k]);
                 kahan_add(fz[k], ksz[k], kcz[k]);
-            } else {
+            }
+        } else if ((s0 + CH) % L == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
                 sx[k] += (double)fx[k];
                 sy[k] += (double)fy[k];
                 sz[k] += (double)fz[k];
+                fx[k] = fy[k] = fz[k] = 0.0f;
             }
         }
         if (!diag) {
@@ -2656,6 +2667,12 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
                     break;
                 case 6:
                     k_pair_mixed_sym<8, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
+                    break;
+                case 7:  // the shape of 7 with FP32 runs of 16 sources
+                    k_pair_mixed_sym<16, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
+                    break;
+                case 8:  // the shape of 7 with FP32 runs of 64 sources (a wave's share)
+                    k_pair_mixed_sym<64, 8, 4, 2, true><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);
                     break;
                 default:
                     k_pair_mixed_sym<8, 8, 4, 2><<<units, 256, 0, st>>>(s.srcm, s.n, nb, s.n_pad, s.part, ctr, (float)uq, full, tb);

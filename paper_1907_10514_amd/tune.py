@@ -112,7 +112,7 @@ def _two_launch_candidates(n: int, precision: int):
         for i, j, fl, lds in itertools.product((1, 2, 4), js, (8, 16), (1, 2)):
             yield dict(i_per_lane=i, j_split=j, flush_len=fl, lds_sources=lds, symmetric=1)
         if (n + 255) // 256 <= 512:
-            for v in (1, 2, 4, 5, 6, 7):
+            for v in (1, 2, 4, 5, 6, 7, 8, 9):
                 yield dict(symmetric=2, sym_variant=v)
     else:
         for i, j, lds in itertools.product((1, 2, 4), js, (1, 2)):

@@ -301,7 +301,7 @@ def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_pair_once_variants(torch_gpu, oracle_mod, prec, variant):
     """Every pair-once kernel variant the tuner may pick meets the bar, on full
     and ragged tiles."""

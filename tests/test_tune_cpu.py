@@ -19,7 +19,7 @@ ALLOWED = {
     "use_graph": {1, 2},
     "lds_sources": {1, 2},
     "symmetric": {1, 2},
-    "sym_variant": set(range(1, 8)),
+    "sym_variant": set(range(1, 10)),
     "update_waves": {4, 8, 16},
     "small_trap": {1, 2},
     "batch_tpt": {1, 2, 4},
