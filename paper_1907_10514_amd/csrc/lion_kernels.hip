@@ -1892,11 +1892,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const int64_t o = offsets[tr];
     const int m = (int)(offsets[tr + 1] - o);
     const int m16 = (m + 15) & ~15;
-    // owner slots: whole waves, except on one wave (traps of <= 64 ions), where
-    // the m owners are followed by the other source parts of the same wave, of
-    // about four sources each (the part sums are added in a dependent chain)
-    const int IS = BLOCK == 64 ? max(m, 1) : min((m + 63) & ~63, BLOCK);
-    const int JP = BLOCK == 64 ? max(1, min(BLOCK / IS, (m + 3) / 4)) : BLOCK / IS;
+    // owner slots: whole waves, except for traps of <= 64 ions, whose m owners
+    // are followed by source parts of about four sources each (at most 8 parts:
+    // the owners add the part sums in a dependent chain)
+    const bool tiny = m <= 64;
+    const int IS = tiny ? max(m, 1) : min((m + 63) & ~63, BLOCK);
+    const int JP = tiny ? max(1, min(min(BLOCK / IS, (m + 3) / 4), 8)) : BLOCK / IS;
     const int tid = threadIdx.x;
     const int slot = tid % IS;
     const int jpart = tid / IS;
@@ -1904,10 +1905,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     const bool owner = jpart == 0;
     // sources per part when each thread has one target: whole FP32 runs of 8 in
     // the FP32 + FP64 mode, multiples of 4 otherwise (padding beyond m adds
-    // nothing), so that the sources of a small trap spread over the parts; on
-    // one wave single sources, so that a part's dependent chain stays short
-    constexpr int kGran = BLOCK == 64 ? 1 : (PREC == 1 ? 8 : 4);
-    const int send = BLOCK == 64 ? m : (PREC == 1 ? m16 : (m + 3) & ~3);
+    // nothing), so that the sources of a small trap spread over the parts; for
+    // traps of <= 64 ions any count, so that a part's dependent chain stays short
+    const int kGran = tiny ? 1 : (PREC == 1 ? 8 : 4);
+    const int send = tiny ? m : (PREC == 1 ? m16 : (m + 3) & ~3);
     const int jlen = ((send + JP - 1) / JP + kGran - 1) / kGran * kGran;
     const int jb = min(jpart * jlen, send);
     const int je = min(jb + jlen, send);
