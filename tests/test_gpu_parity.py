@@ -736,6 +736,34 @@ def test_one_wave_shape_up_to_64_ions(torch_gpu, oracle_mod, n):
     sim.close()
 
 
+@pytest.mark.parametrize("n,block", [(17, 256), (33, 512), (48, 512), (56, 1024), (64, 1024)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_owner_parts_split_up_to_64_ions(torch_gpu, oracle_mod, n, block, prec):
+    """Traps of <= 64 ions on 256 to 1024 threads: m owners followed by at
+    most 8 source parts (48 ions on 512 threads would take 10 without the
+    cap). Forces against the oracle, then forces after 60 steps; in FP64 the
+    run itself against the oracle's steps."""
+    w = li.random_cloud(n, seed=500 + n, sigma=20e-6, light_fraction=0.2)
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
+    sim = _sim(w, prec, oracle_mod, small_trap=2, batch_block=block)
+    assert sim.config()["batch_block"] == block
+    r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    assert _m1(sim.compute_accel(), r, sc) <= TOL[prec]
+    sim.step(60, spec.dt)
+    st, t = sim.get_state()
+    r = oracle_mod.accel(st["x"], st["y"], st["z"], w.charge, w.mass, tr, t)
+    sc = oracle_mod.accel_scale(st["x"], st["y"], st["z"], w.charge, w.mass, tr, t)
+    assert _m1(sim.compute_accel(), r, sc) <= TOL[prec]
+    if prec == "fp64":
+        ref = oracle_mod.step(w.state(), w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, 60)
+        disp = np.max(np.abs(ref["x"] - w.x)) + 1e-12
+        for c in ("x", "y", "z"):
+            assert np.max(np.abs(st[c] - ref[c])) < 1e-10 * disp, c
+    sim.close()
+
+
 def test_one_wave_shape_refused_above_64_ions(torch_gpu, oracle_mod):
     from paper_1907_10514_amd.lion import LionError
 
