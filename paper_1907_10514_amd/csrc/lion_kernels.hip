@@ -1674,11 +1674,62 @@ __device__ __forceinline__ void batch_pair_f32(const BatchMixedSrc& p, double xi
     tz = w * dz;
 }
 
+// FP32 sums of runs of RUN sources over [jb, je), each run added to the FP64
+// sums (sx, sy, sz) of its target; the last run as far as the sources go.
+// Within a run the sources go 8 at a time (unrolled), then one by one.
+template <int TPT, bool FQ, int RUN>
+__device__ __forceinline__ void batch_runs_f32(const BatchMixedSrc* __restrict__ lds, int jb,
+                                               int je, const double (&xi)[TPT],
+                                               const double (&yi)[TPT], const double (&zi)[TPT],
+                                               double (&sx)[TPT], double (&sy)[TPT],
+                                               double (&sz)[TPT]) {
+    for (int j = jb; j < je; j += RUN) {
+        float fx[TPT], fy[TPT], fz[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+        const int jend = min(j + RUN, je);
+        for (int j8 = j; j8 < jend; j8 += 8) {
+            if (j8 + 8 <= jend) {
+#pragma unroll
+                for (int uu = 0; uu < 8; ++uu) {
+                    const BatchMixedSrc q = lds[j8 + uu];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        float tx, ty, tz;
+                        batch_pair_f32<FQ>(q, xi[k], yi[k], zi[k], tx, ty, tz);
+                        fx[k] += tx;
+                        fy[k] += ty;
+                        fz[k] += tz;
+                    }
+                }
+            } else {
+                for (int jj = j8; jj < jend; ++jj) {
+                    const BatchMixedSrc q = lds[jj];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        float tx, ty, tz;
+                        batch_pair_f32<FQ>(q, xi[k], yi[k], zi[k], tx, ty, tz);
+                        fx[k] += tx;
+                        fy[k] += ty;
+                        fz[k] += tz;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            sx[k] += (double)fx[k];
+            sy[k] += (double)fy[k];
+            sz[k] += (double)fz[k];
+        }
+    }
+}
+
 // Field sums of TPT targets per thread over the sources [jb, je) of the LDS
 // stream (je <= m: only the trap's ions, no padding): each source is read once
 // for all TPT targets (il_k = slot + ws k),
 // which cuts the broadcast LDS reads per pair by TPT.  Per target the sums run
-// over the sources in order, as with one target per thread (FP32 runs of 8
+// over the sources in order, as with one target per thread (FP32 runs
 // flushed to FP64, or Kahan).  Targets at or beyond m give unused sums.
 // FQ: every ion carries the charge uq (units of e); the sums run over r^-3 d
 // alone and are scaled by the charge once.
@@ -1750,44 +1801,14 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
             double sx[TPT], sy[TPT], sz[TPT];
 #pragma unroll
             for (int k = 0; k < TPT; ++k) sx[k] = sy[k] = sz[k] = 0.0;
-            // FP32 runs of 8 sources (the last one shorter) flushed to FP64
-            for (int j = jb; j < je; j += 8) {
-                float fx[TPT], fy[TPT], fz[TPT];
-#pragma unroll
-                for (int k = 0; k < TPT; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
-                if (j + 8 <= je) {
-#pragma unroll
-                    for (int uu = 0; uu < 8; ++uu) {
-                        const BatchMixedSrc q = lds[j + uu];
-#pragma unroll
-                        for (int k = 0; k < TPT; ++k) {
-                            float tx, ty, tz;
-                            batch_pair_f32<FQ>(q, xi[k], yi[k], zi[k], tx, ty, tz);
-                            fx[k] += tx;
-                            fy[k] += ty;
-                            fz[k] += tz;
-                        }
-                    }
-                } else {
-                    for (int jj = j; jj < je; ++jj) {
-                        const BatchMixedSrc q = lds[jj];
-#pragma unroll
-                        for (int k = 0; k < TPT; ++k) {
-                            float tx, ty, tz;
-                            batch_pair_f32<FQ>(q, xi[k], yi[k], zi[k], tx, ty, tz);
-                            fx[k] += tx;
-                            fy[k] += ty;
-                            fz[k] += tz;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < TPT; ++k) {
-                    sx[k] += (double)fx[k];
-                    sy[k] += (double)fy[k];
-                    sz[k] += (double)fz[k];
-                }
-            }
+            // FP32 runs flushed to FP64 (the last one shorter): 64 sources with
+            // several targets per thread (large traps) over parts of 64 or more,
+            // else 8 (a lone trap's latency-bound steps measured slower with the
+            // 64-source loop beside them)
+            if (TPT > 1 && je - jb >= 64)
+                batch_runs_f32<TPT, FQ, 64>(lds, jb, je, xi, yi, zi, sx, sy, sz);
+            else
+                batch_runs_f32<TPT, FQ, 8>(lds, jb, je, xi, yi, zi, sx, sy, sz);
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
                 Sx[k] = sx[k] * cs;
