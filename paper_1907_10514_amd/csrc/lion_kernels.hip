@@ -1801,12 +1801,12 @@ __device__ __forceinline__ void batch_pairs_multi(const typename BatchSrc<PREC>:
             double sx[TPT], sy[TPT], sz[TPT];
 #pragma unroll
             for (int k = 0; k < TPT; ++k) sx[k] = sy[k] = sz[k] = 0.0;
-            // FP32 runs flushed to FP64 (the last one shorter): 64 sources with
-            // several targets per thread (large traps) over parts of 64 or more,
-            // else 8 (a lone trap's latency-bound steps measured slower with the
-            // 64-source loop beside them)
-            if (TPT > 1 && je - jb >= 64)
-                batch_runs_f32<TPT, FQ, 64>(lds, jb, je, xi, yi, zi, sx, sy, sz);
+            // FP32 runs flushed to FP64 (the last one shorter): 16 sources with
+            // several targets per thread (large traps), else 8.  On the 512-trap
+            // batch, M1 against the FP64 path 3.7e-7 with runs of 16, 5.0e-7 with
+            // runs of 32 or 64, 3.3e-7 with runs of 8.
+            if constexpr (TPT > 1)
+                batch_runs_f32<TPT, FQ, 16>(lds, jb, je, xi, yi, zi, sx, sy, sz);
             else
                 batch_runs_f32<TPT, FQ, 8>(lds, jb, je, xi, yi, zi, sx, sy, sz);
 #pragma unroll
