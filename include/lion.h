@@ -369,8 +369,9 @@ typedef struct {
                              for N <= LION_SMALL_TRAP_IONS, else 1                           */
     int32_t batch_tpt;    /* batched kernel (and the one-workgroup path): targets per thread
                              for traps of 128 ions or more: 1, 2 or 4 (at most 2 with 1024
-                             threads per trap).  Built-in: 2 (4 below 1024 threads) from 256
-                             ions, 2 from 128 in a batch; 1 below                            */
+                             threads per trap; 2 or 4 is raised where the threads times the
+                             count fall short of the trap's ions).  Built-in: 2 (4 below
+                             1024 threads) from 256 ions, 2 from 128 in a batch; 1 below    */
     int32_t step_launches; /* single trap stepped by the multi-workgroup kernels: 1: one
                              launch per step (each workgroup owns a few targets, takes all
                              sources, reduces over the workgroup and ends the step for its

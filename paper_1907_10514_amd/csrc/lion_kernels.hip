@@ -1939,10 +1939,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     // below kBatchTpt4 ions saves the extra reduction rounds
     const int tpt2_from = gridDim.x == 1 ? kBatchTpt4 : kBatchTpt2;
     int TPT = m >= kBatchTpt4 ? TMAX : (m >= tpt2_from ? 2 : 1);
-    if (TPT > 1)
-        while (TPT < TMAX && TPT * BLOCK < m) TPT *= 2;
     // a requested count (launch-shape tuning) for traps of kBatchTpt2 ions or more
     if (tpt_req > 0 && m >= kBatchTpt2) TPT = min(tpt_req, TMAX);
+    // with several targets per thread, at least enough of them for the BLOCK
+    // threads to cover the trap (TMAX * BLOCK >= kMaxTrap); one target per
+    // thread covers any trap through the KMAX owner slots
+    if (TPT > 1)
+        while (TPT < TMAX && TPT * BLOCK < m) TPT *= 2;
     const int WS = ((m + 64 * TPT - 1) / (64 * TPT)) * 64;  // <= BLOCK
     const int JPW = BLOCK / WS;
     const int wslot = tid % WS, wpart = tid / WS;

@@ -821,6 +821,27 @@ def test_batch_large_traps_run(torch_gpu, oracle_mod, prec, tol, block):
             assert np.max(np.abs(st[c][o:e] - ref[c][o:e])) < tol * disp, (k, c)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+@pytest.mark.parametrize("block,tpt", [(256, 1), (256, 2), (256, 4), (512, 1), (512, 2),
+                                       (512, 4), (1024, 1), (1024, 2)])
+def test_batch_tuner_shapes_accel_parity(torch_gpu, oracle_mod, prec, block, tpt):
+    """Every (threads per trap, targets per thread) shape the batch tuner may
+    pick, forced on traps of 2 to 1024 ions (the FP32 runs of the threads with
+    several targets included): forces against the oracle trap by trap."""
+    w = _large_trap_batch()
+    traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
+    sim = _sim(w, prec, oracle_mod, batch_block=block, batch_tpt=tpt)
+    a = sim.compute_accel()
+    sim.close()
+    r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
+                               np.zeros(w.n_traps))
+    for k in range(w.n_traps):
+        o, e = w.offsets[k], w.offsets[k + 1]
+        sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e],
+                                    traps[k], 0.0)
+        assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
+
+
 def test_batch_equals_single_trap_path(torch_gpu, oracle_mod):
     """One trap run through the batched kernel and through the single-trap
     kernels gives the same trajectory (FP64, to roundoff)."""
