@@ -842,6 +842,35 @@ def test_batch_tuner_shapes_accel_parity(torch_gpu, oracle_mod, prec, block, tpt
         assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
+@pytest.mark.parametrize("n", [100, 300, 700, 1024])
+def test_lone_trap_workgroup_shapes_parity(torch_gpu, oracle_mod, prec, n):
+    """A single trap stepped inside one workgroup, in every workgroup size and
+    targets-per-thread count it accepts: forces against the oracle, then (FP64)
+    a 30-step run against the oracle's steps."""
+    w = li.random_cloud(n, seed=900 + n, sigma=30e-6, light_fraction=0.2)
+    spec = w.traps[0]
+    tr = _oracle_trap(oracle_mod, spec)
+    r = oracle_mod.accel(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    sc = oracle_mod.accel_scale(w.x, w.y, w.z, w.charge, w.mass, tr, 0.0)
+    ref = (oracle_mod.step(w.state(), w.charge, w.mass, tr, spec.gamma, 0.0, spec.dt, 30)
+           if prec == "fp64" else None)
+    for block in (256, 512, 1024):
+        for tpt in (1, 2, 4):
+            if block == 1024 and tpt == 4:
+                continue
+            sim = _sim(w, prec, oracle_mod, small_trap=2, batch_block=block, batch_tpt=tpt)
+            assert sim.config()["batch_block"] == block
+            assert _m1(sim.compute_accel(), r, sc) <= TOL[prec], (block, tpt)
+            if ref is not None:
+                sim.step(30, spec.dt)
+                st, _ = sim.get_state()
+                disp = np.max(np.abs(ref["x"] - w.x)) + 1e-12
+                for c in ("x", "y", "z"):
+                    assert np.max(np.abs(st[c] - ref[c])) < 1e-10 * disp, (block, tpt, c)
+            sim.close()
+
+
 def test_batch_equals_single_trap_path(torch_gpu, oracle_mod):
     """One trap run through the batched kernel and through the single-trap
     kernels gives the same trajectory (FP64, to roundoff)."""
