@@ -304,9 +304,11 @@ def test_pair_once_full_size_and_steps(torch_gpu, oracle_mod, prec):
 @pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_pair_once_variants(torch_gpu, oracle_mod, prec, variant):
     """Every pair-once kernel variant the tuner may pick meets the bar, on full
-    and ragged tiles."""
-    for n in (255, 1000, 4097):
-        w = li.random_cloud(n, seed=500 + n, sigma=60e-6, light_fraction=0.2)
+    and ragged tiles, with one common charge (the charge factored out of the
+    sums) and with mixed charges (per-source charges in the sums)."""
+    for n, mixed_q in ((255, False), (1000, False), (4097, False), (1000, True), (4097, True)):
+        q = np.random.default_rng(n).choice([1, 1, 2, -1], n) if mixed_q else None
+        w = li.random_cloud(n, seed=500 + n, sigma=60e-6, light_fraction=0.2, charge_e=q)
         sim = _sim(w, prec, oracle_mod, symmetric=2, sym_variant=variant)
         assert sim.config()["sym_variant"] == variant
         tr = _oracle_trap(oracle_mod, w.traps[0])
