@@ -829,19 +829,22 @@ def test_batch_large_traps_run(torch_gpu, oracle_mod, prec, tol, block):
 def test_batch_tuner_shapes_accel_parity(torch_gpu, oracle_mod, prec, block, tpt):
     """Every (threads per trap, targets per thread) shape the batch tuner may
     pick, forced on traps of 2 to 1024 ions (the FP32 runs of the threads with
-    several targets included): forces against the oracle trap by trap."""
+    several targets included), with mixed charges and with one common charge
+    (factored out of the sums): forces against the oracle trap by trap."""
     w = _large_trap_batch()
     traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
-    sim = _sim(w, prec, oracle_mod, batch_block=block, batch_tpt=tpt)
-    a = sim.compute_accel()
-    sim.close()
-    r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
-                               np.zeros(w.n_traps))
-    for k in range(w.n_traps):
-        o, e = w.offsets[k], w.offsets[k + 1]
-        sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e], w.mass[o:e],
-                                    traps[k], 0.0)
-        assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
+    for charge in (w.charge, np.full(w.n, li.E_CHARGE)):
+        w.charge = charge
+        sim = _sim(w, prec, oracle_mod, batch_block=block, batch_tpt=tpt)
+        a = sim.compute_accel()
+        sim.close()
+        r = oracle_mod.accel_batch(w.offsets, w.x, w.y, w.z, w.charge, w.mass, traps,
+                                   np.zeros(w.n_traps))
+        for k in range(w.n_traps):
+            o, e = w.offsets[k], w.offsets[k + 1]
+            sc = oracle_mod.accel_scale(w.x[o:e], w.y[o:e], w.z[o:e], w.charge[o:e],
+                                        w.mass[o:e], traps[k], 0.0)
+            assert _m1([c[o:e] for c in a], [c[o:e] for c in r], sc) <= TOL[prec], k
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
