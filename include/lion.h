@@ -332,14 +332,18 @@ typedef struct {
     int32_t i_per_lane;   /* target ions per lane in the pair kernel: 1, 2 or 4          */
     int32_t j_split;      /* source slices per step (1..64; clipped to one per 64 sources),
                              partial sums reduced in slice order                           */
-    int32_t chunk_steps;  /* steps per captured launch graph (1..1000)                     */
+    int32_t chunk_steps;  /* steps per captured launch graph (1..1000).  Built-in: 1000
+                             when one workgroup steps the trap (a single trap on the
+                             one-workgroup path, or batches of traps of at most 16 ions),
+                             else 100                                                     */
     int32_t flush_len;    /* LION_MIXED_F64ACC: sources per FP32 run: 4, 8 or 16           */
     int32_t batch_block;  /* threads per trap in batched mode and on the one-workgroup path:
                              64 (traps of at most 64 ions only), 256, 512 or 1024.  Built-in:
-                             batched, 64 when the largest trap holds at most 12 ions, 1024
+                             batched, 64 when the largest trap holds at most 16 ions, 1024
                              when it holds 256 or more, else 256; a lone trap on the
-                             one-workgroup path, 64 up to 12 ions, 256 up to 32, 512 up to
-                             64, 1024 above                                                 */
+                             one-workgroup path, 64 up to 16 ions, 256 up to 32, 512 up to
+                             64, 1024 above.  64 runs the one-wave kernel (target state in
+                             registers, source parts in consecutive lanes)                  */
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);

@@ -61,9 +61,16 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxTrap = 1024;
-// traps of at most this many ions step on one wave (64-thread workgroups): at 8
-// ions 0.95 against 1.24 us per step (256 threads), at 16 ions 1.42 against 1.26
-constexpr int64_t kOneWaveIons = 12;
+// traps of at most this many ions step on one wave (the one-wave kernel, us per
+// step FP64 / FP32 pairs against 256 threads: 16 ions 0.85 / 0.93 against 1.16 /
+// 1.31, 24 ions 1.40 / 1.48 against 1.31 / 1.48)
+constexpr int64_t kOneWaveIons = 16;
+// steps per captured launch when not set: 1000 where one workgroup steps a trap
+// for the whole launch (a single trap of <= LION_SMALL_TRAP_IONS, or batches of
+// traps on one wave), whose steps take about a microsecond (8 ions: 0.60 against
+// 0.67 us per step with 100), else 100
+constexpr int kChunkLong = 1000;
+constexpr int kChunkDefault = 100;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -290,6 +297,13 @@ bool small_path_active(const lion_sim* s) {
 bool rows_active(const lion_sim* s) {
     return !s->batched && s->ls.rows && !small_path_active(s) && !s->has_bodies &&
            s->d.nbodies == 0 && s->d.src2 && (s->precision == LION_FP64 || s->d.srcm2);
+}
+
+// Steps per captured launch: the configured count, else the built-in one.
+int64_t chunk_len(const lion_sim* s) {
+    if (s->cfg.chunk_steps > 0) return s->cfg.chunk_steps;
+    const bool one_wg = small_path_active(s) || (s->batched && s->ls.batch_block == 64);
+    return one_wg ? kChunkLong : kChunkDefault;
 }
 
 // Accelerations at the current positions and clocks, by the kernels that step
@@ -568,7 +582,7 @@ int create_common(lion_sim** out, int32_t n_traps, const int64_t* n_per_trap, in
     s->body_off[4] = L.tile_brange;
     s->ws = base;
     s->j_max = batched ? 1 : j_max_for(n);
-    s->cfg.chunk_steps = 100;
+    s->cfg.chunk_steps = 0;
     s->cfg.use_graph = 1;
     default_shape(s);
 
@@ -1055,7 +1069,7 @@ static int step_common(lion_sim* s, int64_t nsteps, const double* dts) {
     rc = upload_cooling(s, dts[0]);
     if (rc) return rc;
     LION_HIP(s, hipMemsetAsync(s->d.counter, 0, sizeof(int64_t), s->stream));
-    const int64_t S = std::max(1, s->cfg.chunk_steps);
+    const int64_t S = chunk_len(s);
     for (int64_t done = 0; done < nsteps;) {
         const int64_t L = std::min(S, nsteps - done);
         rc = run_chunk(s, L);
@@ -1090,7 +1104,7 @@ int lion_prepare_step(lion_sim* s, int64_t nsteps) {
         clear_graphs(s);
         s->ls.cool_on = on;
     }
-    const int64_t S = std::max(1, s->cfg.chunk_steps);
+    const int64_t S = chunk_len(s);
     hipGraphExec_t ex = nullptr;
     if (nsteps >= S) {
         int rc = chunk_graph(s, S, &ex);
@@ -1356,7 +1370,7 @@ int lion_set_kernel_config(lion_sim* s, const lion_kernel_config* c) {
     s->cfg.j_split = c->j_split;
     s->cfg.flush_len = c->flush_len;
     s->cfg.batch_block = c->batch_block;
-    s->cfg.chunk_steps = c->chunk_steps > 0 ? c->chunk_steps : 100;
+    s->cfg.chunk_steps = c->chunk_steps > 0 ? c->chunk_steps : 0;
     s->cfg.use_graph = c->use_graph > 0 ? c->use_graph : 1;
     s->cfg.lds_sources = c->lds_sources;
     s->cfg.symmetric = c->symmetric;
@@ -1373,7 +1387,7 @@ int lion_get_kernel_config(const lion_sim* s, lion_kernel_config* c) {
     if (check_handle(s) || !c) return LION_ERR_ARG;
     c->i_per_lane = s->ls.i_per_lane;
     c->j_split = s->ls.j_split;
-    c->chunk_steps = s->cfg.chunk_steps;
+    c->chunk_steps = (int32_t)chunk_len(s);
     c->flush_len = s->ls.flush_len;
     c->batch_block = s->ls.batch_block;
     c->use_graph = s->cfg.use_graph;

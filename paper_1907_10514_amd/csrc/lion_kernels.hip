@@ -2126,6 +2126,158 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
     }
 }
 
+// ------------------------------------------------- traps of <= 64 ions, one wave
+//
+// The batched step of traps of at most 64 ions on one wave, with the target
+// state in registers and no workgroup machinery: lane l works for target
+// l / P over source part l % P (P a power of two, at most 8, with m P <= 64),
+// the parts of a target sit in consecutive lanes and their sums are added by
+// a fixed xor butterfly (every lane of the group ends with the same sum), and
+// the owner (part 0) ends the step.  The arithmetic per pair and per step is
+// that of k_batch (the same pair terms, FP32 runs of at most 8 sources, the
+// cos(Omega t) table, the same step numbering for the cooling draws); the
+// sources of a part are summed in order, the parts by the butterfly.
+
+template <int PREC, bool X>
+__global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
+                                             double* __restrict__ vx, double* __restrict__ vy,
+                                             double* __restrict__ vz, double* __restrict__ ax,
+                                             double* __restrict__ ay, double* __restrict__ az,
+                                             const double* __restrict__ qm,
+                                             const double* __restrict__ qe,
+                                             const double* __restrict__ mass,
+                                             const int32_t* __restrict__ species,
+                                             const TrapDev* __restrict__ traps,
+                                             const CoolDev* __restrict__ cool,
+                                             const int64_t* __restrict__ offsets,
+                                             const int32_t* __restrict__ order,
+                                             const int64_t* __restrict__ counter,
+                                             double* __restrict__ vacc,
+                                             double* __restrict__ vavg, int64_t n_pad,
+                                             int nsteps, int accel_only) {
+    using S = typename BatchSrc<PREC>::T;
+    __shared__ S lds[64];
+    constexpr int kRf = 64;
+    __shared__ double rf[2][kRf];
+    const int tr = order[blockIdx.x];
+    const int64_t o = offsets[tr];
+    const int m = (int)(offsets[tr + 1] - o);  // <= 64 (checked by the host)
+    int P = 1;
+    while (P < 8 && 2 * P <= m && 2 * P * m <= 64) P *= 2;
+    const int lane = threadIdx.x;
+    const int ti = lane / P, part = lane - ti * P;
+    const bool owner = part == 0 && ti < m;
+    const int spp = (m + P - 1) / P;
+    const int jb = min(part * spp, m), je = min(jb + spp, m);
+    const TrapDev T = traps[tr];
+    const int64_t k0 = *counter;
+    const int64_t step0 = cool->step_base + k0 + 1;  // run-wide number of the first step
+    const CoolRef cr = cool_switches<X>(cool);
+    const int64_t ion = o + min(ti, m - 1);
+    double x = 0.0, y = 0.0, z = 0.0, u = 0.0, v = 0.0, w = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    double q_m = 0.0, q_e = 0.0, m_i = 1.0;
+    int32_t sp = 0;
+    if (owner) {
+        const double4 p = src[ion];
+        x = p.x;
+        y = p.y;
+        z = p.z;
+        u = vx[ion];
+        v = vy[ion];
+        w = vz[ion];
+        a0 = ax[ion];
+        a1 = ay[ion];
+        a2 = az[ion];
+        q_m = qm[ion];
+        q_e = qe[ion];
+        m_i = mass[ion];
+        sp = species[ion];
+    }
+    const int total = accel_only ? 1 : nsteps;
+    for (int step = 0; step < total; ++step) {
+        if (step % kRf == 0 && T.ps == 0.0 && lane < kRf && step + lane < total) {
+            const double tq =
+                T.t_start + (double)(k0 + step + lane + (accel_only ? 0 : 1)) * T.dt;
+            rf[(step / kRf) & 1][lane] = cos(T.omega * tq);
+        }
+        if (owner) {
+            if (!accel_only)
+                half_step_drift(T, cr, ion, sp, m_i, step0 + step, x, y, z, u, v, w, a0, a1,
+                                a2);
+            if constexpr (PREC == 0) {
+                lds[ti] = make_double4(x, y, z, 1.5 * q_e);
+            } else if constexpr (PREC == 1) {
+                lds[ti] = make_batch_src(x, y, z, q_e);
+            } else {
+                lds[ti] = make_src(x, y, z, q_e);
+            }
+        }
+        __syncthreads();
+        double Sx = 0.0, Sy = 0.0, Sz = 0.0;
+        const S me = lds[min(ti, m - 1)];
+        if constexpr (PREC == 0) {
+            for (int j = jb; j < je; ++j) pair_f64(lds[j], me.x, me.y, me.z, Sx, Sy, Sz);
+        } else if constexpr (PREC == 1) {
+            // FP32 runs of at most 8 sources, flushed to FP64
+            for (int j0 = jb; j0 < je; j0 += 8) {
+                float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+                const int j1 = min(j0 + 8, je);
+                for (int j = j0; j < j1; ++j) {
+                    float tx, ty, tz;
+                    batch_pair_f32<false>(lds[j], me.x, me.y, me.z, tx, ty, tz);
+                    fx += tx;
+                    fy += ty;
+                    fz += tz;
+                }
+                Sx += (double)fx;
+                Sy += (double)fy;
+                Sz += (double)fz;
+            }
+            Sx *= kMixedFieldScale;
+            Sy *= kMixedFieldScale;
+            Sz *= kMixedFieldScale;
+        } else {
+            const FF t{me.xh, me.yh, me.zh, me.xl, me.yl, me.zl};
+            float sx = 0.0f, sy = 0.0f, sz = 0.0f, cx = 0.0f, cy = 0.0f, cz = 0.0f;
+            for (int j = jb; j < je; ++j) {
+                float tx, ty, tz;
+                pair_f32_terms<false>(lds[j], t, tx, ty, tz);
+                kahan_add(tx, sx, cx);
+                kahan_add(ty, sy, cy);
+                kahan_add(tz, sz, cz);
+            }
+            Sx = ((double)sx - (double)cx) * kMixedFieldScale;
+            Sy = ((double)sy - (double)cy) * kMixedFieldScale;
+            Sz = ((double)sz - (double)cz) * kMixedFieldScale;
+        }
+        // the parts of a target: a fixed butterfly over its P consecutive lanes
+        for (int d = P / 2; d >= 1; d >>= 1) {
+            Sx += __shfl_xor(Sx, d);
+            Sy += __shfl_xor(Sy, d);
+            Sz += __shfl_xor(Sz, d);
+        }
+        if (owner) {
+            const double crf = T.ps == 0.0 ? rf[(step / kRf) & 1][step % kRf] : 0.0;
+            trap_accel_c(T, crf, q_m, x, y, z, Sx, Sy, Sz, a0, a1, a2);
+            if (!accel_only) {
+                end_kick(T, cr, ion, sp, m_i, step0 + step, u, v, w, a0, a1, a2);
+                time_average(cr, ion, n_pad, step0 + step, vacc, vavg, u, v, w);
+            }
+        }
+        // every lane is past its reads of the source stream and the cos table
+        __syncthreads();
+    }
+    if (owner) {
+        src[ion] = make_double4(x, y, z, 1.5 * q_e);
+        vx[ion] = u;
+        vy[ion] = v;
+        vz[ion] = w;
+        ax[ion] = a0;
+        ay[ion] = a1;
+        az[ion] = a2;
+    }
+}
+
 // ------------------------------------------------------------ rigid bodies
 
 __device__ __forceinline__ void quat_rot(const double q[4], double A[9]) {
@@ -2577,10 +2729,20 @@ hipError_t batch_launch(const DevState& s, int n_traps, int max_trap, int nsteps
 }
 
 template <int PREC, bool X>
+hipError_t wave_launch(const DevState& s, int n_traps, int nsteps, int accel_only,
+                       hipStream_t st) {
+    k_wave<PREC, X><<<n_traps, 64, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm, s.qe,
+                                            s.mass, s.species, s.traps, s.cool, s.offsets,
+                                            s.order, s.counter, s.vacc, s.vavg, s.n_pad, nsteps,
+                                            accel_only);
+    return hipGetLastError();
+}
+
+template <int PREC, bool X>
 hipError_t batch_dispatch_x(const DevState& s, int n_traps, int max_trap, int block, int nsteps,
                             int accel_only, double uq, int tpt, hipStream_t st) {
     switch (block) {
-        case 64: return batch_launch<PREC, 64, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
+        case 64: return wave_launch<PREC, X>(s, n_traps, nsteps, accel_only, st);
         case 512: return batch_launch<PREC, 512, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
         case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
         default: return batch_launch<PREC, 256, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);

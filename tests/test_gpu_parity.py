@@ -676,12 +676,12 @@ def _tiny_trap_batch(sizes, seed):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_one_wave_traps_match_oracle(torch_gpu, oracle_mod, prec):
-    """Traps of at most 12 ions step on one wave (64-thread workgroups, the
+    """Traps of at most 16 ions step on one wave (the one-wave kernel, the
     built-in shape).  Forces of every trap against the oracle before and after
     a 130-step run (three launches of 50 steps, so the per-launch table of RF
     phases is refilled within a launch and across launches); in FP64 the run
     itself against the oracle's batched steps."""
-    sizes = np.array([1, 2, 3, 5, 7, 8, 9, 11, 12, 12, 4, 6])
+    sizes = np.array([1, 2, 3, 5, 7, 8, 9, 11, 12, 12, 4, 6, 13, 16])
     w = _tiny_trap_batch(sizes, seed=61)
     traps = [_oracle_trap(oracle_mod, s) for s in w.traps]
     sim = _sim(w, prec, oracle_mod, chunk_steps=50)
