@@ -2130,15 +2130,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
 //
 // The batched step of traps of at most 64 ions on one wave, with the target
 // state in registers and no workgroup machinery: lane l works for target
-// l / P over source part l % P (P a power of two, at most 8, with m P <= 64),
-// the parts of a target sit in consecutive lanes and their sums are added by
+// l / P over source part l % P (P a power of two, at most 8, chosen per launch
+// from the largest trap m_max with m_max P <= 64; see wave_parts), the parts
+// of a target sit in consecutive lanes and their sums are added by
 // a fixed xor butterfly (every lane of the group ends with the same sum), and
 // the owner (part 0) ends the step.  The arithmetic per pair and per step is
 // that of k_batch (the same pair terms, FP32 runs of at most 8 sources, the
 // cos(Omega t) table, the same step numbering for the cooling draws); the
 // sources of a part are summed in order, the parts by the butterfly.
 
-template <int PREC, bool X>
+template <int PREC, int P, bool X>
 __global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
                                              double* __restrict__ vx, double* __restrict__ vy,
                                              double* __restrict__ vz, double* __restrict__ ax,
@@ -2161,9 +2162,7 @@ __global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
     __shared__ double rf[2][kRf];
     const int tr = order[blockIdx.x];
     const int64_t o = offsets[tr];
-    const int m = (int)(offsets[tr + 1] - o);  // <= 64 (checked by the host)
-    int P = 1;
-    while (P < 8 && 2 * P <= m && 2 * P * m <= 64) P *= 2;
+    const int m = (int)(offsets[tr + 1] - o);  // <= 64 and m P <= 64 (checked by the host)
     const int lane = threadIdx.x;
     const int ti = lane / P, part = lane - ti * P;
     const bool owner = part == 0 && ti < m;
@@ -2251,6 +2250,7 @@ __global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
             Sz = ((double)sz - (double)cz) * kMixedFieldScale;
         }
         // the parts of a target: a fixed butterfly over its P consecutive lanes
+#pragma unroll
         for (int d = P / 2; d >= 1; d >>= 1) {
             Sx += __shfl_xor(Sx, d);
             Sy += __shfl_xor(Sy, d);
@@ -2728,21 +2728,42 @@ hipError_t batch_launch(const DevState& s, int n_traps, int max_trap, int nsteps
     return hipGetLastError();
 }
 
-template <int PREC, bool X>
-hipError_t wave_launch(const DevState& s, int n_traps, int nsteps, int accel_only,
-                       hipStream_t st) {
-    k_wave<PREC, X><<<n_traps, 64, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm, s.qe,
-                                            s.mass, s.species, s.traps, s.cool, s.offsets,
-                                            s.order, s.counter, s.vacc, s.vavg, s.n_pad, nsteps,
-                                            accel_only);
+template <int PREC, int P, bool X>
+hipError_t wave_launch_p(const DevState& s, int n_traps, int nsteps, int accel_only,
+                         hipStream_t st) {
+    k_wave<PREC, P, X><<<n_traps, 64, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm,
+                                               s.qe, s.mass, s.species, s.traps, s.cool,
+                                               s.offsets, s.order, s.counter, s.vacc, s.vavg,
+                                               s.n_pad, nsteps, accel_only);
     return hipGetLastError();
+}
+
+// Parts per target of the one-wave kernel for traps of at most max_trap ions: a
+// power of two, at most 8 and at most the trap size, with max_trap * P <= 64
+// (8 ions: 8 parts of one source, 0.41 against 0.57 us per step with 2 parts of
+// four in a stand-alone loop; 2 ions: 2 parts, 0.32 against 0.49 with 32).
+inline int wave_parts(int max_trap) {
+    int P = 1;
+    while (P < 8 && 2 * P <= max_trap && 2 * P * max_trap <= 64) P *= 2;
+    return P;
+}
+
+template <int PREC, bool X>
+hipError_t wave_launch(const DevState& s, int n_traps, int max_trap, int nsteps, int accel_only,
+                       hipStream_t st) {
+    switch (wave_parts(max_trap)) {
+        case 8: return wave_launch_p<PREC, 8, X>(s, n_traps, nsteps, accel_only, st);
+        case 4: return wave_launch_p<PREC, 4, X>(s, n_traps, nsteps, accel_only, st);
+        case 2: return wave_launch_p<PREC, 2, X>(s, n_traps, nsteps, accel_only, st);
+        default: return wave_launch_p<PREC, 1, X>(s, n_traps, nsteps, accel_only, st);
+    }
 }
 
 template <int PREC, bool X>
 hipError_t batch_dispatch_x(const DevState& s, int n_traps, int max_trap, int block, int nsteps,
                             int accel_only, double uq, int tpt, hipStream_t st) {
     switch (block) {
-        case 64: return wave_launch<PREC, X>(s, n_traps, nsteps, accel_only, st);
+        case 64: return wave_launch<PREC, X>(s, n_traps, max_trap, nsteps, accel_only, st);
         case 512: return batch_launch<PREC, 512, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
         case 1024: return batch_launch<PREC, 1024, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
         default: return batch_launch<PREC, 256, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);
