@@ -62,13 +62,15 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxTrap = 1024;
 // traps of at most this many ions step on one wave (the one-wave kernel, us per
-// step FP64 / FP32 pairs against 256 threads: 16 ions 0.85 / 0.93 against 1.16 /
-// 1.31, 24 ions 1.40 / 1.48 against 1.31 / 1.48)
+// step FP64 / FP32 pairs / compensated against 256 threads: 16 ions 0.69 / 0.75 /
+// 0.83 against 1.14 / 1.29 / 1.16; 20 ions 1.12 / 1.13 / 1.36 against 1.14 / 1.29
+// / 1.16)
 constexpr int64_t kOneWaveIons = 16;
 // steps per captured launch when not set: 1000 where one workgroup steps a trap
 // for the whole launch (a single trap of <= LION_SMALL_TRAP_IONS, or batches of
 // traps on one wave), whose steps take about a microsecond (8 ions: 0.60 against
-// 0.67 us per step with 100), else 100
+// 0.67 us per step with 100, before the one-wave kernel's unrolled butterfly),
+// else 100
 constexpr int kChunkLong = 1000;
 constexpr int kChunkDefault = 100;
 
