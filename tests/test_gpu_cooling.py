@@ -188,15 +188,17 @@ def test_beam_cooling_of_free_ions_is_exact(torch_gpu, oracle_mod):
         sim.close()
 
 
+@pytest.mark.parametrize("n_max", [300, 16])
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
-def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec):
+def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec, n_max):
     """Batched traps draw bath kicks by run-wide ion index (trap k's first ion is
     offsets[k]).  Every trap's steps 51-60 (re-anchored at the state the GPU
     reached after 50 steps) match the oracle run with that ion_base within the
     per-ion segment bars at the measured M1 of that trap; in FP64 every trap's
     whole 100-step run also matches within max(1e-10 x displacement, 10x the
-    one-ulp envelope)."""
-    w = li.batch512(n_traps=12, n_min=2, n_max=300, seed=23, nsteps=0)
+    one-ulp envelope).  Traps of up to 300 ions run in the batched kernel, traps
+    of up to 16 in the one-wave kernel."""
+    w = li.batch512(n_traps=12, n_min=2, n_max=n_max, seed=23, nsteps=0)
     rng = np.random.default_rng(4)
     sp = rng.integers(0, 2, w.n).astype(np.int32)
     sim = _cooled_sim(w, prec, oracle_mod, sp, chunk_steps=30)
