@@ -2136,11 +2136,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(double4* __restrict__ src,
 // a fixed xor butterfly (every lane of the group ends with the same sum), and
 // the owner (part 0) ends the step.  The arithmetic per pair and per step is
 // that of k_batch (the same pair terms, FP32 runs of at most 8 sources, the
-// cos(Omega t) table, the same step numbering for the cooling draws); the
-// sources of a part are summed in order, the parts by the butterfly.
+// cos(Omega t) table, the same step numbering for the cooling draws); part p
+// sums the sources p, p + P, ... in order, the parts are added by the
+// butterfly.
 
-template <int PREC, int P, bool X>
-__global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
+template <int PREC, int P, int W, bool X>
+__global__ __launch_bounds__(64 * W) void k_wave(double4* __restrict__ src,
                                              double* __restrict__ vx, double* __restrict__ vy,
                                              double* __restrict__ vz, double* __restrict__ ax,
                                              double* __restrict__ ay, double* __restrict__ az,
@@ -2157,17 +2158,16 @@ __global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
                                              double* __restrict__ vavg, int64_t n_pad,
                                              int nsteps, int accel_only) {
     using S = typename BatchSrc<PREC>::T;
-    __shared__ S lds[64];
+    constexpr int kSlots = 64 * W / P;  // targets per workgroup
+    __shared__ S lds[kSlots];
     constexpr int kRf = 64;
     __shared__ double rf[2][kRf];
     const int tr = order[blockIdx.x];
     const int64_t o = offsets[tr];
-    const int m = (int)(offsets[tr + 1] - o);  // <= 64 and m P <= 64 (checked by the host)
+    const int m = (int)(offsets[tr + 1] - o);  // <= kSlots (checked by the host)
     const int lane = threadIdx.x;
     const int ti = lane / P, part = lane - ti * P;
     const bool owner = part == 0 && ti < m;
-    const int spp = (m + P - 1) / P;
-    const int jb = min(part * spp, m), je = min(jb + spp, m);
     const TrapDev T = traps[tr];
     const int64_t k0 = *counter;
     const int64_t step0 = cool->step_base + k0 + 1;  // run-wide number of the first step
@@ -2214,14 +2214,16 @@ __global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
         __syncthreads();
         double Sx = 0.0, Sy = 0.0, Sz = 0.0;
         const S me = lds[min(ti, m - 1)];
+        // part p takes the sources p, p + P, ...: the P parts of a target read P
+        // consecutive records at a time (no LDS bank conflicts between them)
         if constexpr (PREC == 0) {
-            for (int j = jb; j < je; ++j) pair_f64(lds[j], me.x, me.y, me.z, Sx, Sy, Sz);
+            for (int j = part; j < m; j += P) pair_f64(lds[j], me.x, me.y, me.z, Sx, Sy, Sz);
         } else if constexpr (PREC == 1) {
             // FP32 runs of at most 8 sources, flushed to FP64
-            for (int j0 = jb; j0 < je; j0 += 8) {
+            for (int j0 = part; j0 < m; j0 += 8 * P) {
                 float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-                const int j1 = min(j0 + 8, je);
-                for (int j = j0; j < j1; ++j) {
+                const int j1 = min(j0 + 8 * P, m);
+                for (int j = j0; j < j1; j += P) {
                     float tx, ty, tz;
                     batch_pair_f32<false>(lds[j], me.x, me.y, me.z, tx, ty, tz);
                     fx += tx;
@@ -2238,7 +2240,7 @@ __global__ __launch_bounds__(64) void k_wave(double4* __restrict__ src,
         } else {
             const FF t{me.xh, me.yh, me.zh, me.xl, me.yl, me.zl};
             float sx = 0.0f, sy = 0.0f, sz = 0.0f, cx = 0.0f, cy = 0.0f, cz = 0.0f;
-            for (int j = jb; j < je; ++j) {
+            for (int j = part; j < m; j += P) {
                 float tx, ty, tz;
                 pair_f32_terms<false>(lds[j], t, tx, ty, tz);
                 kahan_add(tx, sx, cx);
@@ -2728,13 +2730,14 @@ hipError_t batch_launch(const DevState& s, int n_traps, int max_trap, int nsteps
     return hipGetLastError();
 }
 
-template <int PREC, int P, bool X>
+template <int PREC, int P, int W, bool X>
 hipError_t wave_launch_p(const DevState& s, int n_traps, int nsteps, int accel_only,
                          hipStream_t st) {
-    k_wave<PREC, P, X><<<n_traps, 64, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm,
-                                               s.qe, s.mass, s.species, s.traps, s.cool,
-                                               s.offsets, s.order, s.counter, s.vacc, s.vavg,
-                                               s.n_pad, nsteps, accel_only);
+    k_wave<PREC, P, W, X><<<n_traps, 64 * W, 0, st>>>(s.src, s.vx, s.vy, s.vz, s.ax, s.ay, s.az,
+                                                      s.qm, s.qe, s.mass, s.species, s.traps,
+                                                      s.cool, s.offsets, s.order, s.counter,
+                                                      s.vacc, s.vavg, s.n_pad, nsteps,
+                                                      accel_only);
     return hipGetLastError();
 }
 
@@ -2752,16 +2755,36 @@ template <int PREC, bool X>
 hipError_t wave_launch(const DevState& s, int n_traps, int max_trap, int nsteps, int accel_only,
                        hipStream_t st) {
     switch (wave_parts(max_trap)) {
-        case 8: return wave_launch_p<PREC, 8, X>(s, n_traps, nsteps, accel_only, st);
-        case 4: return wave_launch_p<PREC, 4, X>(s, n_traps, nsteps, accel_only, st);
-        case 2: return wave_launch_p<PREC, 2, X>(s, n_traps, nsteps, accel_only, st);
-        default: return wave_launch_p<PREC, 1, X>(s, n_traps, nsteps, accel_only, st);
+        case 8: return wave_launch_p<PREC, 8, 1, X>(s, n_traps, nsteps, accel_only, st);
+        case 4: return wave_launch_p<PREC, 4, 1, X>(s, n_traps, nsteps, accel_only, st);
+        case 2: return wave_launch_p<PREC, 2, 1, X>(s, n_traps, nsteps, accel_only, st);
+        default: return wave_launch_p<PREC, 1, 1, X>(s, n_traps, nsteps, accel_only, st);
+    }
+}
+
+// The same kernel on block / 64 waves with 8 parts per target, for traps of at
+// most block / 8 ions (a target's parts stay within one wave).
+constexpr int kWaveMultiIons = 48;
+template <int PREC, bool X>
+hipError_t wave_launch_multi(const DevState& s, int n_traps, int block, int nsteps,
+                             int accel_only, hipStream_t st) {
+    switch (block) {
+        case 1024: return wave_launch_p<PREC, 8, 16, X>(s, n_traps, nsteps, accel_only, st);
+        case 512: return wave_launch_p<PREC, 8, 8, X>(s, n_traps, nsteps, accel_only, st);
+        default: return wave_launch_p<PREC, 8, 4, X>(s, n_traps, nsteps, accel_only, st);
     }
 }
 
 template <int PREC, bool X>
 hipError_t batch_dispatch_x(const DevState& s, int n_traps, int max_trap, int block, int nsteps,
                             int accel_only, double uq, int tpt, hipStream_t st) {
+    // traps of at most 48 ions and block / 8: the wave kernel on block / 64 waves
+    // (us per step FP64 / FP32 pairs against the batched kernel: 20 ions 0.88 / 0.99
+    // against 1.15 / 1.30, 32 ions 1.02 / 1.13 against 1.32 / 1.48, 48 ions 1.31 /
+    // 1.39 against 1.50 / 1.49; 64 ions 1.64 / 1.63 against 1.63 / 1.52 and 100
+    // ions 3.29 / 3.03 against 2.72 / 2.35, so larger traps keep the batched kernel)
+    if (block != 64 && 8 * max_trap <= block && max_trap <= kWaveMultiIons)
+        return wave_launch_multi<PREC, X>(s, n_traps, block, nsteps, accel_only, st);
     switch (block) {
         case 64: return wave_launch<PREC, X>(s, n_traps, max_trap, nsteps, accel_only, st);
         case 512: return batch_launch<PREC, 512, X>(s, n_traps, max_trap, nsteps, accel_only, uq, tpt, st);

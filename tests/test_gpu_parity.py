@@ -738,13 +738,15 @@ def test_one_wave_shape_up_to_64_ions(torch_gpu, oracle_mod, n):
     sim.close()
 
 
-@pytest.mark.parametrize("n,block", [(17, 256), (33, 512), (48, 512), (56, 1024), (64, 1024)])
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,block", [(17, 256), (24, 256), (33, 512), (48, 512), (40, 1024),
+                                     (56, 1024), (64, 1024)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_owner_parts_split_up_to_64_ions(torch_gpu, oracle_mod, n, block, prec):
-    """Traps of <= 64 ions on 256 to 1024 threads: m owners followed by at
-    most 8 source parts (48 ions on 512 threads would take 10 without the
-    cap). Forces against the oracle, then forces after 60 steps; in FP64 the
-    run itself against the oracle's steps."""
+    """Traps of <= 64 ions on 256 to 1024 threads: up to 48 ions (and block / 8)
+    the wave kernel on block / 64 waves with 8 parts per target, above that the
+    batched kernel's m owners followed by at most 8 source parts (48 ions on 512
+    threads would take 10 without the cap). Forces against the oracle, then
+    forces after 60 steps; in FP64 the run itself against the oracle's steps."""
     w = li.random_cloud(n, seed=500 + n, sigma=20e-6, light_fraction=0.2)
     spec = w.traps[0]
     tr = _oracle_trap(oracle_mod, spec)
