@@ -342,8 +342,10 @@ typedef struct {
                              batched, 64 when the largest trap holds at most 16 ions, 1024
                              when it holds 256 or more, else 256; a lone trap on the
                              one-workgroup path, 64 up to 16 ions, 256 up to 32, 512 up to
-                             64, 1024 above.  64 runs the one-wave kernel (target state in
-                             registers, source parts in consecutive lanes)                  */
+                             64, 1024 above.  64 runs the wave kernel on one wave (target
+                             state in registers, source parts in consecutive lanes); 256,
+                             512 or 1024 run it on that many threads for traps of at most
+                             48 ions and threads / 8, the batched kernel otherwise          */
     int32_t use_graph;    /* 1: replay captured graphs, 2: plain stream launches           */
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
