@@ -29,6 +29,7 @@
 //         relative error even for close pairs of far-off-centre ions; r^-3 from
 //         v_rsq_f32; sums in FP32 over short runs flushed to FP64, or Kahan.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <math.h>
 
 #include "lion_internal.h"
@@ -803,19 +804,20 @@ __device__ __forceinline__ bool sym_unit_excluded(const int32_t* __restrict__ ti
     return tile_body && tile_body[a] >= 0 && tile_body[a] == tile_body[b];
 }
 
-__device__ __forceinline__ void sym_unit_zero(double* __restrict__ part, int64_t n,
-                                              int64_t n_pad, int a, int b) {
+template <typename PT>
+__device__ __forceinline__ void sym_unit_zero(PT* __restrict__ part, int64_t n, int64_t n_pad,
+                                              int a, int b) {
     const int64_t i = (int64_t)a * kSymTile + threadIdx.x;  // target side, slot b
     if (i < n) {
-        part[((int64_t)b * 3 + 0) * n_pad + i] = 0.0;
-        part[((int64_t)b * 3 + 1) * n_pad + i] = 0.0;
-        part[((int64_t)b * 3 + 2) * n_pad + i] = 0.0;
+        part[((int64_t)b * 3 + 0) * n_pad + i] = PT(0);
+        part[((int64_t)b * 3 + 1) * n_pad + i] = PT(0);
+        part[((int64_t)b * 3 + 2) * n_pad + i] = PT(0);
     }
     if (a != b) {  // reaction side, slot a
         const int64_t j = (int64_t)b * kSymTile + threadIdx.x;
-        part[((int64_t)a * 3 + 0) * n_pad + j] = 0.0;
-        part[((int64_t)a * 3 + 1) * n_pad + j] = 0.0;
-        part[((int64_t)a * 3 + 2) * n_pad + j] = 0.0;
+        part[((int64_t)a * 3 + 0) * n_pad + j] = PT(0);
+        part[((int64_t)a * 3 + 1) * n_pad + j] = PT(0);
+        part[((int64_t)a * 3 + 2) * n_pad + j] = PT(0);
     }
 }
 
@@ -888,12 +890,13 @@ __device__ __forceinline__ double column_sum64(const T* __restrict__ buf, int la
 // Target-side sums of the 4 targets per lane, added over the 4 waves in wave
 // order through LDS in two halves (targets 0-1, then 2-3) and stored to the
 // partial slot s.  red holds at least (kWaves - 1) * 3 * 64 * 2 doubles.
+template <typename PT>
 __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy)[4],
-                                                    double (&sz)[4], double* __restrict__ part,
+                                                    double (&sz)[4], PT* __restrict__ part,
                                                     int s, int64_t n, int64_t n_pad,
                                                     int64_t base, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double* px = part + (int64_t)(3 * s) * n_pad;
+    PT* px = part + (int64_t)(3 * s) * n_pad;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         if (wave > 0) {
@@ -917,9 +920,9 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
                 }
                 const int64_t i = base + 64 * (2 * h + k);
                 if (i < n) {
-                    px[i] = x;
-                    px[n_pad + i] = y;
-                    px[2 * n_pad + i] = z;
+                    px[i] = (PT)x;
+                    px[n_pad + i] = (PT)y;
+                    px[2 * n_pad + i] = (PT)z;
                 }
             }
         }
@@ -937,9 +940,10 @@ __device__ __forceinline__ void reduce_store_halves(double (&sx)[4], double (&sy
 // body id (or a number unique to a free ion) and a pair of equal codes adds 0.
 // KH: the compensated mode, in which the FP32 runs are added in compensated
 // FP32 (Kahan) instead of FP64 within the tile pair.
-template <int L, int CH, int UNR, bool PF, bool FQ, bool MK = false, bool KH = false>
+template <int L, int CH, int UNR, bool PF, bool FQ, bool MK = false, bool KH = false,
+          typename PT = double>
 __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm, int64_t n,
-                                               int nb, int64_t n_pad, double* __restrict__ part,
+                                               int nb, int64_t n_pad, PT* __restrict__ part,
                                                int a, int b, float uq, float4* tile,
                                                double* smem,
                                                const int32_t* __restrict__ code = nullptr,
@@ -1055,7 +1059,7 @@ __device__ __forceinline__ void mixed_sym_body(const MixedSrc* __restrict__ srcm
             if ((lane % P) == 0 && col < CH * 3) {
                 const int uu = col / 3, c = col - 3 * uu;
                 const int64_t j = (int64_t)b * kSymTile + wave * 64 + s0 + uu;
-                part[((int64_t)a * 3 + c) * n_pad + j] = FQ ? tot * (double)uq : tot;
+                part[((int64_t)a * 3 + c) * n_pad + j] = (PT)(FQ ? tot * (double)uq : tot);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -1097,18 +1101,23 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
     constexpr int kRed = (kWaves - 1) * 3 * 64 * 2;
     constexpr int kBuf = (kWaves * 64 * S + 1) / 2;
     __shared__ __align__(16) double smem[kBuf > kRed ? kBuf : kRed];
+    // tile partials: FP32 in the FP32 + FP64-run mode (each tile's FP64 sum
+    // rounded once; the tiles are added in FP64 by the epilogue), FP64 in the
+    // compensated mode
+    using PT = typename std::conditional<KH, double, float>::type;
+    PT* pt = reinterpret_cast<PT*>(part);
     int a, b;
     sym_unit(nb, a, b);
     if (sym_unit_excluded(tile_body, a, b))
-        sym_unit_zero(part, n, n_pad, a, b);
+        sym_unit_zero(pt, n, n_pad, a, b);
     else if (MK && bt.may_share(a, b))
-        mixed_sym_body<L, CH, UNR, PF, false, true, KH>(srcm, n, nb, n_pad, part, a, b, uq, tile,
+        mixed_sym_body<L, CH, UNR, PF, false, true, KH>(srcm, n, nb, n_pad, pt, a, b, uq, tile,
                                                         smem, bt.code, tcode);
     else if (uq != 0.0f && b < full_tiles)
-        mixed_sym_body<L, CH, UNR, PF, true, false, KH>(srcm, n, nb, n_pad, part, a, b, uq, tile,
+        mixed_sym_body<L, CH, UNR, PF, true, false, KH>(srcm, n, nb, n_pad, pt, a, b, uq, tile,
                                                         smem);
     else
-        mixed_sym_body<L, CH, UNR, PF, false, false, KH>(srcm, n, nb, n_pad, part, a, b, uq, tile,
+        mixed_sym_body<L, CH, UNR, PF, false, false, KH>(srcm, n, nb, n_pad, pt, a, b, uq, tile,
                                                          smem);
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter += 1;
 }
@@ -1336,7 +1345,7 @@ __device__ __forceinline__ void end_step_ion(
 // ions with 4 waves: wave g adds the partial slots [g*per, (g+1)*per) in slot
 // order, wave 0 adds the four group sums in group order (deterministic for a
 // given number of slots), then applies the trap field and kick / damp / drift.
-template <int MODE, int UW, bool X>
+template <int MODE, int UW, bool X, typename PT = double>
 __global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
                                                 MixedSrc* __restrict__ srcm,
                                                 double* __restrict__ vx, double* __restrict__ vy,
@@ -1346,7 +1355,7 @@ __global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
                                                 const double* __restrict__ qe,
                                                 const double* __restrict__ mass,
                                                 const int32_t* __restrict__ species,
-                                                const double* __restrict__ part, int j_split,
+                                                const PT* __restrict__ part, int j_split,
                                                 int64_t n, int64_t n_pad, double field_scale,
                                                 const TrapDev* __restrict__ traps,
                                                 const CoolDev* __restrict__ cool,
@@ -1365,10 +1374,10 @@ __global__ __launch_bounds__(64 * UW) void k_update(double4* __restrict__ src,
     if (i < n) {
 #pragma unroll 4
         for (int s = s0; s < s1; ++s) {
-            const double* px = part + (int64_t)(3 * s) * n_pad;
-            Sx += px[i];
-            Sy += px[n_pad + i];
-            Sz += px[2 * n_pad + i];
+            const PT* px = part + (int64_t)(3 * s) * n_pad;
+            Sx += (double)px[i];
+            Sy += (double)px[n_pad + i];
+            Sz += (double)px[2 * n_pad + i];
         }
     }
     if (g > 0) {
@@ -2937,29 +2946,41 @@ hipError_t launch_pair(const DevState& s, int precision, const LaunchShape& ls, 
     }
 }
 
-template <int MODE, int UW>
+template <int MODE, int UW, typename PT>
 void update_launch(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
                    const int64_t* ctr, hipStream_t st) {
     const unsigned g = blocks_for(s.n, 64);  // 64 ions per block of UW waves
+    const PT* part = reinterpret_cast<const PT*>(s.part);
     if (ls.cool_on && MODE != kModeAccel)
-        k_update<MODE, UW, true><<<g, 64 * UW, 0, st>>>(
+        k_update<MODE, UW, true, PT><<<g, 64 * UW, 0, st>>>(
             s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm, s.qe, s.mass, s.species,
-            s.part, ls.j_split, s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
+            part, ls.j_split, s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
     else
-        k_update<MODE, UW, false><<<g, 64 * UW, 0, st>>>(
+        k_update<MODE, UW, false, PT><<<g, 64 * UW, 0, st>>>(
             s.src, srcm, s.vx, s.vy, s.vz, s.ax, s.ay, s.az, s.qm, s.qe, s.mass, s.species,
-            s.part, ls.j_split, s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
+            part, ls.j_split, s.n, s.n_pad, scale, s.traps, s.cool, ctr, s.vacc, s.vavg, s.rb);
 }
 
+template <int MODE, typename PT>
+void update_dispatch_t(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
+                       const int64_t* ctr, hipStream_t st) {
+    if (ls.update_waves == 16)
+        update_launch<MODE, 16, PT>(s, ls, scale, srcm, ctr, st);
+    else if (ls.update_waves == 8)
+        update_launch<MODE, 8, PT>(s, ls, scale, srcm, ctr, st);
+    else
+        update_launch<MODE, 4, PT>(s, ls, scale, srcm, ctr, st);
+}
+
+// The pair-once kernels of the FP32 + FP64-run mode leave FP32 tile partials,
+// every other pair kernel FP64 ones.
 template <int MODE>
 void update_dispatch(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
-                     const int64_t* ctr, hipStream_t st) {
-    if (ls.update_waves == 16)
-        update_launch<MODE, 16>(s, ls, scale, srcm, ctr, st);
-    else if (ls.update_waves == 8)
-        update_launch<MODE, 8>(s, ls, scale, srcm, ctr, st);
+                     const int64_t* ctr, hipStream_t st, bool f32_partials) {
+    if (f32_partials)
+        update_dispatch_t<MODE, float>(s, ls, scale, srcm, ctr, st);
     else
-        update_launch<MODE, 4>(s, ls, scale, srcm, ctr, st);
+        update_dispatch_t<MODE, double>(s, ls, scale, srcm, ctr, st);
 }
 
 hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls, int mode,
@@ -2967,10 +2988,11 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
     const double scale = precision == 0 ? 1.0 : kMixedFieldScale;
     const int64_t* ctr = use_counter ? s.counter : nullptr;
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
+    const bool f32 = precision == 1 && ls.symmetric;
     switch (mode) {
-        case kModeAccel: update_dispatch<kModeAccel>(s, ls, scale, srcm, ctr, st); break;
-        case kModeEnd: update_dispatch<kModeEnd>(s, ls, scale, srcm, ctr, st); break;
-        default: update_dispatch<kModeEndDrift>(s, ls, scale, srcm, ctr, st); break;
+        case kModeAccel: update_dispatch<kModeAccel>(s, ls, scale, srcm, ctr, st, f32); break;
+        case kModeEnd: update_dispatch<kModeEnd>(s, ls, scale, srcm, ctr, st, f32); break;
+        default: update_dispatch<kModeEndDrift>(s, ls, scale, srcm, ctr, st, f32); break;
     }
     return hipGetLastError();
 }
