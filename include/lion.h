@@ -335,9 +335,8 @@ typedef struct {
     int32_t j_split;      /* source slices per step (1..64; clipped to one per 64 sources),
                              partial sums reduced in slice order                           */
     int32_t chunk_steps;  /* steps per captured launch graph (1..1000).  Built-in: 1000
-                             when one workgroup steps the trap (a single trap on the
-                             one-workgroup path, or batches of traps of at most 16 ions),
-                             else 100                                                     */
+                             for a single trap on the one-workgroup path and for batches
+                             of traps of at most 64 ions, else 100                        */
     int32_t flush_len;    /* LION_MIXED_F64ACC: sources per FP32 run: 4, 8 or 16           */
     int32_t batch_block;  /* threads per trap in batched mode and on the one-workgroup path:
                              64 (traps of at most 64 ions only), 256, 512 or 1024.  Built-in:

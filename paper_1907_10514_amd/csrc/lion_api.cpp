@@ -67,10 +67,10 @@ constexpr int kMaxTrap = 1024;
 // / 1.16)
 constexpr int64_t kOneWaveIons = 16;
 // steps per captured launch when not set: 1000 where one workgroup steps a trap
-// for the whole launch (a single trap of <= LION_SMALL_TRAP_IONS, or batches of
-// traps on one wave), whose steps take about a microsecond (8 ions: 0.60 against
-// 0.67 us per step with 100, before the one-wave kernel's unrolled butterfly),
-// else 100
+// for the whole launch and a step takes a microsecond or two (a single trap of
+// <= LION_SMALL_TRAP_IONS, or batches of traps of <= 64 ions; 8 ions: 0.60
+// against 0.67 us per step with 100, before the one-wave kernel's unrolled
+// butterfly), else 100
 constexpr int kChunkLong = 1000;
 constexpr int kChunkDefault = 100;
 
@@ -304,7 +304,7 @@ bool rows_active(const lion_sim* s) {
 // Steps per captured launch: the configured count, else the built-in one.
 int64_t chunk_len(const lion_sim* s) {
     if (s->cfg.chunk_steps > 0) return s->cfg.chunk_steps;
-    const bool one_wg = small_path_active(s) || (s->batched && s->ls.batch_block == 64);
+    const bool one_wg = small_path_active(s) || (s->batched && s->max_trap <= 64);
     return one_wg ? kChunkLong : kChunkDefault;
 }
 
