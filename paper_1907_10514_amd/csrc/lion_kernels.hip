@@ -472,9 +472,9 @@ constexpr int kWaves = 4;
 
 // Sum the per-wave partials of 64*I targets in wave order; wave 0 stores.
 // red must hold 3 * 3 * 64 * I doubles of LDS.
-template <int I>
+template <int I, typename PT = double>
 __device__ __forceinline__ void reduce_store_in(double (&sx)[I], double (&sy)[I],
-                                                double (&sz)[I], double* __restrict__ part,
+                                                double (&sz)[I], PT* __restrict__ part,
                                                 int s, int64_t n, int64_t n_pad, int64_t base,
                                                 double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -488,7 +488,7 @@ __device__ __forceinline__ void reduce_store_in(double (&sx)[I], double (&sy)[I]
     }
     __syncthreads();
     if (wave == 0) {
-        double* px = part + (int64_t)(3 * s) * n_pad;
+        PT* px = part + (int64_t)(3 * s) * n_pad;
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             double x = sx[k], y = sy[k], z = sz[k];
@@ -500,20 +500,29 @@ __device__ __forceinline__ void reduce_store_in(double (&sx)[I], double (&sy)[I]
             }
             const int64_t i = base + 64 * k;
             if (i < n) {
-                px[i] = x;
-                px[n_pad + i] = y;
-                px[2 * n_pad + i] = z;
+                px[i] = (PT)x;
+                px[n_pad + i] = (PT)y;
+                px[2 * n_pad + i] = (PT)z;
             }
         }
     }
 }
 
-template <int I>
+template <int I, typename PT = double>
 __device__ __forceinline__ void reduce_store(double (&sx)[I], double (&sy)[I], double (&sz)[I],
-                                             double* __restrict__ part, int s, int64_t n,
+                                             PT* __restrict__ part, int s, int64_t n,
                                              int64_t n_pad, int64_t base) {
     __shared__ double red[(kWaves - 1) * 3 * 64 * I];
-    reduce_store_in<I>(sx, sy, sz, part, s, n, n_pad, base, red);
+    reduce_store_in<I, PT>(sx, sy, sz, part, s, n, n_pad, base, red);
+}
+
+// Partials of the FP32 pair kernels: FP32 in the FP32 + FP64-run mode (each
+// slice's or tile pair's FP64 sum rounded once when stored, the slices added in
+// FP64 by the epilogue), FP64 in the compensated mode.
+template <bool KAHAN>
+__device__ __forceinline__ typename std::conditional<KAHAN, double, float>::type* mixed_partials(
+    double* part) {
+    return reinterpret_cast<typename std::conditional<KAHAN, double, float>::type*>(part);
 }
 
 // FP64: sources through scalar loads (wave-uniform addresses) into SGPRs; FP64
@@ -701,7 +710,7 @@ __global__ __launch_bounds__(256) void k_pair_mixed_s(const MixedSrc* __restrict
         }
     }
     A.finish();
-    reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
+    reduce_store<I>(A.sx, A.sy, A.sz, mixed_partials<KAHAN>(part), s, n, n_pad, base);
     if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
 }
 
@@ -752,7 +761,7 @@ __global__ __launch_bounds__(256) void k_pair_mixed_l(const MixedSrc* __restrict
         }
     }
     A.finish();
-    reduce_store<I>(A.sx, A.sy, A.sz, part, s, n, n_pad, base);
+    reduce_store<I>(A.sx, A.sy, A.sz, mixed_partials<KAHAN>(part), s, n, n_pad, base);
     if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter += 1;
 }
 
@@ -1101,11 +1110,7 @@ void k_pair_mixed_sym(const MixedSrc* __restrict__ srcm, int64_t n, int nb, int6
     constexpr int kRed = (kWaves - 1) * 3 * 64 * 2;
     constexpr int kBuf = (kWaves * 64 * S + 1) / 2;
     __shared__ __align__(16) double smem[kBuf > kRed ? kBuf : kRed];
-    // tile partials: FP32 in the FP32 + FP64-run mode (each tile's FP64 sum
-    // rounded once; the tiles are added in FP64 by the epilogue), FP64 in the
-    // compensated mode
-    using PT = typename std::conditional<KH, double, float>::type;
-    PT* pt = reinterpret_cast<PT*>(part);
+    auto* pt = mixed_partials<KH>(part);
     int a, b;
     sym_unit(nb, a, b);
     if (sym_unit_excluded(tile_body, a, b))
@@ -2972,8 +2977,8 @@ void update_dispatch_t(const DevState& s, const LaunchShape& ls, double scale, M
         update_launch<MODE, 4, PT>(s, ls, scale, srcm, ctr, st);
 }
 
-// The pair-once kernels of the FP32 + FP64-run mode leave FP32 tile partials,
-// every other pair kernel FP64 ones.
+// The pair kernels of the FP32 + FP64-run mode leave FP32 partials, those of
+// the FP64 and compensated modes FP64 ones.
 template <int MODE>
 void update_dispatch(const DevState& s, const LaunchShape& ls, double scale, MixedSrc* srcm,
                      const int64_t* ctr, hipStream_t st, bool f32_partials) {
@@ -2988,7 +2993,7 @@ hipError_t launch_update(const DevState& s, int precision, const LaunchShape& ls
     const double scale = precision == 0 ? 1.0 : kMixedFieldScale;
     const int64_t* ctr = use_counter ? s.counter : nullptr;
     MixedSrc* srcm = precision == 0 ? nullptr : s.srcm;
-    const bool f32 = precision == 1 && ls.symmetric;
+    const bool f32 = precision == 1;
     switch (mode) {
         case kModeAccel: update_dispatch<kModeAccel>(s, ls, scale, srcm, ctr, st, f32); break;
         case kModeEnd: update_dispatch<kModeEnd>(s, ls, scale, srcm, ctr, st, f32); break;
