@@ -53,9 +53,9 @@ typedef struct lion_sim lion_sim;
  *   LION_FP64          pair differences, r^-3 and accumulation in FP64
  *   LION_MIXED_F64ACC  pair arithmetic in FP32 on float-float positions,
  *                      accumulated in FP32 over short runs of sources and
- *                      flushed into FP64 sums (the pair-once kernels round
- *                      each tile pair's FP64 sum once to FP32 when storing it;
- *                      the tiles are added in FP64)
+ *                      flushed into FP64 sums (each workgroup's FP64 sum per
+ *                      source slice or tile pair is rounded once to FP32 when
+ *                      stored; the slices are added in FP64)
  *   LION_MIXED_KAHAN   pair arithmetic in FP32, compensated (Kahan) FP32 sums */
 enum lion_precision { LION_FP64 = 0, LION_MIXED_F64ACC = 1, LION_MIXED_KAHAN = 2 };
 
