@@ -71,8 +71,12 @@ def test_pseudo_accel_parity(torch_gpu, oracle_mod, n, prec, sym):
     sim.close()
 
 
-def test_pseudo_batch_accel_parity(torch_gpu, oracle_mod):
-    w = li.batch512(n_traps=10, n_min=2, n_max=300, seed=41, nsteps=0)
+@pytest.mark.parametrize("n_max", [300, 32, 16])
+def test_pseudo_batch_accel_parity(torch_gpu, oracle_mod, n_max):
+    """Batched pseudopotential traps: the batched kernel (traps of up to 300
+    ions) and the wave kernel (up to 32 ions on 256 threads, up to 16 on one
+    wave)."""
+    w = li.batch512(n_traps=10, n_min=2, n_max=n_max, seed=41, nsteps=0)
     trs = [_pseudo(oracle_mod, s.q_x, s.a_x) for s in w.traps]
     from paper_1907_10514_amd import Simulation
 
