@@ -188,7 +188,7 @@ def test_beam_cooling_of_free_ions_is_exact(torch_gpu, oracle_mod):
         sim.close()
 
 
-@pytest.mark.parametrize("n_max", [300, 16])
+@pytest.mark.parametrize("n_max", [300, 32, 16])
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec, n_max):
     """Batched traps draw bath kicks by run-wide ion index (trap k's first ion is
@@ -197,7 +197,7 @@ def test_cooled_batch_matches_oracle(torch_gpu, oracle_mod, prec, n_max):
     per-ion segment bars at the measured M1 of that trap; in FP64 every trap's
     whole 100-step run also matches within max(1e-10 x displacement, 10x the
     one-ulp envelope).  Traps of up to 300 ions run in the batched kernel, traps
-    of up to 16 in the one-wave kernel."""
+    of up to 32 in the wave kernel (on 256 threads, or one wave up to 16)."""
     w = li.batch512(n_traps=12, n_min=2, n_max=n_max, seed=23, nsteps=0)
     rng = np.random.default_rng(4)
     sp = rng.integers(0, 2, w.n).astype(np.int32)

@@ -94,11 +94,11 @@ def test_time_average_single_trap(torch_gpu, oracle_mod, prec):
     sim.close()
 
 
-@pytest.mark.parametrize("n_max", [200, 16])
+@pytest.mark.parametrize("n_max", [200, 32, 16])
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_kahan"])
 def test_time_average_batch(torch_gpu, oracle_mod, prec, n_max):
     """Window means of batched traps against the oracle: traps of up to 200
-    ions (the batched kernel) and of up to 16 (the one-wave kernel)."""
+    ions (the batched kernel) and of up to 32 and 16 (the wave kernel)."""
     w = li.batch512(n_traps=10, n_min=2, n_max=n_max, seed=29, nsteps=0)
     sim = _sim(w, prec, oracle_mod)
     sim.set_time_average(10)
