@@ -351,8 +351,8 @@ typedef struct {
     int32_t lds_sources;  /* FP32 pair modes: 1: sources by scalar loads, 2: LDS tiles        */
     int32_t symmetric;    /* 1: all ordered pairs; 2: each pair once (Newton's third law);
                              one trap of N <= 131072 (else LION_ERR_UNSUPPORTED).  Built-in
-                             (0): each pair once where that is allowed and N >= 8192
-                             (N >= 10240 for LION_MIXED_F64ACC).  With
+                             (0): each pair once where that is allowed and N >= 8192.
+                             With
                              LION_MIXED_KAHAN the FP32 runs of each 256 x 256 tile pair are
                              added in compensated FP32 and the tile-pair totals in FP64       */
     int32_t sym_variant;  /* pair-once kernel variant, 1..9 (built-in: 9 for

@@ -181,8 +181,8 @@ void default_shape(lion_sim* s) {
     ls.lds_sources = s->cfg.lds_sources > 0 ? (s->cfg.lds_sources == 2 ? 1 : 0) : 1;
     const int nb = lion::sym_tiles(n);
     // pair-once kernels: when asked for, and by default for one trap from the
-    // size where they measured faster (8192 ions, 10240 for FP32 pairs with FP64
-    // run sums; from 12288 on by a wide margin in every precision)
+    // size where they measured faster (8192 ions; from 12288 on by a wide margin
+    // in every precision)
     const bool sym_ok = nb <= lion::kMaxSymTiles && !s->batched;
     const int64_t sym_from = s->precision == LION_MIXED_F64ACC ? lion::kSymDefaultIonsMixed
                                                                 : lion::kSymDefaultIons;

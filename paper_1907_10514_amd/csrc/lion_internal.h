@@ -207,10 +207,11 @@ struct LaunchShape {
 // epilogue then adds one partial per tile.
 inline int sym_tiles(int64_t n) { return (int)((n + 255) / 256); }
 constexpr int kMaxSymTiles = 512;
-// Pair-once kernels by default from here: 32 tiles for FP64 and the
-// compensated mode, 40 for FP32 pairs with FP64 run sums (measured crossovers).
+// Pair-once kernels by default from here: 32 tiles in every precision (measured
+// crossovers; FP32 pairs with FP64 run sums moved from 40 tiles to 32 once both
+// kernel families stored FP32 partials: 8192 ions 31.5 against 32.9 us per step).
 constexpr int64_t kSymDefaultIons = 8192;
-constexpr int64_t kSymDefaultIonsMixed = 10240;
+constexpr int64_t kSymDefaultIonsMixed = 8192;
 
 // Kernel launchers (lion_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_drift(const DevState& s, bool cool_on, hipStream_t st);
